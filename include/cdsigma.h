@@ -1,0 +1,234 @@
+/*
+ * cdsigma — C ABI of the MI355X (gfx950) Cholesky-decomposition Sigma(2)
+ * quasi-particle path.
+ *
+ * Method: Vysotskiy & Cederbaum, "On the Cholesky Decomposition for electron
+ * propagator methods: General aspects and application on C60"
+ * (arXiv:0912.1459).  The calls follow the paper's problem statement:
+ *   ERI supermatrix + threshold delta  ->  Cholesky vectors L^K  (Sec. II.A)
+ *   vectors + MO coefficients + orbital energies
+ *        ->  quasi-particle energies and pole strengths          (Sec. II.B)
+ *
+ * Conventions shared by every call
+ *   - Every function returns an int status: CDS_OK (0) or a negative CDS_E*
+ *     code.  No function throws, aborts or exits.  On CDS_EINVAL nothing has
+ *     been written or enqueued.  cds_last_error() returns a text for the last
+ *     failure on that context.
+ *   - Array arguments are DEVICE pointers to caller-owned memory unless their
+ *     name starts with h_ (HOST memory).  The library never frees or keeps
+ *     caller memory beyond the call.  It owns internal device workspace,
+ *     allocated on first need and grown on demand, released by cds_destroy().
+ *   - All device work is enqueued on the stream given to cds_create().  Calls
+ *     that return host results (h_* outputs) synchronize that stream before
+ *     returning; others return once the work is enqueued.
+ *   - Indices are 0-based.  Basis functions are normalized primitive
+ *     s-Gaussians chi_mu(r) = (2a/pi)^(3/4) exp(-a |r - A_mu|^2).  The pair
+ *     (product density) index is I(mu,nu) = nu(nu+1)/2 + mu for mu <= nu, so
+ *     npairs = nbf(nbf+1)/2 (Sec. II.A, product-density set).
+ *   - Floating point is IEEE FP64 unless a `prec` argument says otherwise.
+ *   - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef CDSIGMA_H
+#define CDSIGMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define CDS_OK        0
+#define CDS_EINVAL   -1   /* invalid argument (nothing written)                */
+#define CDS_ENOMEM   -2   /* device workspace allocation failed               */
+#define CDS_EDEVICE  -3   /* a HIP runtime call failed                        */
+#define CDS_ENOTPSD  -4   /* a residual diagonal fell below -psd_tol          */
+#define CDS_ECAP     -5   /* max_vec vectors made before D_max <= delta;
+                             outputs are a valid, resumable state             */
+#define CDS_ESTATE   -6   /* call out of order (e.g. context already broken)  */
+
+/* ---- precision of the transform / contraction --------------------------- */
+#define CDS_PREC_FP64   0 /* FP64 operands, FP64 MFMA                         */
+#define CDS_PREC_FP32   1 /* FP32 operands, FP32 MFMA, FP32 accumulation      */
+#define CDS_PREC_BF16X3 2 /* FP32 operands split x = hi + lo (bf16 each);
+                             a*b ~ hi*hi + hi*lo + lo*hi on bf16 MFMA with
+                             FP32 accumulation                                */
+
+/* ---- Cholesky termination detail (h_status of the CD calls) ------------- */
+#define CDS_CD_CONVERGED 0 /* largest residual diagonal <= delta              */
+#define CDS_CD_CAP       1 /* max_vec reached first (return code CDS_ECAP)    */
+#define CDS_CD_FULLRANK  2 /* every pair became a pivot                       */
+#define CDS_CD_NOTPSD   -4 /* return code CDS_ENOTPSD                         */
+
+/* ---- quasi-particle solve status per target ----------------------------- */
+#define CDS_QP_CONVERGED 0 /* |w_{n+1} - w_n| <= conv                         */
+#define CDS_QP_MAX_ITER  1 /* max_iter Newton steps without convergence       */
+#define CDS_QP_NONFINITE 2 /* a pole was hit or a value became non-finite     */
+
+/* ---- Newton evaluation mode --------------------------------------------- */
+#define CDS_QP_RECOMPUTE 0 /* every Newton step recomputes the MO integrals
+                              from B by the contraction GEMM (the paper's
+                              scheme, Sec. "Computational details")           */
+#define CDS_QP_RESIDUES  1 /* one contraction forms the pair-symmetrised pole
+                              residues; each Newton step then sums them over
+                              the energy denominators (same formula)          */
+
+typedef struct cds_ctx cds_ctx;
+
+/* Per-context accumulated device times (HIP events on the context stream),
+ * algorithmic bytes and flops.  Reset by cds_reset_stats(). */
+typedef struct cds_stats {
+    double t_cd_ms;          /* pivoted Cholesky: all step kernels            */
+    double t_cd_kernel_ms;   /* partial-GEMV kernel time only                 */
+    double t_transform_ms;   /* AO->MO transform                              */
+    double t_contract_ms;    /* contraction GEMM launches                     */
+    double t_epilogue_ms;    /* denominator sums / residue forming            */
+    double t_newton_ms;      /* whole quasi-particle solves                   */
+    double t_adjoint_ms;     /* adjoint calls                                 */
+    double bytes_cd;         /* algorithmic CD bytes: sum_k 8 npairs k + 64 npairs */
+    double flops_contract;   /* 2 M nsel nmo nocc nvirt per contraction       */
+    int64_t n_cd_steps;
+    int64_t n_contract;
+    int64_t n_newton_iter;
+} cds_stats;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context. */
+int cds_create(int device, void *hip_stream, cds_ctx **out);
+/* Release the context and all its workspace (synchronizes its stream). */
+void cds_destroy(cds_ctx *ctx);
+/* Text of the last error on ctx ("" if none).  Valid until the next call. */
+const char *cds_last_error(const cds_ctx *ctx);
+int cds_get_stats(const cds_ctx *ctx, cds_stats *out);
+int cds_reset_stats(cds_ctx *ctx);
+/* 1: time every partial-GEMV launch of the Cholesky step with HIP events
+ * (accumulated in cds_stats.t_cd_kernel_ms); 0 (default): off. */
+int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
+/* Library version string (static). */
+const char *cds_version(void);
+
+/*
+ * ERI columns, Eq. (integral) of Sec. II.A, closed form for s-Gaussians:
+ *   V_IJ = K_I K_J 2 pi^(5/2) / (p q sqrt(p+q)) F0(pq/(p+q) |P-Q|^2),
+ *   F0(T) = 1/2 sqrt(pi/T) erf(sqrt T)  (series 1 - T/3 + T^2/10 for T < 1e-12).
+ * centres: nbf x 3 (row mu = centre of chi_mu), alpha: nbf exponents.
+ * cols: ncol pair indices (device int64).  out: ncol x npairs, column c of V
+ * at out + c*npairs.  Errors: EINVAL for nbf < 1, ncol < 0, NULL pointers.
+ */
+int cds_eri_columns(cds_ctx *ctx, int32_t nbf, const double *centres, const double *alpha,
+                    int64_t ncol, const int64_t *cols, double *out);
+
+/*
+ * Diagonal-pivoted incomplete Cholesky decomposition of the ERI supermatrix
+ * to threshold delta (Sec. II.A: Eqs. (gs_coulomb), (CD), (stricterr)).
+ * Columns are evaluated on demand from the basis (no npairs^2 storage).
+ *
+ * Each step picks the pivot p = the lowest pair index I (not yet a pivot)
+ * with D_I >= D_max - tau, where D is the residual diagonal and D_max its
+ * largest non-pivot entry; forms c = V[:,p] - L[:, :k] L[p, :k]^T;
+ * L[:,k] = c / sqrt(D_p) with L[p,k] = sqrt(D_p) and exactly 0 on earlier
+ * pivots; D -= L[:,k]^2; D_p = 0.  It stops when D_max <= delta, after
+ * max_vec vectors, or when every pair is a pivot.
+ *
+ * L: vector-major, vector k at L + k*ldl, entries 0..npairs-1 (ldl >= npairs);
+ *    the library may read (never write) entries npairs..ldl-1 of each vector.
+ * piv: int64[max_vec] pivot pair of each vector.  D: double[npairs] residual
+ *    diagonal, 0 on pivots.
+ * tau < 0 selects the default 1e-10 * max_I V_II.  psd_tol < 0 selects
+ *    1e3 * 2^-52 * max_I V_II; a non-pivot D_I < -psd_tol stops with ENOTPSD.
+ * nvec_in: 0 starts afresh; > 0 resumes from vectors 0..nvec_in-1, their
+ *    pivots and D exactly as an earlier call left them (to a smaller delta or
+ *    larger max_vec).  Resumed and direct runs give identical results.
+ * h_nvec: vectors made in total; h_dmax: final D_max; h_status: CDS_CD_*.
+ * Returns CDS_OK (converged or full rank), CDS_ECAP, CDS_ENOTPSD, or an error.
+ */
+int cds_cholesky_sgauss(cds_ctx *ctx, int32_t nbf, const double *centres, const double *alpha,
+                        double delta, double tau, double psd_tol, int64_t max_vec,
+                        double *L, int64_t ldl, int64_t *piv, double *D, int64_t nvec_in,
+                        int64_t *h_nvec, double *h_dmax, int32_t *h_status);
+
+/* Same decomposition of a dense symmetric npairs x npairs matrix V (column I
+ * at V + I*ldv).  Used to separate ERI rounding from decomposition rounding. */
+int cds_cholesky_dense(cds_ctx *ctx, int64_t npairs, const double *V, int64_t ldv,
+                       double delta, double tau, double psd_tol, int64_t max_vec,
+                       double *L, int64_t ldl, int64_t *piv, double *D, int64_t nvec_in,
+                       int64_t *h_nvec, double *h_dmax, int32_t *h_status);
+
+/*
+ * AO->MO transform of the Cholesky vectors, Eq. (transformation):
+ *   B^K_pq = sum_{mu,nu} C_mu,p L^K_mu,nu C_nu,q   (all ordered AO pairs),
+ * for the two blocks the self-energy reads (Eq. (SE) via Eq. (aomo)):
+ *   Bsel[(s*nmo + r)*ldk + K] = B^K[h_sel[s], r]          s < nsel, r < nmo
+ *   Bvo [(a*nocc + i)*ldk + K] = B^K[nocc + a, i]          a < nmo-nocc, i < nocc
+ * Entries K in [nvec, ldk) are written as 0 (ldk >= nvec; ldk a multiple of 64
+ * is fastest).  C: nbf x nmo row-major (C[mu*nmo + p]), columns are MOs.
+ * prec: CDS_PREC_FP64 writes double; CDS_PREC_FP32 and CDS_PREC_BF16X3 write
+ * float (the bf16 split happens inside the contraction).  The transform
+ * itself runs in FP64 for FP64 output and in the requested precision
+ * otherwise.  h_sel: host int32[nsel], each in [0, nmo).
+ */
+int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const double *L,
+                  int64_t ldl, const double *C, int32_t nmo, int32_t nocc, int32_t nsel,
+                  const int32_t *h_sel, int64_t ldk, void *Bsel, void *Bvo);
+
+/*
+ * Second-order self-energy, Eq. (SE), and its energy derivative at T trial
+ * energies per target, with (qi|aj) and (qa|ib) formed from B by Eq. (aomo):
+ *   h_sigma[s*T + t]  = Sigma_qq(h_omega[s*T + t]),   q = h_sel[s]
+ *   h_dsigma[s*T + t] = dSigma_qq/domega at the same energy.
+ * Bsel, Bvo as written by cds_transform with the same prec, nvec, ldk, nmo,
+ * nocc, nsel.  eps: device double[nmo] orbital energies (occupied first).
+ * The contraction runs in `prec`; denominators and sums run in FP64.
+ */
+int cds_sigma2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo, int32_t nocc,
+               int32_t nsel, const int32_t *h_sel, const void *Bsel, const void *Bvo,
+               const double *eps, int32_t T, const double *h_omega, double *h_sigma,
+               double *h_dsigma);
+
+/*
+ * Quasi-particle equation w = e_q + Sigma_qq(w), Eq. (qpapp), solved per
+ * target by Newton-Raphson, Eq. (iter), with pole strength Eq. (ps):
+ *   P_n = 1/(1 - Sigma'(w_n)),  w_{n+1} = w_n + (e_q + Sigma(w_n) - w_n) P_n,
+ * starting at w_0 = e_q (h_omega0 == NULL) or h_omega0[s], stopping when
+ * |w_{n+1} - w_n| <= conv (Eq. (NR)).  Outputs per target: h_omega = w_{n+1},
+ * h_pole = P_n, h_iters = n+1, h_status = CDS_QP_*.  IP = -w for an occupied
+ * target, EA = -w for a virtual one.  mode: CDS_QP_RECOMPUTE or
+ * CDS_QP_RESIDUES.  max_iter >= 1.
+ */
+int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                 int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                 const void *Bvo, const double *eps, const double *h_omega0, double conv,
+                 int32_t max_iter, int32_t mode, double *h_omega, double *h_pole,
+                 int32_t *h_iters, int32_t *h_status);
+
+/*
+ * Adjoint of the converged quasi-particle solve by implicit differentiation
+ * of F(w, theta) = e_q + Sigma_qq(w; theta) - w = 0 (not in the paper):
+ *   d(w*)/d(theta) = P dF/dtheta,  P = 1/(1 - Sigma'(w*)).
+ * Given converged h_omega[s] and cotangents h_omega_bar[s], accumulates
+ * (overwrites) Bsel_bar, Bvo_bar (layouts and precision of Bsel, Bvo) and
+ * eps_bar (device double[nmo]) with sum_s omega_bar_s d(w*_s)/d(theta).  The
+ * gradient w.r.t. B is taken with Bsel and Bvo as independent inputs.
+ */
+int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                   int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                   const void *Bvo, const double *eps, const double *h_omega,
+                   const double *h_omega_bar, void *Bsel_bar, void *Bvo_bar, double *eps_bar);
+
+/*
+ * Adjoint of cds_transform with respect to C (FP64):
+ *   C_bar = sum_K L^K C (Bbar^K + Bbar^K^T),
+ * where Bbar^K (nmo x nmo) holds Bsel_bar[s, r, K] at row h_sel[s] and
+ * Bvo_bar[a, i, K] at (nocc + a, i), zero elsewhere (accumulated where they
+ * overlap).  Bsel_bar, Bvo_bar in the layout and precision `prec` of
+ * cds_transform.  C_bar: nbf x nmo row-major, overwritten.
+ */
+int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec,
+                          const double *L, int64_t ldl, const double *C, int32_t nmo,
+                          int32_t nocc, int32_t nsel, const int32_t *h_sel, int64_t ldk,
+                          const void *Bsel_bar, const void *Bvo_bar, double *C_bar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDSIGMA_H */

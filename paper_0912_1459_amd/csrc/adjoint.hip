@@ -1,0 +1,284 @@
+// Adjoints of the quasi-particle solve and of the AO->MO transform.
+//
+// The converged energy w* solves F(w, theta) = e_q + Sigma_qq(w; theta) - w = 0
+// (Eq. (qpapp) of the paper); implicit differentiation gives
+//   dw*/dtheta = P dF/dtheta,   P = 1 / (1 - Sigma'(w*))   (pole strength, Eq. (ps)).
+// With g = (q r|a j) = G[s][r][a*nocc+j] (Eq. (aomo)) the self-energy Eq. (SE)
+// depends on each integral through its own term and its exchange partner:
+//   dSigma/dx_{a;ij} = (4 x_{a;ij} - 2 x_{a;ji}) / d_{a;ij},  same for y.
+// Since G = Bsel Bvo^T:
+//   Bsel_bar[s] = W[s] Bvo            (W = omega_bar P dSigma/dG)
+//   Bvo_bar     = sum_s W[s]^T Bsel[s]
+// and the energies enter through the denominators and e_q itself.
+// Transform adjoint: B^K = C^T L^K C gives C_bar = sum_K L^K C (Bbar^K + Bbar^K^T).
+#include "cds_internal.h"
+
+#include <cmath>
+#include <vector>
+
+int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, const void *Blo);
+int cds_sigma_eval_internal(cds_ctx *ctx, int prec, int64_t nvec, int64_t ldk, int nmo, int nocc,
+                            int nsel, const void *Bsel, const void *Bvo, const double *eps,
+                            const double *h_omega, int T, double *h_out);
+int cds_contract_internal(cds_ctx *ctx, int prec, int64_t nvec, int64_t ldk, int nmo, int nocc,
+                          int nsel, const void *Bsel, const void *Bvo, int s0, int nsc, void *G);
+int cds_grad_epilogue_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int nsc, const void *G,
+                               const double *eps, const double *d_omega, const double *d_gscale,
+                               void *W, double *epsA, double *epsB);
+
+namespace {
+
+// bf16 hi/lo planes -> float
+__global__ void planes_to_float_kernel(const __bf16 *__restrict__ b, int64_t n, float *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (float)b[t] + (float)b[n + t];
+}
+
+template <typename T>
+__global__ void zero_cols_kernel(T *__restrict__ B, int64_t nrows, int64_t ldk, int64_t c0)
+{
+    int64_t npad = ldk - c0;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * npad) return;
+    int64_t r = t / npad;
+    B[r * ldk + c0 + (t - r * npad)] = (T)0;
+}
+
+// eps_bar[r] = sum over targets and blocks of the energy partials, + P*omega_bar on e_q
+__global__ void eps_bar_kernel(const double *__restrict__ epsA, const double *__restrict__ epsB, int nsel,
+                               int nocc, int nvirt, const int32_t *__restrict__ sel,
+                               const double *__restrict__ gscale, double *__restrict__ out)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int nmo = nocc + nvirt;
+    if (r >= nmo) return;
+    double acc = 0.0;
+    for (int s = 0; s < nsel; ++s) {
+        const double *A = epsA + (int64_t)s * nvirt * (nocc + 1);
+        const double *B = epsB + (int64_t)s * nvirt * (nocc + 1);
+        if (r < nocc) {
+            for (int a = 0; a < nvirt; ++a) acc += A[(int64_t)a * (nocc + 1) + r];
+            for (int a = 0; a < nvirt; ++a) acc += B[(int64_t)a * (nocc + 1) + r];
+        } else {
+            int a = r - nocc;
+            acc += A[(int64_t)a * (nocc + 1) + nocc];
+            acc += B[(int64_t)a * (nocc + 1) + nocc];
+        }
+        if (sel[s] == r) acc += gscale[s];
+    }
+    out[r] = acc;
+}
+
+// S[kb][p][q] = Bbar^K[p][q] + Bbar^K[q][p] (FP64), Bbar scattered from the sel and vo blocks
+template <typename BT>
+__global__ void sym_bar_kernel(const BT *__restrict__ bsel, const BT *__restrict__ bvo, int64_t ldk, int64_t k0,
+                               int nkb, int nmo, int nocc, int nsel, const int32_t *__restrict__ sel,
+                               double *__restrict__ S)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t per = (int64_t)nmo * nmo;
+    if (t >= per * nkb) return;
+    int kb = (int)(t / per);
+    int64_t rem = t - kb * per;
+    int p = (int)(rem / nmo), q = (int)(rem - (int64_t)p * nmo);
+    int64_t K = k0 + kb;
+    double v = 0.0;
+    for (int s = 0; s < nsel; ++s) {
+        if (sel[s] == p) v += (double)bsel[((int64_t)s * nmo + q) * ldk + K];
+        if (sel[s] == q) v += (double)bsel[((int64_t)s * nmo + p) * ldk + K];
+    }
+    if (p >= nocc && q < nocc) v += (double)bvo[((int64_t)(p - nocc) * nocc + q) * ldk + K];
+    if (q >= nocc && p < nocc) v += (double)bvo[((int64_t)(q - nocc) * nocc + p) * ldk + K];
+    S[t] = v;
+}
+
+// Lu[kb][mu][nu] (nu padded to np_) in FP64
+__global__ void unpack64_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, int nkb, int nbf,
+                                int np_, double *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t per = (int64_t)nbf * np_;
+    if (t >= per * nkb) return;
+    int kb = (int)(t / per);
+    int64_t rem = t - (int64_t)kb * per;
+    int mu = (int)(rem / np_), nu = (int)(rem - (int64_t)mu * np_);
+    double v = 0.0;
+    if (nu < nbf) {
+        int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
+        v = L[(k0 + kb) * ldl + (int64_t)b * (b + 1) / 2 + a];
+    }
+    out[t] = v;
+}
+
+}  // namespace
+
+extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                              int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                              const void *Bvo, const double *eps, const double *h_omega,
+                              const double *h_omega_bar, void *Bsel_bar, void *Bvo_bar, double *eps_bar)
+{
+    CDS_CALL(cds_enter(ctx));
+    CDS_REQUIRE(ctx, prec == CDS_PREC_FP64 || prec == CDS_PREC_FP32 || prec == CDS_PREC_BF16X3,
+                "unknown precision %d", prec);
+    CDS_REQUIRE(ctx, nmo >= 2 && nocc >= 1 && nocc < nmo && nocc <= 1024, "bad nocc/nmo");
+    CDS_REQUIRE(ctx, nsel >= 1 && h_sel && h_omega && h_omega_bar, "bad targets");
+    CDS_REQUIRE(ctx, nvec >= 1 && ldk >= nvec, "need nvec >= 1, ldk >= nvec");
+    CDS_REQUIRE(ctx, prec != CDS_PREC_BF16X3 || ldk % 64 == 0, "BF16X3 needs ldk % 64 == 0");
+    CDS_REQUIRE(ctx, Bsel && Bvo && eps && Bsel_bar && Bvo_bar && eps_bar, "NULL pointer");
+    for (int s = 0; s < nsel; ++s)
+        CDS_REQUIRE(ctx, h_sel[s] >= 0 && h_sel[s] < nmo, "h_sel[%d] out of range", s);
+    CdsTimer tall;
+    CDS_CALL(cds_timer_start(ctx, &tall));
+    const int nvirt = nmo - nocc;
+    const int64_t nvo = (int64_t)nvirt * nocc, nselr = (int64_t)nsel * nmo;
+
+    // pole strengths at the converged energies
+    std::vector<double> out((size_t)nsel * 2);
+    CDS_CALL(cds_sigma_eval_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, eps, h_omega, 1,
+                                     out.data()));
+    std::vector<double> hscale(nsel);
+    for (int s = 0; s < nsel; ++s) hscale[s] = h_omega_bar[s] / (1.0 - out[2 * s + 1]);
+
+    // working copies: float operands for BF16X3 (planes -> float)
+    const int gprec = prec == CDS_PREC_FP64 ? CDS_PREC_FP64 : CDS_PREC_FP32;
+    const size_t es = prec == CDS_PREC_FP64 ? 8 : 4;
+    const void *Bs = Bsel, *Bv = Bvo;
+    void *tmp;
+    size_t nB = (size_t)(nselr + nvo) * ldk;
+    size_t small = (size_t)nsel * 8 * 3 + (size_t)nsel * 4 + 256;
+    size_t epsbytes = (size_t)2 * nsel * nvirt * (nocc + 1) * 8;
+    CDS_CALL(cds_ws(ctx, WS_AD_TMP, (prec == CDS_PREC_BF16X3 ? nB * 4 : 0) + small + epsbytes, &tmp));
+    unsigned char *tp = (unsigned char *)tmp;
+    if (prec == CDS_PREC_BF16X3) {
+        float *fs = (float *)tp, *fv = fs + nselr * ldk;
+        hipLaunchKernelGGL(planes_to_float_kernel, dim3((unsigned)cds_ceil_div(nselr * ldk, 256)), dim3(256),
+                           0, ctx->stream, (const __bf16 *)Bsel, nselr * ldk, fs);
+        hipLaunchKernelGGL(planes_to_float_kernel, dim3((unsigned)cds_ceil_div(nvo * ldk, 256)), dim3(256), 0,
+                           ctx->stream, (const __bf16 *)Bvo, nvo * ldk, fv);
+        CDS_LAUNCHED(ctx);
+        Bs = fs;
+        Bv = fv;
+        tp += nB * 4;
+    }
+    double *d_omega = (double *)tp;
+    double *d_scale = d_omega + nsel;
+    int32_t *d_sel = (int32_t *)(d_scale + nsel);
+    double *epsA = (double *)(tp + small);
+    double *epsB = epsA + (size_t)nsel * nvirt * (nocc + 1);
+    CDS_HIP(ctx, hipMemcpyAsync(d_omega, h_omega, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
+    CDS_HIP(ctx, hipMemcpyAsync(d_scale, hscale.data(), (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
+    CDS_HIP(ctx, hipMemcpyAsync(d_sel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
+
+    // chunks of targets: G and W each nsc * nmo * nvo
+    size_t per = (size_t)nmo * nvo * es;
+    int csz = (int)std::max<size_t>(1, ((size_t)2 << 30) / std::max<size_t>(per, 1));
+    csz = std::min(csz, (int)nsel);
+    void *G, *W;
+    CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * per, &G));
+    CDS_CALL(cds_ws(ctx, WS_AD_G, (size_t)csz * per, &W));
+    for (int s0 = 0; s0 < nsel; s0 += csz) {
+        const int nsc = std::min(csz, nsel - s0);
+        CDS_CALL(cds_contract_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, s0, nsc, G));
+        CDS_CALL(cds_grad_epilogue_internal(ctx, prec, nmo, nocc, nsc, G, eps, d_omega + s0, d_scale + s0, W,
+                                            epsA + (size_t)s0 * nvirt * (nocc + 1),
+                                            epsB + (size_t)s0 * nvirt * (nocc + 1)));
+        // Bsel_bar[s0..] = W Bvo :  (nsc*nmo) x nvec, reduction over nvo
+        GemmDesc d1 = {};
+        d1.M = (int64_t)nsc * nmo; d1.N = nvec; d1.K = nvo; d1.batch = 1;
+        d1.A = W; d1.sAm = nvo; d1.sAk = 1;
+        d1.B = Bv; d1.sBk = ldk; d1.sBn = 1;
+        d1.C = (unsigned char *)Bsel_bar + (size_t)s0 * nmo * ldk * es; d1.sCm = ldk; d1.sCn = 1;
+        d1.alpha = 1.0; d1.beta = 0.0;
+        CDS_CALL(cds_gemm_ex(ctx, gprec, d1, nullptr, nullptr));
+        // Bvo_bar += W^T Bsel[s0..] : nvo x nvec, reduction over nsc*nmo
+        GemmDesc d2 = {};
+        d2.M = nvo; d2.N = nvec; d2.K = (int64_t)nsc * nmo; d2.batch = 1;
+        d2.A = W; d2.sAm = 1; d2.sAk = nvo;
+        d2.B = (const unsigned char *)Bs + (size_t)s0 * nmo * ldk * es; d2.sBk = ldk; d2.sBn = 1;
+        d2.C = Bvo_bar; d2.sCm = ldk; d2.sCn = 1;
+        d2.alpha = 1.0; d2.beta = s0 == 0 ? 0.0 : 1.0;
+        CDS_CALL(cds_gemm_ex(ctx, gprec, d2, nullptr, nullptr));
+    }
+    if (ldk > nvec) {
+        if (gprec == CDS_PREC_FP64) {
+            hipLaunchKernelGGL(zero_cols_kernel<double>, dim3((unsigned)cds_ceil_div(nselr * (ldk - nvec), 256)),
+                               dim3(256), 0, ctx->stream, (double *)Bsel_bar, nselr, ldk, nvec);
+            hipLaunchKernelGGL(zero_cols_kernel<double>, dim3((unsigned)cds_ceil_div(nvo * (ldk - nvec), 256)),
+                               dim3(256), 0, ctx->stream, (double *)Bvo_bar, nvo, ldk, nvec);
+        } else {
+            hipLaunchKernelGGL(zero_cols_kernel<float>, dim3((unsigned)cds_ceil_div(nselr * (ldk - nvec), 256)),
+                               dim3(256), 0, ctx->stream, (float *)Bsel_bar, nselr, ldk, nvec);
+            hipLaunchKernelGGL(zero_cols_kernel<float>, dim3((unsigned)cds_ceil_div(nvo * (ldk - nvec), 256)),
+                               dim3(256), 0, ctx->stream, (float *)Bvo_bar, nvo, ldk, nvec);
+        }
+        CDS_LAUNCHED(ctx);
+    }
+    hipLaunchKernelGGL(eps_bar_kernel, dim3((unsigned)cds_ceil_div(nmo, 64)), dim3(64), 0, ctx->stream,
+                       (const double *)epsA, (const double *)epsB, nsel, nocc, nvirt, (const int32_t *)d_sel,
+                       (const double *)d_scale, eps_bar);
+    CDS_LAUNCHED(ctx);
+    CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_adjoint_ms));
+    CDS_CALL(cds_timers_flush(ctx));
+    return CDS_OK;
+}
+
+extern "C" int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec,
+                                     const double *L, int64_t ldl, const double *C, int32_t nmo,
+                                     int32_t nocc, int32_t nsel, const int32_t *h_sel, int64_t ldk,
+                                     const void *Bsel_bar, const void *Bvo_bar, double *C_bar)
+{
+    CDS_CALL(cds_enter(ctx));
+    CDS_REQUIRE(ctx, prec == CDS_PREC_FP64 || prec == CDS_PREC_FP32 || prec == CDS_PREC_BF16X3,
+                "unknown precision %d", prec);
+    CDS_REQUIRE(ctx, nbf >= 1 && nmo >= 2 && nmo <= nbf && nocc >= 1 && nocc < nmo, "bad sizes");
+    CDS_REQUIRE(ctx, nsel >= 1 && h_sel, "bad targets");
+    CDS_REQUIRE(ctx, nvec >= 1 && ldk >= nvec && ldl >= cds_npairs(nbf), "bad nvec/ldk/ldl");
+    CDS_REQUIRE(ctx, L && C && Bsel_bar && Bvo_bar && C_bar, "NULL pointer");
+    for (int s = 0; s < nsel; ++s)
+        CDS_REQUIRE(ctx, h_sel[s] >= 0 && h_sel[s] < nmo, "h_sel[%d] out of range", s);
+    CdsTimer tall;
+    CDS_CALL(cds_timer_start(ctx, &tall));
+    const int np_ = (int)(cds_ceil_div(nbf, 64) * 64);
+    const int kb = (int)std::min<int64_t>(32, nvec);
+    void *wl, *ws, *wk, *wsel;
+    CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)kb * nbf * np_ * 8, &wl));
+    CDS_CALL(cds_ws(ctx, WS_AD_TMP2, (size_t)kb * nmo * nmo * 8, &ws));
+    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)kb * nbf * nmo * 8, &wk));
+    CDS_CALL(cds_ws(ctx, WS_TR_CX, (size_t)nsel * 4 + 64, &wsel));
+    CDS_HIP(ctx, hipMemcpyAsync(wsel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
+    for (int64_t k0 = 0; k0 < nvec; k0 += kb) {
+        const int nkb = (int)std::min<int64_t>(kb, nvec - k0);
+        int64_t n1 = (int64_t)nkb * nbf * np_;
+        hipLaunchKernelGGL(unpack64_kernel, dim3((unsigned)cds_ceil_div(n1, 256)), dim3(256), 0, ctx->stream, L,
+                           ldl, k0, nkb, nbf, np_, (double *)wl);
+        int64_t n2 = (int64_t)nkb * nmo * nmo;
+        if (prec == CDS_PREC_FP64)
+            hipLaunchKernelGGL(sym_bar_kernel<double>, dim3((unsigned)cds_ceil_div(n2, 256)), dim3(256), 0,
+                               ctx->stream, (const double *)Bsel_bar, (const double *)Bvo_bar, ldk, k0, nkb,
+                               nmo, nocc, nsel, (const int32_t *)wsel, (double *)ws);
+        else
+            hipLaunchKernelGGL(sym_bar_kernel<float>, dim3((unsigned)cds_ceil_div(n2, 256)), dim3(256), 0,
+                               ctx->stream, (const float *)Bsel_bar, (const float *)Bvo_bar, ldk, k0, nkb,
+                               nmo, nocc, nsel, (const int32_t *)wsel, (double *)ws);
+        CDS_LAUNCHED(ctx);
+        // Wk[kb][mu][p] = sum_r C[mu][r] S[kb][r][p]
+        GemmDesc g1 = {};
+        g1.M = nbf; g1.N = nmo; g1.K = nmo; g1.batch = nkb;
+        g1.A = C; g1.sAm = nmo; g1.sAk = 1; g1.sAb = 0;
+        g1.B = ws; g1.sBn = nmo; g1.sBk = 1; g1.sBb = (int64_t)nmo * nmo;
+        g1.C = wk; g1.sCm = nmo; g1.sCn = 1; g1.sCb = (int64_t)nbf * nmo;
+        g1.alpha = 1.0; g1.beta = 0.0;
+        CDS_CALL(cds_gemm_ex(ctx, CDS_PREC_FP64, g1, nullptr, nullptr));
+        // C_bar[mu][p] += sum_{kb, nu} Lu[kb][nu][mu] Wk[kb][nu][p]   (Lu symmetric in mu, nu)
+        GemmDesc g2 = {};
+        g2.M = nbf; g2.N = nmo; g2.K = (int64_t)nkb * nbf; g2.batch = 1;
+        g2.A = wl; g2.sAm = 1; g2.sAk = np_;
+        g2.B = wk; g2.sBk = nmo; g2.sBn = 1;
+        g2.C = C_bar; g2.sCm = nmo; g2.sCn = 1;
+        g2.alpha = 1.0; g2.beta = k0 == 0 ? 0.0 : 1.0;
+        CDS_CALL(cds_gemm_ex(ctx, CDS_PREC_FP64, g2, nullptr, nullptr));
+    }
+    CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_adjoint_ms));
+    return CDS_OK;
+}

@@ -1,0 +1,131 @@
+// Internal declarations of the cdsigma HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "cdsigma.h"
+
+// Workspace slots: each slot is an independent device buffer owned by the
+// context and grown on demand.  Calls use fixed slots so that one call never
+// clobbers memory another part of the same call still needs.
+enum CdsSlot {
+    WS_PAIRS = 0,   // pair table (SoA) of the basis
+    WS_CD_PART,     // partial GEMV sums of the CD step
+    WS_CD_TILE,     // per-tile max/min of the residual diagonal
+    WS_CD_MASK,     // pivot mask
+    WS_CD_STATE,    // device CD state
+    WS_TR_UNPACK,   // unpacked L^K batch for the transform
+    WS_TR_T,        // L^K C_X batch
+    WS_TR_B,        // K-major B blocks before the transpose
+    WS_TR_CX,       // gathered occupied + selected columns of C
+    WS_SG_G,        // contraction output G (integrals)
+    WS_SG_PART,     // per-block partial sums of the denominator reduction
+    WS_SG_RES,      // pole residues (residue mode)
+    WS_SG_OMEGA,    // trial energies on the device
+    WS_SG_OUT,      // reduced sigma / dsigma on the device
+    WS_AD_G,        // adjoint: dSigma/dG weights
+    WS_AD_TMP,      // adjoint scratch
+    WS_AD_TMP2,
+    WS_SLOTS
+};
+
+struct CdsTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    double *acc = nullptr;
+};
+
+struct cds_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void *ws[WS_SLOTS] = {};
+    size_t ws_bytes[WS_SLOTS] = {};
+    void *pinned = nullptr;          // small pinned host buffer (state readback)
+    size_t pinned_bytes = 0;
+    cds_stats stats = {};
+    std::vector<CdsTimer> pending;   // recorded event pairs not yet accumulated
+    std::vector<hipEvent_t> free_events;
+    bool broken = false;
+    bool kernel_timing = false;      // time every CD partial-GEMV launch with events
+};
+
+// error helpers -------------------------------------------------------------
+int cds_fail(cds_ctx *ctx, int code, const char *fmt, ...);
+
+#define CDS_HIP(ctx, expr)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return cds_fail((ctx), CDS_EDEVICE, "%s failed: %s (%s:%d)", #expr,      \
+                            hipGetErrorString(e_), __FILE__, __LINE__);             \
+    } while (0)
+
+#define CDS_REQUIRE(ctx, cond, ...)                                                 \
+    do {                                                                            \
+        if (!(cond)) return cds_fail((ctx), CDS_EINVAL, __VA_ARGS__);               \
+    } while (0)
+
+#define CDS_CALL(expr)                                                              \
+    do {                                                                            \
+        int r_ = (expr);                                                            \
+        if (r_ != CDS_OK) return r_;                                                \
+    } while (0)
+
+// launch check: reports launch-configuration errors immediately
+#define CDS_LAUNCHED(ctx) CDS_HIP(ctx, hipGetLastError())
+
+// device workspace of at least `bytes` in `slot` (contents not preserved on growth)
+int cds_ws(cds_ctx *ctx, int slot, size_t bytes, void **out);
+// pinned host scratch of at least `bytes`
+int cds_pinned(cds_ctx *ctx, size_t bytes, void **out);
+// begin context entry: checks ctx, sets device, clears the error text
+int cds_enter(cds_ctx *ctx);
+
+// event timing: start records an event now; stop records the closing event and
+// queues the pair, whose elapsed time is added to *acc at the next flush.
+int cds_timer_start(cds_ctx *ctx, CdsTimer *t);
+int cds_timer_stop(cds_ctx *ctx, CdsTimer *t, double *acc);
+int cds_timers_flush(cds_ctx *ctx);   // synchronizes the stream
+
+static inline int64_t cds_npairs(int64_t nbf) { return nbf * (nbf + 1) / 2; }
+__host__ __device__ static inline int64_t cds_ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline bool cds_aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ---- shared device helpers -------------------------------------------------
+// pair I -> (mu, nu), mu <= nu, I = nu(nu+1)/2 + mu
+__device__ __forceinline__ void cds_pair_decode(int64_t I, int64_t &mu, int64_t &nu)
+{
+    int64_t n = (int64_t)((sqrt(8.0 * (double)I + 1.0) - 1.0) * 0.5);
+    if (n * (n + 1) / 2 > I) --n;
+    if ((n + 1) * (n + 2) / 2 <= I) ++n;
+    nu = n;
+    mu = I - n * (n + 1) / 2;
+}
+
+// precision tags ---------------------------------------------------------------
+static inline size_t cds_prec_bytes(int prec) { return prec == CDS_PREC_FP64 ? 8 : 4; }
+
+// internal entry points shared between translation units ----------------------
+// GEMM engine (gemm.hip): C[b][m][n] = alpha * sum_k A(m,k) B(k,n) (+ beta C)
+struct GemmDesc {
+    int64_t M, N, K, batch;
+    const void *A;
+    int64_t sAm, sAk, sAb;   // element strides of A(m,k) and per batch
+    const void *B;
+    int64_t sBk, sBn, sBb;
+    void *C;
+    int64_t sCm, sCn, sCb;
+    double alpha, beta;      // beta: 0 overwrite, 1 accumulate
+};
+// prec of A/B/C: FP64 -> double, FP32/BF16X3 -> float storage
+int cds_gemm(cds_ctx *ctx, int prec, const GemmDesc &d);
+// Alo/Blo: lo planes of BF16X3 operands (hi planes at d.A / d.B); NULL otherwise
+int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, const void *Blo);

@@ -1,0 +1,657 @@
+// Second-order self-energy and quasi-particle solves (Sec. II.B of the paper):
+//   Eq. (SE)   Sigma_qq(w) = sum_{a,i,j} (2(qi|aj) - (qj|ai)) (qi|aj) / (w + e_a - e_i - e_j)
+//                          + sum_{i,a,b} (2(qa|ib) - (qb|ia)) (qa|ib) / (w + e_i - e_a - e_b)
+//   Eq. (aomo) (pq|rs) = sum_K B^K_pq B^K_rs
+//   Eqs. (qpapp), (iter), (ps), (NR): Newton solve of w = e_q + Sigma_qq(w).
+//
+// Contraction: one MFMA GEMM per chunk of targets,
+//   G[s][r][a*nocc + j] = sum_K Bsel[s][r][K] Bvo[a][j][K] = (q r | a j),
+// so (qi|aj) = G[s][i][a*nocc+j] and (qa|ib) = (qa|bi) = G[s][nocc+a][b*nocc+i].
+// Epilogue kernels then form the numerators, divide by the denominators and
+// reduce deterministically (per-block partials, fixed-order final sums):
+//   part A (2h1p): one block per (s, a), elements (i, j) of X^a
+//   part B (2p1h): one block per (s, a), elements (b, i) of row a of the Y^i
+// Residue mode stores the pair-symmetrised numerators
+//   R = U_uv + U_vu = 2 (g_uv^2 + g_vu^2 - g_uv g_vu)  (u < v),  R = g_uu^2
+// once; each later Newton step is one pass over R.
+#include "cds_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, const void *Blo);
+
+namespace {
+
+constexpr int EP_NT = 256;
+constexpr int TMAX = 16;
+
+enum EpMode { EP_SIGMA = 0, EP_RESIDUE = 1, EP_GRAD = 2 };
+
+struct EpArgs {
+    const void *G;          // integrals of this chunk: [sc][nmo][nvo] (double or float)
+    int nmo, nocc, nvirt, nsc;
+    int64_t nvo;
+    const double *eps;      // device orbital energies
+    const double *omega;    // [sc][T] trial energies (chunk-relative)
+    int T;
+    double *part;           // partial sums [sc][nblk][T][2]
+    int nblkA, nblkB;       // blocks per target in part A / part B
+    void *R;                // residues [sc][nres] (RESIDUE mode)
+    int64_t nres, offB;     // residues per target; start of part B within a target
+    // gradient mode
+    const double *gscale;   // [sc] omega_bar * P per target
+    void *W;                // weights dSigma/dG scaled, same layout as G
+    double *epsA;           // [sc][nvirt][nocc + 1] part A energy partials
+    double *epsB;           // [sc][nvirt][nocc + 1] part B energy partials
+};
+
+template <typename GT>
+__device__ __forceinline__ double ld(const void *p, int64_t i) { return (double)((const GT *)p)[i]; }
+
+template <int NTH>
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NTH / 64; ++k) s += sh[k];   // fixed order
+    __syncthreads();
+    if (threadIdx.x == 0) sh[0] = s;
+    __syncthreads();
+    return sh[0];
+}
+
+// reduce per-thread sums acc[t][0..1] over the block and store to part
+template <int NTH>
+__device__ __forceinline__ void flush_partials(double (*acc)[2], int T, double *dst, double *sh)
+{
+    for (int t = 0; t < T; ++t)
+        for (int c = 0; c < 2; ++c) {
+            double v = block_sum<NTH>(acc[t][c], sh);
+            if (threadIdx.x == 0) dst[t * 2 + c] = v;
+        }
+}
+
+// part A: block (a = blockIdx.x, s = blockIdx.y), elements (i, j), d = w + e_a - e_i - e_j
+template <typename GT, int MODE>
+__global__ __launch_bounds__(EP_NT) void part_a_kernel(EpArgs e)
+{
+    __shared__ double sh[EP_NT / 64];
+    __shared__ double eo[1024];
+    const int a = blockIdx.x, s = blockIdx.y, nocc = e.nocc;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
+    __syncthreads();
+    const double ea = e.eps[nocc + a];
+    const int64_t gbase = (int64_t)s * e.nmo * e.nvo + (int64_t)a * nocc;   // + i*nvo + j
+    double acc[TMAX][2];
+    double w[TMAX];
+    const int T = (MODE == EP_SIGMA || MODE == EP_GRAD) ? e.T : 0;
+    for (int t = 0; t < T; ++t) {
+        acc[t][0] = acc[t][1] = 0.0;
+        w[t] = e.omega[s * e.T + t];
+    }
+    if constexpr (MODE == EP_GRAD) {
+        // thread i owns e-bar_i (row sums); block sums e-bar_a
+        const double gs = e.gscale[s];
+        double sa = 0.0;
+        for (int i = threadIdx.x; i < nocc; i += EP_NT) {
+            double si = 0.0;
+            for (int j = 0; j < nocc; ++j) {
+                double x = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
+                double xt = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
+                double d = w[0] + ea - eo[i] - eo[j];
+                double u = (2.0 * x - xt) * x, ut = (2.0 * xt - x) * xt;
+                double id = 1.0 / d;
+                ((GT *)e.W)[gbase + (int64_t)i * e.nvo + j] = (GT)(gs * (4.0 * x - 2.0 * xt) * id);
+                si += (u + ut) * id * id;     // d symmetric in (i, j)
+                sa -= u * id * id;
+            }
+            e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + i] = gs * si;
+        }
+        sa = block_sum<EP_NT>(sa, sh);
+        if (threadIdx.x == 0) e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + nocc] = gs * sa;
+        return;
+    }
+    const int64_t nij = (int64_t)nocc * nocc;
+    for (int64_t q = threadIdx.x; q < nij; q += EP_NT) {
+        const int i = (int)(q / nocc), j = (int)(q - (int64_t)i * nocc);
+        if (MODE == EP_RESIDUE && i > j) continue;
+        double x = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
+        double xt = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
+        if constexpr (MODE == EP_SIGMA) {
+            double u = (2.0 * x - xt) * x;
+            double dd = ea - eo[i] - eo[j];
+            for (int t = 0; t < T; ++t) {
+                double id = 1.0 / (w[t] + dd);
+                double ui = u * id;
+                acc[t][0] += ui;
+                acc[t][1] -= ui * id;
+            }
+        } else {
+            double r = (i == j) ? x * x : 2.0 * (x * x + xt * xt - x * xt);
+            int64_t p = (int64_t)j * (j + 1) / 2 + i;     // packed (i <= j)
+            ((GT *)e.R)[(int64_t)s * e.nres + (int64_t)a * (nocc * (nocc + 1) / 2) + p] = (GT)r;
+        }
+    }
+    if constexpr (MODE == EP_SIGMA)
+        flush_partials<EP_NT>(acc, T, e.part + (((int64_t)s * (e.nblkA + e.nblkB) + a) * e.T) * 2, sh);
+}
+
+// part B: y_{i;ab} = G[s][nocc+a][b*nocc+i], partner y_{i;ba} = G[s][nocc+b][a*nocc+i],
+// d = w + e_i - e_a - e_b.  SIGMA / GRAD: block per (s, a) over all (b, i).
+// RESIDUE: block blk handles a = blk and a = nvirt-1-blk over b >= a (balanced).
+template <typename GT, int MODE>
+__global__ __launch_bounds__(EP_NT) void part_b_kernel(EpArgs e)
+{
+    __shared__ double sh[EP_NT / 64];
+    __shared__ double eo[1024];
+    __shared__ double acc_i[1024];
+    const int s = blockIdx.y, nocc = e.nocc, nvirt = e.nvirt;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
+    __syncthreads();
+    const double *ev = e.eps + nocc;
+    const int64_t gs0 = (int64_t)s * e.nmo * e.nvo;
+    double acc[TMAX][2];
+    double w[TMAX];
+    const int T = (MODE == EP_SIGMA || MODE == EP_GRAD) ? e.T : 0;
+    for (int t = 0; t < T; ++t) {
+        acc[t][0] = acc[t][1] = 0.0;
+        w[t] = e.omega[s * e.T + t];
+    }
+    if constexpr (MODE == EP_RESIDUE) {
+        const int blk = blockIdx.x;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int a = pass == 0 ? blk : nvirt - 1 - blk;
+            if (pass == 1 && a == blk) break;
+            const int64_t base_a = gs0 + (int64_t)(nocc + a) * e.nvo;
+            const int64_t nitem = (int64_t)(nvirt - a) * nocc;
+            const int64_t roff = (int64_t)s * e.nres + e.offB +
+                                 (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
+            for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
+                const int b = a + (int)(q / nocc), i = (int)(q - (int64_t)(b - a) * nocc);
+                double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
+                double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
+                double r = (a == b) ? y * y : 2.0 * (y * y + yt * yt - y * yt);
+                ((GT *)e.R)[roff + q] = (GT)r;
+            }
+        }
+        return;
+    }
+    const int a = blockIdx.x;
+    const double ea = ev[a];
+    const int64_t base_a = gs0 + (int64_t)(nocc + a) * e.nvo;
+    const int64_t nitem = (int64_t)nvirt * nocc;
+    if constexpr (MODE == EP_GRAD) {
+        const double gsc = e.gscale[s];
+        for (int i = threadIdx.x; i < nocc; i += EP_NT) acc_i[i] = 0.0;
+        __syncthreads();
+        // threads own fixed i (i = tid % nocc) so that per-i sums are deterministic
+        const int per = EP_NT / nocc > 0 ? EP_NT / nocc : 1;
+        const int i0 = threadIdx.x % nocc, bsub = threadIdx.x / nocc;
+        double sa = 0.0, si = 0.0;
+        if (bsub < per) {
+            for (int i = i0; i < nocc; i += (nocc > EP_NT ? EP_NT : nocc)) {
+                double sii = 0.0;
+                for (int b = bsub; b < nvirt; b += per) {
+                    double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
+                    double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
+                    double d = w[0] + eo[i] - ea - ev[b];
+                    double id = 1.0 / d;
+                    double u = (2.0 * y - yt) * y, ut = (2.0 * yt - y) * yt;
+                    ((GT *)e.W)[base_a + (int64_t)b * nocc + i] = (GT)(gsc * (4.0 * y - 2.0 * yt) * id);
+                    sii -= u * id * id;           // role i of element (a, b, i)
+                    sa += (u + ut) * id * id;     // roles a of (a,b,i) and b of (b,a,i)
+                }
+                if (nocc > EP_NT) {
+                    si = sii;
+                    e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + i] = gsc * si;
+                } else {
+                    si = sii;
+                }
+            }
+        }
+        if (nocc <= EP_NT) {
+            // combine the `per` threads sharing each i in fixed order
+            for (int k = 0; k < per; ++k) {
+                __syncthreads();
+                if (bsub == k && bsub < per) acc_i[i0] += si;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < nocc; i += EP_NT)
+                e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + i] = gsc * acc_i[i];
+        }
+        sa = block_sum<EP_NT>(sa, sh);
+        if (threadIdx.x == 0) e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + nocc] = gsc * sa;
+        return;
+    }
+    for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
+        const int b = (int)(q / nocc), i = (int)(q - (int64_t)b * nocc);
+        double y = ld<GT>(e.G, base_a + q);
+        double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
+        double u = (2.0 * y - yt) * y;
+        double dd = eo[i] - ea - ev[b];
+        for (int t = 0; t < T; ++t) {
+            double id = 1.0 / (w[t] + dd);
+            double ui = u * id;
+            acc[t][0] += ui;
+            acc[t][1] -= ui * id;
+        }
+    }
+    flush_partials<EP_NT>(acc, T, e.part + (((int64_t)s * (e.nblkA + e.nblkB) + e.nblkA + a) * e.T) * 2, sh);
+}
+
+// Newton sweep over stored residues: Sigma(w) = sum R / (w - pole), one trial per target.
+// Blocks [0, nvirt) handle part A of a = blockIdx.x; blocks [nvirt, nvirt + ceil(nvirt/2))
+// handle the balanced part-B pairs.
+template <typename RT>
+__global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__restrict__ active)
+{
+    __shared__ double sh[EP_NT / 64];
+    __shared__ double eo[1024];
+    const int s = active[blockIdx.y], nocc = e.nocc, nvirt = e.nvirt;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
+    __syncthreads();
+    const double *ev = e.eps + nocc;
+    const double w = e.omega[s];
+    const RT *R = (const RT *)e.R + (int64_t)s * e.nres;
+    double acc[1][2] = {{0.0, 0.0}};
+    const int blk = blockIdx.x;
+    if (blk < nvirt) {
+        const int a = blk;
+        const int64_t npair = (int64_t)nocc * (nocc + 1) / 2;
+        const RT *Ra = R + (int64_t)a * npair;
+        const double ea = ev[a];
+        for (int64_t p = threadIdx.x; p < npair; p += EP_NT) {
+            int64_t j = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+            if (j * (j + 1) / 2 > p) --j;
+            if ((j + 1) * (j + 2) / 2 <= p) ++j;
+            const int64_t i = p - j * (j + 1) / 2;
+            double id = 1.0 / (w + ea - eo[i] - eo[j]);
+            double ri = (double)Ra[p] * id;
+            acc[0][0] += ri;
+            acc[0][1] -= ri * id;
+        }
+    } else {
+        const int pb = blk - nvirt;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int a = pass == 0 ? pb : nvirt - 1 - pb;
+            if (pass == 1 && a == pb) break;
+            const int64_t nitem = (int64_t)(nvirt - a) * nocc;
+            const RT *Rb = R + e.offB + (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
+            const double ea = ev[a];
+            for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
+                const int b = a + (int)(q / nocc), i = (int)(q - (int64_t)(b - a) * nocc);
+                double id = 1.0 / (w + eo[i] - ea - ev[b]);
+                double ri = (double)Rb[q] * id;
+                acc[0][0] += ri;
+                acc[0][1] -= ri * id;
+            }
+        }
+    }
+    flush_partials<EP_NT>(acc, 1, e.part + ((int64_t)blockIdx.y * (e.nblkA + e.nblkB) + blk) * 2, sh);
+}
+
+// out[s][t][c] = sum over blocks of part[s][blk][t][c] in block order
+__global__ void reduce_partials_kernel(const double *__restrict__ part, int nsc, int nblk, int T,
+                                       double *__restrict__ out)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nsc * T * 2) return;
+    int s = idx / (T * 2), tc = idx - s * T * 2;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[((int64_t)s * nblk + b) * T * 2 + tc];
+    out[idx] = acc;
+}
+
+struct SigmaShape {
+    int prec;
+    int64_t nvec, ldk;
+    int nmo, nocc, nvirt, nsel;
+    int64_t nvo, nselr;
+};
+
+int check_shape(cds_ctx *ctx, const SigmaShape &sh, const int32_t *h_sel, const void *Bsel,
+                const void *Bvo, const double *eps)
+{
+    CDS_REQUIRE(ctx, sh.prec == CDS_PREC_FP64 || sh.prec == CDS_PREC_FP32 || sh.prec == CDS_PREC_BF16X3,
+                "unknown precision %d", sh.prec);
+    CDS_REQUIRE(ctx, sh.nmo >= 2 && sh.nocc >= 1 && sh.nocc < sh.nmo, "need 1 <= nocc < nmo");
+    CDS_REQUIRE(ctx, sh.nocc <= 1024, "nocc must be <= 1024");
+    CDS_REQUIRE(ctx, sh.nsel >= 1 && sh.nsel <= 65535 && h_sel, "need 1 <= nsel and h_sel");
+    CDS_REQUIRE(ctx, sh.nvec >= 1 && sh.ldk >= sh.nvec, "need nvec >= 1, ldk >= nvec");
+    CDS_REQUIRE(ctx, sh.prec != CDS_PREC_BF16X3 || sh.ldk % 64 == 0, "BF16X3 needs ldk % 64 == 0");
+    CDS_REQUIRE(ctx, Bsel && Bvo && eps, "NULL pointer");
+    for (int s = 0; s < sh.nsel; ++s)
+        CDS_REQUIRE(ctx, h_sel[s] >= 0 && h_sel[s] < sh.nmo, "h_sel[%d] out of range", s);
+    return CDS_OK;
+}
+
+// targets per chunk so that G stays below ~4 GiB
+int chunk_targets(const SigmaShape &sh)
+{
+    size_t es = sh.prec == CDS_PREC_FP64 ? 8 : 4;
+    size_t per = (size_t)sh.nmo * sh.nvo * es;
+    size_t lim = (size_t)4 << 30;
+    int n = (int)std::max<size_t>(1, lim / std::max<size_t>(per, 1));
+    return std::min(n, sh.nsel);
+}
+
+// G for targets [s0, s0+nsc)
+int contract_chunk(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void *Bvo, int s0,
+                   int nsc, void *G)
+{
+    const size_t es = sh.prec == CDS_PREC_FP64 ? 8 : (sh.prec == CDS_PREC_FP32 ? 4 : 2);
+    GemmDesc d = {};
+    d.M = (int64_t)nsc * sh.nmo;
+    d.N = sh.nvo;
+    d.K = sh.ldk;
+    d.batch = 1;
+    d.A = (const unsigned char *)Bsel + (size_t)s0 * sh.nmo * sh.ldk * es;
+    d.sAm = sh.ldk;
+    d.sAk = 1;
+    d.B = Bvo;
+    d.sBn = sh.ldk;
+    d.sBk = 1;
+    d.C = G;
+    d.sCm = sh.nvo;
+    d.sCn = 1;
+    d.alpha = 1.0;
+    d.beta = 0.0;
+    const void *Alo = nullptr, *Blo = nullptr;
+    if (sh.prec == CDS_PREC_BF16X3) {
+        Alo = (const __bf16 *)Bsel + sh.nselr * sh.ldk + (int64_t)s0 * sh.nmo * sh.ldk;
+        Blo = (const __bf16 *)Bvo + sh.nvo * sh.ldk;
+    }
+    CdsTimer t;
+    CDS_CALL(cds_timer_start(ctx, &t));
+    CDS_CALL(cds_gemm_ex(ctx, sh.prec, d, Alo, Blo));
+    CDS_CALL(cds_timer_stop(ctx, &t, &ctx->stats.t_contract_ms));
+    ctx->stats.flops_contract += 2.0 * (double)sh.nvec * nsc * sh.nmo * (double)sh.nvo;
+    ctx->stats.n_contract += 1;
+    return CDS_OK;
+}
+
+template <int MODE>
+int launch_epilogue(cds_ctx *ctx, const SigmaShape &sh, EpArgs &e, bool fp64)
+{
+    dim3 ga((unsigned)sh.nvirt, (unsigned)e.nsc);
+    dim3 gb((unsigned)(MODE == EP_RESIDUE ? (sh.nvirt + 1) / 2 : sh.nvirt), (unsigned)e.nsc);
+    if (fp64) {
+        hipLaunchKernelGGL((part_a_kernel<double, MODE>), ga, dim3(EP_NT), 0, ctx->stream, e);
+        hipLaunchKernelGGL((part_b_kernel<double, MODE>), gb, dim3(EP_NT), 0, ctx->stream, e);
+    } else {
+        hipLaunchKernelGGL((part_a_kernel<float, MODE>), ga, dim3(EP_NT), 0, ctx->stream, e);
+        hipLaunchKernelGGL((part_b_kernel<float, MODE>), gb, dim3(EP_NT), 0, ctx->stream, e);
+    }
+    CDS_LAUNCHED(ctx);
+    return CDS_OK;
+}
+
+// Sigma, Sigma' for all targets at T energies each (device omega [nsel][T]) -> host out [nsel][T][2]
+int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void *Bvo,
+               const double *eps, const double *d_omega, int T, double *h_out)
+{
+    const int csz = chunk_targets(sh);
+    const size_t es = sh.prec == CDS_PREC_FP64 ? 8 : 4;
+    void *G, *part, *out;
+    CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * sh.nmo * sh.nvo * es, &G));
+    const int nblk = 2 * sh.nvirt;
+    CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)csz * nblk * T * 2 * 8, &part));
+    CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)sh.nsel * T * 2 * 8, &out));
+    for (int s0 = 0; s0 < sh.nsel; s0 += csz) {
+        const int nsc = std::min(csz, sh.nsel - s0);
+        CDS_CALL(contract_chunk(ctx, sh, Bsel, Bvo, s0, nsc, G));
+        EpArgs e = {};
+        e.G = G;
+        e.nmo = sh.nmo;
+        e.nocc = sh.nocc;
+        e.nvirt = sh.nvirt;
+        e.nsc = nsc;
+        e.nvo = sh.nvo;
+        e.eps = eps;
+        e.omega = d_omega + (int64_t)s0 * T;
+        e.T = T;
+        e.part = (double *)part;
+        e.nblkA = sh.nvirt;
+        e.nblkB = sh.nvirt;
+        CdsTimer t;
+        CDS_CALL(cds_timer_start(ctx, &t));
+        CDS_CALL(launch_epilogue<EP_SIGMA>(ctx, sh, e, sh.prec == CDS_PREC_FP64));
+        int n = nsc * T * 2;
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
+                           ctx->stream, (const double *)part, nsc, nblk, T,
+                           (double *)out + (int64_t)s0 * T * 2);
+        CDS_LAUNCHED(ctx);
+        CDS_CALL(cds_timer_stop(ctx, &t, &ctx->stats.t_epilogue_ms));
+    }
+    CDS_HIP(ctx, hipMemcpyAsync(h_out, out, (size_t)sh.nsel * T * 2 * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return CDS_OK;
+}
+
+}  // namespace
+
+// shared with the adjoint translation unit
+int cds_sigma_eval_internal(cds_ctx *ctx, int prec, int64_t nvec, int64_t ldk, int nmo, int nocc,
+                            int nsel, const void *Bsel, const void *Bvo, const double *eps,
+                            const double *h_omega, int T, double *h_out)
+{
+    SigmaShape sh = {prec, nvec, ldk, nmo, nocc, nmo - nocc, nsel,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsel * nmo};
+    void *om;
+    CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * T * 8, &om));
+    CDS_HIP(ctx, hipMemcpyAsync(om, h_omega, (size_t)nsel * T * 8, hipMemcpyHostToDevice, ctx->stream));
+    return eval_sigma(ctx, sh, Bsel, Bvo, eps, (const double *)om, T, h_out);
+}
+
+// G for targets [s0, s0+nsc) into buffer G (adjoint)
+int cds_contract_internal(cds_ctx *ctx, int prec, int64_t nvec, int64_t ldk, int nmo, int nocc,
+                          int nsel, const void *Bsel, const void *Bvo, int s0, int nsc, void *G)
+{
+    SigmaShape sh = {prec, nvec, ldk, nmo, nocc, nmo - nocc, nsel,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsel * nmo};
+    return contract_chunk(ctx, sh, Bsel, Bvo, s0, nsc, G);
+}
+
+// gradient-weight epilogue for a chunk (adjoint)
+int cds_grad_epilogue_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int nsc, const void *G,
+                               const double *eps, const double *d_omega, const double *d_gscale,
+                               void *W, double *epsA, double *epsB)
+{
+    SigmaShape sh = {prec, 0, 0, nmo, nocc, nmo - nocc, nsc,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsc * nmo};
+    EpArgs e = {};
+    e.G = G;
+    e.nmo = nmo;
+    e.nocc = nocc;
+    e.nvirt = nmo - nocc;
+    e.nsc = nsc;
+    e.nvo = sh.nvo;
+    e.eps = eps;
+    e.omega = d_omega;
+    e.T = 1;
+    e.gscale = d_gscale;
+    e.W = W;
+    e.epsA = epsA;
+    e.epsB = epsB;
+    return launch_epilogue<EP_GRAD>(ctx, sh, e, prec == CDS_PREC_FP64);
+}
+
+extern "C" int cds_sigma2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                          int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                          const void *Bvo, const double *eps, int32_t T, const double *h_omega,
+                          double *h_sigma, double *h_dsigma)
+{
+    CDS_CALL(cds_enter(ctx));
+    SigmaShape sh = {prec, nvec, ldk, nmo, nocc, nmo - nocc, nsel,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsel * nmo};
+    CDS_CALL(check_shape(ctx, sh, h_sel, Bsel, Bvo, eps));
+    CDS_REQUIRE(ctx, T >= 1 && T <= TMAX, "T must be in [1, %d]", TMAX);
+    CDS_REQUIRE(ctx, h_omega && h_sigma && h_dsigma, "NULL host pointer");
+    std::vector<double> out((size_t)nsel * T * 2);
+    CDS_CALL(cds_sigma_eval_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, eps, h_omega, T,
+                                     out.data()));
+    for (int64_t k = 0; k < (int64_t)nsel * T; ++k) {
+        h_sigma[k] = out[2 * k];
+        h_dsigma[k] = out[2 * k + 1];
+    }
+    CDS_CALL(cds_timers_flush(ctx));
+    return CDS_OK;
+}
+
+extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                            int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                            const void *Bvo, const double *eps, const double *h_omega0, double conv,
+                            int32_t max_iter, int32_t mode, double *h_omega, double *h_pole,
+                            int32_t *h_iters, int32_t *h_status)
+{
+    CDS_CALL(cds_enter(ctx));
+    SigmaShape sh = {prec, nvec, ldk, nmo, nocc, nmo - nocc, nsel,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsel * nmo};
+    CDS_CALL(check_shape(ctx, sh, h_sel, Bsel, Bvo, eps));
+    CDS_REQUIRE(ctx, max_iter >= 1, "max_iter must be >= 1");
+    CDS_REQUIRE(ctx, conv >= 0.0 && std::isfinite(conv), "conv must be finite and >= 0");
+    CDS_REQUIRE(ctx, mode == CDS_QP_RECOMPUTE || mode == CDS_QP_RESIDUES, "unknown mode %d", mode);
+    CDS_REQUIRE(ctx, h_omega && h_pole && h_iters && h_status, "NULL host pointer");
+
+    CdsTimer tall;
+    CDS_CALL(cds_timer_start(ctx, &tall));
+    std::vector<double> heps(nmo);
+    CDS_HIP(ctx, hipMemcpyAsync(heps.data(), eps, (size_t)nmo * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+
+    std::vector<double> w(nsel), pole(nsel, NAN);
+    std::vector<int> active, status(nsel, -1), iters(nsel, 0);
+    for (int s = 0; s < nsel; ++s) w[s] = h_omega0 ? h_omega0[s] : heps[h_sel[s]];
+
+    // residue mode: one contraction per target chunk, residues kept on the device
+    const int64_t npairA = (int64_t)nocc * (nocc + 1) / 2;
+    const int64_t nres = (int64_t)sh.nvirt * npairA + (int64_t)nocc * sh.nvirt * (sh.nvirt + 1) / 2;
+    const size_t res_es = prec == CDS_PREC_FP64 ? 8 : 4;
+    void *R = nullptr, *om = nullptr, *part = nullptr, *outd = nullptr, *act = nullptr;
+    const int nblkA = sh.nvirt, nblkB = (sh.nvirt + 1) / 2;
+    if (mode == CDS_QP_RESIDUES) {
+        CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * nres * res_es + (size_t)nsel * 4, &R));
+        const int csz = chunk_targets(sh);
+        void *G;
+        CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * nmo * sh.nvo * res_es, &G));
+        for (int s0 = 0; s0 < nsel; s0 += csz) {
+            const int nsc = std::min(csz, nsel - s0);
+            CDS_CALL(contract_chunk(ctx, sh, Bsel, Bvo, s0, nsc, G));
+            EpArgs e = {};
+            e.G = G;
+            e.nmo = nmo;
+            e.nocc = nocc;
+            e.nvirt = sh.nvirt;
+            e.nsc = nsc;
+            e.nvo = sh.nvo;
+            e.eps = eps;
+            e.R = (unsigned char *)R + (size_t)s0 * nres * res_es;
+            e.nres = nres;
+            e.offB = (int64_t)sh.nvirt * npairA;
+            CdsTimer t;
+            CDS_CALL(cds_timer_start(ctx, &t));
+            CDS_CALL(launch_epilogue<EP_RESIDUE>(ctx, sh, e, prec == CDS_PREC_FP64));
+            CDS_CALL(cds_timer_stop(ctx, &t, &ctx->stats.t_epilogue_ms));
+        }
+        CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * 8, &om));
+        CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsel * (nblkA + nblkB) * 2 * 8, &part));
+        CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)nsel * 2 * 8 + (size_t)nsel * 4 + 64, &outd));
+        act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
+    }
+    void *hp;
+    CDS_CALL(cds_pinned(ctx, (size_t)nsel * (2 * 8 + 8 + 4) + 64, &hp));
+    double *h_out = (double *)hp;
+    double *h_w = h_out + (size_t)nsel * 2;
+    int *h_act = (int *)(h_w + nsel);
+
+    for (int s = 0; s < nsel; ++s) active.push_back(s);
+    std::vector<double> out_all((size_t)nsel * 2);
+    for (int it = 1; it <= max_iter && !active.empty(); ++it) {
+        if (mode == CDS_QP_RESIDUES) {
+            for (int s = 0; s < nsel; ++s) h_w[s] = w[s];
+            for (size_t k = 0; k < active.size(); ++k) h_act[k] = active[k];
+            CDS_HIP(ctx, hipMemcpyAsync(om, h_w, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
+            CDS_HIP(ctx, hipMemcpyAsync(act, h_act, active.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+            EpArgs e = {};
+            e.nmo = nmo;
+            e.nocc = nocc;
+            e.nvirt = sh.nvirt;
+            e.nvo = sh.nvo;
+            e.eps = eps;
+            e.omega = (const double *)om;
+            e.T = 1;
+            e.R = R;
+            e.nres = nres;
+            e.offB = (int64_t)sh.nvirt * npairA;
+            e.part = (double *)part;
+            e.nblkA = nblkA;
+            e.nblkB = nblkB;
+            dim3 g((unsigned)(nblkA + nblkB), (unsigned)active.size());
+            if (prec == CDS_PREC_FP64)
+                hipLaunchKernelGGL(sweep_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
+            else
+                hipLaunchKernelGGL(sweep_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
+            CDS_LAUNCHED(ctx);
+            int n = (int)active.size() * 2;
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
+                               ctx->stream, (const double *)part, (int)active.size(), nblkA + nblkB, 1,
+                               (double *)outd);
+            CDS_LAUNCHED(ctx);
+            CDS_HIP(ctx, hipMemcpyAsync(h_out, outd, (size_t)active.size() * 2 * 8, hipMemcpyDeviceToHost,
+                                        ctx->stream));
+            CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            for (size_t k = 0; k < active.size(); ++k) {
+                out_all[2 * active[k]] = h_out[2 * k];
+                out_all[2 * active[k] + 1] = h_out[2 * k + 1];
+            }
+        } else {
+            // recompute the integrals for every target at its current energy (T = 1)
+            CDS_CALL(cds_sigma_eval_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, eps,
+                                             w.data(), 1, out_all.data()));
+        }
+        ctx->stats.n_newton_iter += 1;
+        std::vector<int> still;
+        for (int s : active) {
+            const double q_eps = heps[h_sel[s]];
+            const double sg = out_all[2 * s], ds = out_all[2 * s + 1];
+            iters[s] = it;
+            if (!std::isfinite(sg) || !std::isfinite(ds)) {   // a denominator vanished
+                status[s] = CDS_QP_NONFINITE;
+                continue;
+            }
+            const double P = 1.0 / (1.0 - ds);
+            const double wn = w[s] + (q_eps + sg - w[s]) * P;
+            pole[s] = P;
+            if (!std::isfinite(wn) || !std::isfinite(P)) {
+                w[s] = wn;
+                status[s] = CDS_QP_NONFINITE;
+                continue;
+            }
+            if (std::fabs(wn - w[s]) <= conv) {
+                w[s] = wn;
+                status[s] = CDS_QP_CONVERGED;
+                continue;
+            }
+            w[s] = wn;
+            still.push_back(s);
+        }
+        active.swap(still);
+    }
+    for (int s : active) status[s] = CDS_QP_MAX_ITER;
+    for (int s = 0; s < nsel; ++s) {
+        h_omega[s] = w[s];
+        h_pole[s] = pole[s];
+        h_iters[s] = iters[s];
+        h_status[s] = status[s];
+    }
+    CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_newton_ms));
+    CDS_CALL(cds_timers_flush(ctx));
+    return CDS_OK;
+}
