@@ -14,9 +14,10 @@
 //            a*b ~ hi*hi + hi*lo + lo*hi, three v_mfma_f32_16x16x32_bf16 per
 //            block and 32-k slice, FP32 accumulation; 64 k per stage
 //
-// MFMA lane layout (16 x 16 output): lane l holds output rows 4*(l/16)+e,
-// e = 0..3, of column l%16; operand A supplies row l%16, operand B column
-// l%16.  The k index carried by a lane is permuted consistently for A and B
+// MFMA lane layout (16 x 16 output, measured on gfx950): lane l holds column
+// l%16; for the f32-accumulating MFMAs its four values are rows 4*(l/16)+e,
+// for v_mfma_f64_16x16x4f64 rows (l/16)+4*e, e = 0..3.  Operand A supplies
+// row l%16, operand B column l%16.  The k index carried by a lane is permuted consistently for A and B
 // (lane group g = l/16 reads 16-byte chunks g and g+4 of the 128-byte k
 // slice), which leaves the k-sum unchanged.
 #include "cds_internal.h"
@@ -242,7 +243,8 @@ __global__ __launch_bounds__(NT, PREC == CDS_PREC_FP64 ? 1 : 2) void gemm_kernel
             if (n >= a.N) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t m = m0 + wm + 16 * i + 4 * g + e;
+                // f32/bf16 MFMA: lane group g holds rows 4g..4g+3; f64: rows g, g+4, g+8, g+12
+                const int64_t m = m0 + wm + 16 * i + (PREC == CDS_PREC_FP64 ? g + 4 * e : 4 * g + e);
                 if (m >= a.M) continue;
                 O *dst = C + m * a.sCm + n * a.sCn;
                 double v = a.alpha * (double)acc[i][j][e];
