@@ -195,7 +195,8 @@ def cholesky(delta: float, *, centres: torch.Tensor | None = None, alpha: torch.
             piv[:nvec_in] = resume.piv[:nvec_in]
         D = resume.D.clone()
     else:
-        Lbuf = torch.zeros((max_vec, ldl), dtype=torch.float64, device=dev)
+        # every entry the library reads is written first (vectors < nvec, rows < npairs)
+        Lbuf = torch.empty((max_vec, ldl), dtype=torch.float64, device=dev)
         piv = torch.zeros(max_vec, dtype=torch.int64, device=dev)
         D = torch.empty(np_, dtype=torch.float64, device=dev)
     nvec = ctypes.c_int64()
