@@ -79,7 +79,7 @@ typedef struct cds_ctx cds_ctx;
  * algorithmic bytes and flops.  Reset by cds_reset_stats(). */
 typedef struct cds_stats {
     double t_cd_ms;          /* pivoted Cholesky: all step kernels            */
-    double t_cd_kernel_ms;   /* partial-GEMV kernel time only                 */
+    double t_cd_kernel_ms;   /* Cholesky step-kernel time (with kernel timing on) */
     double t_transform_ms;   /* AO->MO transform                              */
     double t_contract_ms;    /* contraction GEMM launches                     */
     double t_epilogue_ms;    /* denominator sums / residue forming            */
@@ -90,6 +90,13 @@ typedef struct cds_stats {
     int64_t n_cd_steps;
     int64_t n_contract;
     int64_t n_newton_iter;
+    double t_cd_pass_ms;     /* look-ahead pass kernels (with kernel timing on) */
+    double bytes_cd_pass;    /* bytes those passes read/write: 8 npairs (k0 + ncand) */
+    int64_t n_cd_pass;       /* look-ahead blocks started                     */
+    int64_t n_cd_miss;       /* steps whose pivot was not a look-ahead candidate */
+    double flops_cd_pass;    /* nominal pass flops: 2 npairs k0 (64 candidates) */
+    double bytes_cd_step;    /* bytes the step kernels moved: 8 npairs (k - first
+                                vector subtracted) + 42 npairs per step         */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -101,9 +108,16 @@ void cds_destroy(cds_ctx *ctx);
 const char *cds_last_error(const cds_ctx *ctx);
 int cds_get_stats(const cds_ctx *ctx, cds_stats *out);
 int cds_reset_stats(cds_ctx *ctx);
-/* 1: time every partial-GEMV launch of the Cholesky step with HIP events
- * (accumulated in cds_stats.t_cd_kernel_ms); 0 (default): off. */
+/* 1: time every step-kernel and look-ahead-pass launch of the Cholesky
+ * decomposition with HIP events (cds_stats.t_cd_kernel_ms, t_cd_pass_ms);
+ * 0 (default): off. */
 int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
+/* Look-ahead of the pivoted Cholesky: every block_steps steps one pass over L
+ * forms the residual columns of up to 64 candidate pivots (the next pivot and
+ * the largest residual diagonals); steps whose pivot is a candidate then only
+ * subtract the vectors made since.  0 disables it (each step streams all of L).
+ * Default 16; valid range [0, 256]. */
+int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
 /* Library version string (static). */
 const char *cds_version(void);
 
@@ -138,7 +152,13 @@ int cds_eri_columns(cds_ctx *ctx, int32_t nbf, const double *centres, const doub
  *    1e3 * 2^-52 * max_I V_II; a non-pivot D_I < -psd_tol stops with ENOTPSD.
  * nvec_in: 0 starts afresh; > 0 resumes from vectors 0..nvec_in-1, their
  *    pivots and D exactly as an earlier call left them (to a smaller delta or
- *    larger max_vec).  Resumed and direct runs give identical results.
+ *    larger max_vec).  Resumed and direct runs make the same pivots; with the
+ *    look-ahead off (cds_set_cd_lookahead(ctx, 0)) they are bitwise identical,
+ *    with it on the vectors agree to rounding (different summation grouping).
+ *
+ * The residual columns are formed with a look-ahead over candidate pivots
+ * (see cds_set_cd_lookahead); the pivot rule and the results are those of the
+ * plain one-vector-per-step algorithm above.
  * h_nvec: vectors made in total; h_dmax: final D_max; h_status: CDS_CD_*.
  * Returns CDS_OK (converged or full rank), CDS_ECAP, CDS_ENOTPSD, or an error.
  */

@@ -97,6 +97,10 @@ class Context:
     def set_kernel_timing(self, on: bool):
         self.check(self.lib.cds_set_kernel_timing(self.h, int(bool(on))))
 
+    def set_cd_lookahead(self, block_steps: int):
+        """Cholesky look-ahead block length (0: plain one-vector-per-step streaming)."""
+        self.check(self.lib.cds_set_cd_lookahead(self.h, int(block_steps)))
+
 
 _default = {}
 

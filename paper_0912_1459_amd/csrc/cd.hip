@@ -3,19 +3,33 @@
 // columns of normalized s-Gaussians evaluated on demand (Eq. (integral),
 // closed form through the Boys function F0).
 //
-// Device layout (HBM):
-//   pair table  SoA  p[I], Px[I], Py[I], Pz[I], K[I]     5 x npairs FP64
-//   L           vector-major, vector k at L + k*ldl        FP64
-//   D           residual diagonal                           FP64[npairs]
-//   mask        1 on pivot pairs                            u8[npairs]
-//   part        partial GEMV sums, split s at part + s*npad FP64
+// Each step k picks the pivot p (lowest index within tau of the largest residual
+// diagonal), forms the residual column c = V[:,p] - sum_{j<k} L[j] L[j][p], sets
+// L[k] = c / sqrt(D_p) and updates D.  Done literally, step k streams k*npairs*8
+// bytes of L.  This implementation forms the same residual columns with a
+// look-ahead over candidate pivots, which leaves the pivot sequence unchanged:
 //
-// One step k (three launches, no host round trip):
-//   cd_partial   grid (row tiles x j-splits): part[s][I] = sum_{j in split s} L[j][I] L[j][p]
-//   cd_finalize  grid (row tiles): c_I = V_Ip - sum_s part[s][I]; L[k][I] = c_I / sqrt(D_p)
-//                (0 on earlier pivots, sqrt(D_p) on p); D_I -= L[k][I]^2; per-tile max/min
-//   cd_select    one block: D_max, status, next pivot = lowest index with D_I >= D_max - tau
-// The partial kernel streams k*npairs*8 bytes of L per step: it is HBM-bound.
+//   every `block_steps` steps (default 16; block start at step k0):
+//     cd_cand    the pivot of step k0 plus the argmax rows of the tiles with the
+//                largest residual diagonals (up to CD_NCAND candidates)
+//     cd_gather  P[j][c] = L[j][cand_c]                               j < k0
+//     cd_pass    R[c][I] = V[I][cand_c] - sum_{j<k0} L[j][I] P[j][c]  (one read of L,
+//                FP64 MFMA)
+//   every step k, ONE launch (cd_step), each 64-row block:
+//     - picks the pivot itself from the previous step's statistics (64 super-tile
+//       maxima kept with order-preserving integer atomics, then one super-tile's
+//       tiles, then one tile's rows); every block reaches the same pivot;
+//     - c_I = R[slot][I] - sum_{k0<=j<k} L[j][I] L[j][p] when p is candidate `slot`,
+//       else V_Ip - sum_{j<k} L[j][I] L[j][p] (a miss);
+//     - writes L[k], the next residual diagonal and pivot mask, tile statistics.
+//   D, the mask and the tile statistics are double-buffered and the super-tile
+//   statistics triple-buffered by step parity, so no block reads what another
+//   block of the same launch writes: no fences or grid barriers.
+//
+// Device layout (HBM): pair table SoA p, Px, Py, Pz, K (5 x npairs FP64); L vector-
+// major (vector k at L + k*ldl); D FP64[2][npairs] (the first copy is the caller's);
+// pivot mask u8[2][npairs]; candidate residual columns R[c][ldr]; candidate rows
+// P[j][CD_NCAND].
 #include "cds_internal.h"
 
 #include <cfloat>
@@ -23,23 +37,65 @@
 
 namespace {
 
-constexpr int CD_BLOCK = 256;           // threads of the partial/finalize kernels
-constexpr int CD_JCHUNK = 128;          // vectors per j-split of the partial GEMV
-constexpr int CD_FIN_TILE = 256;        // rows per finalize tile (one per thread)
-constexpr int CD_SEL_BLOCK = 1024;
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int CD_TILE = 64;             // rows per step/pass block (= pivot scan tile)
+constexpr int CD_NT = 256;              // threads of the step kernel
+constexpr int CD_PCHUNK = 1024;         // pivot-row entries staged in LDS per chunk
+constexpr int CD_AUX_NT = 1024;         // threads of the one-block kernels
+constexpr int CD_NSUP = 64;             // super-tiles of the hierarchical pivot search
+constexpr int CD_NCAND = 64;            // candidate residual columns per look-ahead block
+constexpr int CD_PASS_JC = 64;          // candidate-row entries staged per pass chunk
 
 struct PairTable {
     double *p, *Px, *Py, *Pz, *K;
 };
 
 struct CdState {
-    int64_t k;       // vectors made so far
-    int64_t p;       // pivot of the next vector
-    double dp;       // residual diagonal of that pivot
-    double dmax;     // largest non-pivot residual diagonal
+    int64_t k;       // vectors made so far (block 0 of every step)
+    double dmax;     // largest non-pivot residual diagonal seen by the last step
     int32_t done;    // 1 once a termination rule fired
     int32_t status;  // CDS_CD_* once done
+    int32_t ncand;   // candidates of the current look-ahead block
+    int32_t pad;
+    int64_t nmiss;   // steps whose pivot was not a candidate
+    double bytes;    // bytes the step kernels read and wrote (8 npairs (k - jstart) + 42 npairs)
 };
+
+struct CdBufs {
+    double *D[2];                       // residual diagonal, by parity
+    unsigned char *mask[2];             // pivot mask, by parity
+    double *tmax[2];                    // per-tile max of non-pivot D
+    int64_t *targ[2];                   // its row (lowest index on ties)
+    double *tmin[2];                    // per-tile min of non-pivot D
+    unsigned long long *smax[3];        // super-tile max keys (atomicMax), triple-buffered
+    unsigned long long *smin[3];        // super-tile min keys (atomicMin)
+    int64_t ntile, tps;                 // tiles; tiles per super-tile
+};
+
+struct CdParams {
+    int64_t npairs, max_vec;
+    double delta, tau, psd_tol;
+};
+
+// order-preserving map of doubles to unsigned keys; 0 means "no entry" (-inf),
+// ~0 means "no entry" for minima (+inf)
+__device__ __forceinline__ unsigned long long okey(double v)
+{
+    long long b = __double_as_longlong(v);
+    return b < 0 ? ~(unsigned long long)b : ((unsigned long long)b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double okey_max(unsigned long long u)
+{
+    if (u == 0ull) return -INFINITY;
+    return (u & 0x8000000000000000ull) ? __longlong_as_double((long long)(u & 0x7fffffffffffffffull))
+                                       : __longlong_as_double((long long)~u);
+}
+__device__ __forceinline__ double okey_min(unsigned long long u)
+{
+    if (u == ~0ull) return INFINITY;
+    return okey_max(u);
+}
 
 __device__ __forceinline__ double boys_f0(double T)
 {
@@ -164,7 +220,143 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *sh)
     return sh[0];
 }
 
-// ---- CD kernels ------------------------------------------------------------------
+
+// (value, index) argmax: larger value wins, lower index on equal values
+__device__ __forceinline__ void amax_merge(double &v, int64_t &i, double v2, int64_t i2)
+{
+    if (v2 > v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void block_argmax(double &v, int64_t &idx, double *shv, int64_t *shi)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        double v2 = __shfl_xor(v, o, 64);
+        int64_t i2 = __shfl_xor(idx, o, 64);
+        amax_merge(v, idx, v2, i2);
+    }
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        shv[w] = v;
+        shi[w] = idx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < NT / 64; ++k) amax_merge(shv[0], shi[0], shv[k], shi[k]);
+    }
+    __syncthreads();
+    v = shv[0];
+    idx = shi[0];
+    __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int *sh, int *total)
+{
+    // inclusive scan within each wave, then over the wave totals (fixed order)
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (l >= o) x += y;
+    }
+    __syncthreads();
+    if (l == 63) sh[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int i = 0; i < NT / 64; ++i) {
+            int t = sh[i];
+            sh[i] = a;
+            a += t;
+        }
+        sh[NT / 64] = a;
+    }
+    __syncthreads();
+    int r = sh[w] + x - v;
+    *total = sh[NT / 64];
+    __syncthreads();
+    return r;
+}
+
+// ---- pivot choice (identical in every block that calls it) --------------------
+enum { PICK_GO = -100 };
+
+struct Pick {
+    int status;      // PICK_GO or a CDS_CD_* termination
+    double mx;       // largest non-pivot residual diagonal
+    int64_t p;       // pivot
+    double dp;       // its residual diagonal
+};
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Largest non-pivot D from the super-tile keys, termination tests, then the lowest index
+// I (not a pivot) with D_I >= D_max - tau: first super-tile, then first tile, then first
+// row, each found with one wave-wide ballot.  Executed by the 64 lanes of ONE wave; every
+// block that calls it on the same buffers gets the same answer.
+__device__ Pick cd_pick_wave(const CdBufs &b, int r, int sr, const CdParams &cp, int64_t k)
+{
+    const int l = threadIdx.x & 63;               // CD_NSUP == 64: one super-tile per lane
+    const double v = okey_max(b.smax[sr][l]);
+    const double mx = wave_max(v);
+    const double mn = wave_min(okey_min(b.smin[sr][l]));
+    Pick pk;
+    pk.mx = mx;
+    pk.p = -1;
+    pk.dp = 0.0;
+    pk.status = PICK_GO;
+    if (mn < -cp.psd_tol) pk.status = CDS_CD_NOTPSD;
+    else if (mx == -INFINITY) pk.status = CDS_CD_FULLRANK;
+    else if (mx <= cp.delta) pk.status = CDS_CD_CONVERGED;
+    else if (k >= cp.max_vec) pk.status = CDS_CD_CAP;
+    if (pk.status != PICK_GO) return pk;
+    const double thresh = mx - cp.tau;
+    const unsigned long long bs = __ballot(v >= thresh);
+    const int64_t sidx = __ffsll((long long)bs) - 1;
+    int64_t t = -1;
+    if (bs) {
+        const int64_t t0 = sidx * b.tps, t1 = min(b.ntile, t0 + b.tps);
+        for (int64_t u0 = t0; u0 < t1; u0 += 64) {
+            const int64_t u = u0 + l;
+            const unsigned long long bt = __ballot(u < t1 && b.tmax[r][u] >= thresh);
+            if (bt) {
+                t = u0 + __ffsll((long long)bt) - 1;
+                break;
+            }
+        }
+    }
+    if (t < 0) {                                  // only with non-finite residuals
+        pk.status = CDS_CD_NOTPSD;
+        return pk;
+    }
+    const int64_t I = t * CD_TILE + l;
+    const double d = I < cp.npairs ? b.D[r][I] : -INFINITY;
+    const bool ok = I < cp.npairs && !b.mask[r][I] && d >= thresh;
+    const unsigned long long bp = __ballot(ok);
+    if (!bp) {
+        pk.status = CDS_CD_NOTPSD;
+        return pk;
+    }
+    const int lp = __ffsll((long long)bp) - 1;
+    pk.p = t * CD_TILE + lp;
+    pk.dp = __shfl(d, lp, 64);
+    return pk;
+}
+
 __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, int64_t npairs,
                                    unsigned char *__restrict__ mask)
 {
@@ -175,199 +367,408 @@ __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, i
     }
 }
 
-// per-tile max and min of non-pivot residual diagonals (start / resume)
-__global__ __launch_bounds__(CD_FIN_TILE) void tile_stats_kernel(
-    int64_t npairs, const double *__restrict__ D, const unsigned char *__restrict__ mask,
-    double *__restrict__ tmax, double *__restrict__ tmin)
+// tile and super-tile statistics of D[0] / mask[0] (start or resume)
+__global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, int64_t npairs)
 {
-    __shared__ double sh[CD_FIN_TILE / 64];
-    int64_t I = (int64_t)blockIdx.x * CD_FIN_TILE + threadIdx.x;
+    __shared__ double shv[1], sh[1];
+    __shared__ int64_t shi[1];
+    const int64_t I = (int64_t)blockIdx.x * CD_TILE + threadIdx.x;
     double mx = -INFINITY, mn = INFINITY;
-    if (I < npairs && !mask[I]) mx = mn = D[I];
-    mx = block_max<CD_FIN_TILE>(mx, sh);
-    mn = block_min<CD_FIN_TILE>(mn, sh);
+    int64_t ix = INT64_MAX;
+    if (I < npairs && !b.mask[0][I]) {
+        mx = mn = b.D[0][I];
+        ix = I;
+    }
+    block_argmax<CD_TILE>(mx, ix, shv, shi);
+    mn = block_min<CD_TILE>(mn, sh);
     if (threadIdx.x == 0) {
-        tmax[blockIdx.x] = mx;
-        tmin[blockIdx.x] = mn;
+        b.tmax[0][blockIdx.x] = mx;
+        b.targ[0][blockIdx.x] = ix;
+        b.tmin[0][blockIdx.x] = mn;
+        const int64_t sidx = blockIdx.x / b.tps;
+        if (mx != -INFINITY) atomicMax(&b.smax[0][sidx], okey(mx));
+        if (mn != INFINITY) atomicMin(&b.smin[0][sidx], okey(mn));
     }
 }
 
-// part[s][I..I+VW-1] = sum_{j in split s} L[j][I] * L[j][p]
-template <int VW>
-__global__ __launch_bounds__(CD_BLOCK) void cd_partial_kernel(
-    const double *__restrict__ L, int64_t ldl, int64_t npairs, int64_t npad,
-    const CdState *__restrict__ st, double *__restrict__ part)
-{
-    __shared__ double prow[CD_JCHUNK];
-    if (st->done) return;
-    const int64_t k = st->k, p = st->p;
-    const int64_t j0 = (int64_t)blockIdx.y * CD_JCHUNK;
-    const int64_t j1 = min(j0 + (int64_t)CD_JCHUNK, k);
-    const int nj = (int)(j1 - j0);
-    for (int t = threadIdx.x; t < nj; t += CD_BLOCK) prow[t] = L[(j0 + t) * ldl + p];
-    __syncthreads();
-    const int64_t I = ((int64_t)blockIdx.x * CD_BLOCK + threadIdx.x) * VW;
-    if (I >= npairs) return;
-    const double *Lp = L + j0 * ldl + I;
-    if constexpr (VW == 2) {
-        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-        int j = 0;
-        for (; j + 4 <= nj; j += 4) {
-            double2 v0 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + 0) * ldl);
-            double2 v1 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + 1) * ldl);
-            double2 v2 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + 2) * ldl);
-            double2 v3 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + 3) * ldl);
-            a0 = fma(v0.x, prow[j], a0);
-            a1 = fma(v0.y, prow[j], a1);
-            b0 = fma(v1.x, prow[j + 1], b0);
-            b1 = fma(v1.y, prow[j + 1], b1);
-            a0 = fma(v2.x, prow[j + 2], a0);
-            a1 = fma(v2.y, prow[j + 2], a1);
-            b0 = fma(v3.x, prow[j + 3], b0);
-            b1 = fma(v3.y, prow[j + 3], b1);
-        }
-        for (; j < nj; ++j) {
-            double2 v = *reinterpret_cast<const double2 *>(Lp + (int64_t)j * ldl);
-            a0 = fma(v.x, prow[j], a0);
-            a1 = fma(v.y, prow[j], a1);
-        }
-        double2 r;
-        r.x = a0 + b0;
-        r.y = a1 + b1;
-        *reinterpret_cast<double2 *>(part + (int64_t)blockIdx.y * npad + I) = r;
-    } else {
-        double a0 = 0.0, b0 = 0.0;
-        int j = 0;
-        for (; j + 2 <= nj; j += 2) {
-            a0 = fma(Lp[(int64_t)j * ldl], prow[j], a0);
-            b0 = fma(Lp[(int64_t)(j + 1) * ldl], prow[j + 1], b0);
-        }
-        for (; j < nj; ++j) a0 = fma(Lp[(int64_t)j * ldl], prow[j], a0);
-        part[(int64_t)blockIdx.y * npad + I] = a0 + b0;
-    }
-}
-
-// new vector k, residual diagonal update, per-tile max/min of the updated D
-template <bool DENSE>
-__global__ __launch_bounds__(CD_FIN_TILE) void cd_finalize_kernel(
+// One Cholesky step (one launch).  Block = CD_TILE rows; thread (jg, rl): rows I0..I0+VW-1,
+// vectors j = jstart + jg, + JG, ...; partial sums combined in LDS in fixed order.
+// r/w: read/write parity of D, mask and tile stats; sr/sw/sz: super-tile buffers read,
+// written (atomics) and reset for the step after next.  Loads that do not depend on the
+// pivot (the vectors made since the block start, D, mask) are issued before wave 0
+// finishes the pivot search.
+template <int VW, bool DENSE>
+__global__ __launch_bounds__(CD_NT) void cd_step_kernel(
+    CdBufs b, CdParams cp, int r, int sr, int sw, int sz, int64_t k, int64_t k0, int bsteps,
     PairTable pt, const double *__restrict__ V, int64_t ldv, double *__restrict__ L, int64_t ldl,
-    int64_t npairs, int64_t npad, const double *__restrict__ part, int nsplit,
-    double *__restrict__ D, unsigned char *__restrict__ mask, const CdState *__restrict__ st,
-    double *__restrict__ tmax, double *__restrict__ tmin)
+    const double *__restrict__ R, int64_t ldr, const int64_t *__restrict__ cand, CdState *st,
+    int64_t *__restrict__ piv)
 {
-    __shared__ double sh[CD_FIN_TILE / 64];
+    constexpr int RL = CD_TILE / VW;            // row lanes
+    constexpr int JG = CD_NT / RL;              // vector groups
+    constexpr int NPF = 2;                      // prefetched vectors per thread
+    __shared__ double sp[CD_PCHUNK];
+    __shared__ double red[JG][CD_TILE];
+    __shared__ double shd[CD_NT / 64];
+    __shared__ double shv[CD_NT / 64];
+    __shared__ int64_t shi[CD_NT / 64];
+    __shared__ Pick spk;
+    __shared__ int sslot;
     if (st->done) return;
-    const int64_t k = st->k, p = st->p;
-    const double sq = sqrt(st->dp);
-    const int64_t I = (int64_t)blockIdx.x * CD_FIN_TILE + threadIdx.x;
+    const int rl = threadIdx.x % RL, jg = threadIdx.x / RL;
+    const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
+    const int64_t I0 = tile0 + (int64_t)VW * rl;
+    const bool rows_ok = I0 < cp.npairs;
+    // prefetch (independent of the pivot)
+    const int64_t nblk = bsteps > 0 ? k - k0 : 0;        // vectors since the block start
+    double pf[NPF][VW];
+#pragma unroll
+    for (int m = 0; m < NPF; ++m) {
+        const int64_t j = k0 + jg + (int64_t)m * JG;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) pf[m][v] = 0.0;
+        if (rows_ok && j < k0 + nblk) {
+            if constexpr (VW == 2) {
+                double2 x = *reinterpret_cast<const double2 *>(L + j * ldl + I0);
+                pf[m][0] = x.x;
+                pf[m][1] = x.y;
+            } else {
+                pf[m][0] = L[j * ldl + I0];
+            }
+        }
+    }
+    const int64_t If = tile0 + threadIdx.x;              // finalize row of threads < CD_TILE
+    double d_old = 0.0;
+    unsigned char m_old = 1;
+    if (threadIdx.x < CD_TILE && If < cp.npairs) {
+        d_old = b.D[r][If];
+        m_old = b.mask[r][If];
+    }
+    if (threadIdx.x < 64) {
+        const Pick pk0 = cd_pick_wave(b, r, sr, cp, k);
+        if (threadIdx.x == 0) spk = pk0;
+    }
+    __syncthreads();
+    const Pick pk = spk;
+    if (pk.status != PICK_GO) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->k = k;
+            st->dmax = pk.mx;
+            st->status = pk.status;
+            st->done = 1;
+        }
+        return;
+    }
+    const int64_t p = pk.p;
+    const double sq = sqrt(pk.dp);
+    if (threadIdx.x == 0) sslot = -1;
+    __syncthreads();
+    if (bsteps > 0 && threadIdx.x < st->ncand && cand[threadIdx.x] == p) sslot = threadIdx.x;
+    __syncthreads();
+    const int slot = sslot;
+    double acc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[v] = 0.0;
+    if (slot >= 0) {
+        // hit: subtract the vectors made since the block start (prefetched first)
+        for (int64_t c0 = k0; c0 < k; c0 += CD_PCHUNK) {
+            const int nj = (int)min((int64_t)CD_PCHUNK, k - c0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < nj; t += CD_NT) sp[t] = L[(c0 + t) * ldl + p];
+            __syncthreads();
+            if (rows_ok) {
+                int j = jg;
+                if (c0 == k0) {
+#pragma unroll
+                    for (int m = 0; m < NPF; ++m, j += JG)
+                        if (j < nj)
+#pragma unroll
+                            for (int v = 0; v < VW; ++v) acc[v] = fma(pf[m][v], sp[j], acc[v]);
+                }
+                for (; j < nj; j += JG) {
+                    const double *Lp = L + (c0 + j) * ldl + I0;
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) acc[v] = fma(Lp[v], sp[j], acc[v]);
+                }
+            }
+        }
+    } else {
+        // miss (or no look-ahead): subtract all earlier vectors
+        for (int64_t c0 = 0; c0 < k; c0 += CD_PCHUNK) {
+            const int nj = (int)min((int64_t)CD_PCHUNK, k - c0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < nj; t += CD_NT) sp[t] = L[(c0 + t) * ldl + p];
+            __syncthreads();
+            if (rows_ok) {
+                const double *Lp = L + c0 * ldl + I0;
+                int j = jg;
+                if constexpr (VW == 2) {
+                    double b0 = 0.0, b1 = 0.0;
+                    for (; j + 3 * JG < nj; j += 4 * JG) {
+                        double2 v0 = *reinterpret_cast<const double2 *>(Lp + (int64_t)j * ldl);
+                        double2 v1 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + JG) * ldl);
+                        double2 v2 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + 2 * JG) * ldl);
+                        double2 v3 = *reinterpret_cast<const double2 *>(Lp + (int64_t)(j + 3 * JG) * ldl);
+                        acc[0] = fma(v0.x, sp[j], acc[0]);
+                        acc[1] = fma(v0.y, sp[j], acc[1]);
+                        b0 = fma(v1.x, sp[j + JG], b0);
+                        b1 = fma(v1.y, sp[j + JG], b1);
+                        acc[0] = fma(v2.x, sp[j + 2 * JG], acc[0]);
+                        acc[1] = fma(v2.y, sp[j + 2 * JG], acc[1]);
+                        b0 = fma(v3.x, sp[j + 3 * JG], b0);
+                        b1 = fma(v3.y, sp[j + 3 * JG], b1);
+                    }
+                    for (; j < nj; j += JG) {
+                        double2 v = *reinterpret_cast<const double2 *>(Lp + (int64_t)j * ldl);
+                        acc[0] = fma(v.x, sp[j], acc[0]);
+                        acc[1] = fma(v.y, sp[j], acc[1]);
+                    }
+                    acc[0] += b0;
+                    acc[1] += b1;
+                } else {
+                    double b0 = 0.0;
+                    for (; j + JG < nj; j += 2 * JG) {
+                        acc[0] = fma(Lp[(int64_t)j * ldl], sp[j], acc[0]);
+                        b0 = fma(Lp[(int64_t)(j + JG) * ldl], sp[j + JG], b0);
+                    }
+                    for (; j < nj; j += JG) acc[0] = fma(Lp[(int64_t)j * ldl], sp[j], acc[0]);
+                    acc[0] += b0;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < VW; ++v) red[jg][VW * rl + v] = acc[v];
+    __syncthreads();
+    const int w = 1 - r;
     double mx = -INFINITY, mn = INFINITY;
-    if (I < npairs) {
-        double l;
-        if (mask[I]) {
+    int64_t ix = INT64_MAX;
+    if (threadIdx.x < CD_TILE && If < cp.npairs) {
+        const int64_t I = If;
+        double l, dn;
+        unsigned char m = m_old;
+        if (m) {
             l = 0.0;                          // earlier pivot: exactly zero
+            dn = d_old;
         } else if (I == p) {
             l = sq;                           // the pivot's own entry
+            dn = 0.0;
+            m = 1;
         } else {
             double c;
-            if constexpr (DENSE) {
+            if (slot >= 0) {
+                c = R[(int64_t)slot * ldr + I];
+            } else if constexpr (DENSE) {
                 c = V[p * ldv + I];
             } else {
                 c = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[p], pt.Px[p],
                            pt.Py[p], pt.Pz[p], pt.K[p]);
             }
-            double acc = 0.0;
-            for (int s = 0; s < nsplit; ++s) acc += part[(int64_t)s * npad + I];
-            c -= acc;
+            double s = 0.0;
+#pragma unroll
+            for (int g = 0; g < JG; ++g) s += red[g][threadIdx.x];
+            c -= s;
             l = c / sq;
-            double d = D[I] - l * l;
-            D[I] = d;
-            mx = mn = d;
+            dn = d_old - l * l;
+            mx = mn = dn;
+            ix = I;
         }
         L[k * ldl + I] = l;
-        if (I == p) {
-            D[I] = 0.0;
-            mask[I] = 1;
-        }
+        b.D[w][I] = dn;
+        b.mask[w][I] = m;
     }
-    mx = block_max<CD_FIN_TILE>(mx, sh);
-    mn = block_min<CD_FIN_TILE>(mn, sh);
+    block_argmax<CD_NT>(mx, ix, shv, shi);
+    mn = block_min<CD_NT>(mn, shd);
     if (threadIdx.x == 0) {
-        tmax[blockIdx.x] = mx;
-        tmin[blockIdx.x] = mn;
+        b.tmax[w][blockIdx.x] = mx;
+        b.targ[w][blockIdx.x] = ix;
+        b.tmin[w][blockIdx.x] = mn;
+        const int64_t sidx = blockIdx.x / b.tps;
+        if (mx != -INFINITY) atomicMax(&b.smax[sw][sidx], okey(mx));
+        if (mn != INFINITY) atomicMin(&b.smin[sw][sidx], okey(mn));
+    }
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < CD_NSUP) {
+            b.smax[sz][threadIdx.x] = 0ull;
+            b.smin[sz][threadIdx.x] = ~0ull;
+        }
+        if (threadIdx.x == 0) {
+            piv[k] = p;
+            st->k = k + 1;
+            st->dmax = pk.mx;
+            if (bsteps > 0 && slot < 0) st->nmiss += 1;
+            st->bytes += 8.0 * (double)cp.npairs * (double)(k - (slot >= 0 ? k0 : 0)) + 42.0 * (double)cp.npairs;
+        }
     }
 }
 
-// termination tests and the next pivot (one block)
-__global__ __launch_bounds__(CD_SEL_BLOCK) void cd_select_kernel(
-    int after_step, int64_t ntiles, const double *__restrict__ tmax,
-    const double *__restrict__ tmin, const double *__restrict__ D,
-    const unsigned char *__restrict__ mask, int64_t npairs, double delta, double tau,
-    double psd_tol, int64_t max_vec, CdState *st, int64_t *__restrict__ piv)
+// Look-ahead block start (one block): candidates = this step's pivot, then the argmax rows
+// of the tiles whose largest residual diagonal is among the top CD_NCAND-1 (threshold from
+// a 4-pass radix select on the IEEE bits of the tile maxima; ties at the threshold resolved
+// by lowest tile index), in a deterministic order.
+__global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams cp, int r, int sr, int64_t k,
+                                                            CdState *st, int64_t *__restrict__ cand)
 {
-    __shared__ double shd[CD_SEL_BLOCK / 64];
-    __shared__ int64_t shi[CD_SEL_BLOCK / 64];
+    __shared__ int shs[CD_AUX_NT / 64 + 1];
+    __shared__ unsigned int hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_need;
+    __shared__ Pick spk;
     if (st->done) return;
-    int64_t k = st->k;
-    if (after_step) {
-        if (threadIdx.x == 0) piv[k] = st->p;
-        k += 1;
+    if (threadIdx.x < 64) {
+        const Pick pk0 = cd_pick_wave(b, r, sr, cp, k);
+        if (threadIdx.x == 0) spk = pk0;
     }
-    double mx = -INFINITY, mn = INFINITY;
-    for (int64_t t = threadIdx.x; t < ntiles; t += CD_SEL_BLOCK) {
-        mx = fmax(mx, tmax[t]);
-        mn = fmin(mn, tmin[t]);
+    __syncthreads();
+    const Pick pk = spk;
+    if (pk.status != PICK_GO) return;            // the step kernel records the termination
+    const int64_t p = pk.p;
+    const int want = CD_NCAND - 1;
+    const int64_t ntile = b.ntile;
+    const double *tmax = b.tmax[r];
+    const int64_t *targ = b.targ[r];
+    auto key = [&](int64_t t) -> unsigned long long {
+        double v = tmax[t];
+        if (!(v > 0.0) || targ[t] == p) return 0ull;
+        return (unsigned long long)__double_as_longlong(v);
+    };
+    if (threadIdx.x == 0) {
+        s_prefix = 0ull;
+        s_need = want;
     }
-    mx = block_max<CD_SEL_BLOCK>(mx, shd);
-    mn = block_min<CD_SEL_BLOCK>(mn, shd);
-    int status = -100;
-    if (mn < -psd_tol) status = CDS_CD_NOTPSD;
-    else if (mx == -INFINITY) status = CDS_CD_FULLRANK;
-    else if (mx <= delta) status = CDS_CD_CONVERGED;
-    else if (k >= max_vec) status = CDS_CD_CAP;
-    if (status != -100) {
-        if (threadIdx.x == 0) {
-            st->k = k;
-            st->dmax = mx;
-            st->status = status;
-            st->done = 1;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 56 - 8 * pass;
+        for (int q = threadIdx.x; q < 256; q += CD_AUX_NT) hist[q] = 0;
+        __syncthreads();
+        const unsigned long long prefix = s_prefix;
+        for (int64_t t = threadIdx.x; t < ntile; t += CD_AUX_NT) {
+            unsigned long long u = key(t);
+            if (u == 0ull) continue;
+            if (pass > 0 && (u >> (shift + 8)) != prefix) continue;
+            atomicAdd(&hist[(u >> shift) & 0xFF], 1u);
         }
-        return;
-    }
-    const double thresh = mx - tau;
-    int64_t ft = INT64_MAX;
-    for (int64_t t = threadIdx.x; t < ntiles; t += CD_SEL_BLOCK)
-        if (tmax[t] >= thresh && t < ft) ft = t;
-    ft = block_min_i64<CD_SEL_BLOCK>(ft, shi);
-    int64_t cand = INT64_MAX;
-    if (ft != INT64_MAX && threadIdx.x < CD_FIN_TILE) {
-        int64_t I = ft * CD_FIN_TILE + threadIdx.x;
-        if (I < npairs && !mask[I] && D[I] >= thresh) cand = I;
-    }
-    cand = block_min_i64<CD_SEL_BLOCK>(cand, shi);
-    if (cand == INT64_MAX) {
-        // no candidate although D_max > delta: only possible with non-finite residuals
+        __syncthreads();
         if (threadIdx.x == 0) {
-            st->k = k;
-            st->dmax = mx;
-            st->status = CDS_CD_NOTPSD;
-            st->done = 1;
+            int need = s_need, q = 255;
+            for (; q > 0; --q) {
+                if ((int)hist[q] >= need) break;
+                need -= hist[q];
+            }
+            s_prefix = (prefix << 8) | (unsigned long long)q;
+            s_need = need;
         }
-        return;
+        __syncthreads();
+    }
+    const unsigned long long thr = s_prefix;     // top 32 bits of the boundary key
+    const int64_t per = (ntile + CD_AUX_NT - 1) / CD_AUX_NT;
+    const int64_t t0 = threadIdx.x * per, t1 = min(ntile, t0 + per);
+    int na = 0, nbd = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        unsigned long long u = key(t);
+        if (u == 0ull) continue;
+        if ((u >> 32) > thr) ++na;
+        else if ((u >> 32) == thr) ++nbd;
+    }
+    int tot_a, tot_b;
+    int ia = block_excl_scan<CD_AUX_NT>(na, shs, &tot_a);
+    int ib = block_excl_scan<CD_AUX_NT>(nbd, shs, &tot_b);
+    const int nabove = min(tot_a, want);
+    for (int64_t t = t0; t < t1; ++t) {
+        unsigned long long u = key(t);
+        if (u == 0ull) continue;
+        if ((u >> 32) > thr) {
+            if (ia < want) cand[1 + ia] = targ[t];
+            ++ia;
+        } else if ((u >> 32) == thr) {
+            if (nabove + ib < want) cand[1 + nabove + ib] = targ[t];
+            ++ib;
+        }
     }
     if (threadIdx.x == 0) {
-        st->k = k;
-        st->p = cand;
-        st->dp = D[cand];
-        st->dmax = mx;
+        cand[0] = p;
+        st->ncand = 1 + min(nabove + tot_b, want);
+    }
+}
+
+// P[j][c] = L[j][cand_c], j < k0, c < ncand (one thread per entry)
+__global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
+                                 const int64_t *__restrict__ cand, double *__restrict__ P)
+{
+    if (st->done) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = e / CD_NCAND;
+    const int c = (int)(e % CD_NCAND);
+    if (j >= k0) return;
+    P[e] = c < st->ncand ? L[j * ldl + cand[c]] : 0.0;
+}
+
+// R[c][I] = V[I][cand_c] - sum_{j<k0} L[j][I] P[j][c] for all candidates, one read of L.
+// Block = 64 rows x 4 waves; wave w: rows [16w, 16w+16) x 64 candidates = 4 f64 MFMA blocks
+// (v_mfma_f64_16x16x4f64: A = L rows (lane l: row l%16, k l/16), B = P from LDS).
+template <bool DENSE>
+__global__ __launch_bounds__(256) void cd_pass_kernel(
+    PairTable pt, const double *__restrict__ V, int64_t ldv, const double *__restrict__ L, int64_t ldl,
+    int64_t npairs, int64_t k0, const CdState *__restrict__ st, const int64_t *__restrict__ cand,
+    const double *__restrict__ P, double *__restrict__ R, int64_t ldr)
+{
+    __shared__ double sp[CD_PASS_JC][CD_NCAND];
+    if (st->done) return;
+    const int nc = st->ncand;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+    const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
+    const int64_t rowA = tile0 + 16 * w + r16;
+    const bool rowok = rowA < npairs;
+    doublex4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t j0 = 0; j0 < k0; j0 += CD_PASS_JC) {
+        const int nj = (int)min((int64_t)CD_PASS_JC, k0 - j0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < CD_PASS_JC * CD_NCAND; t += 256) {
+            const int jj = t / CD_NCAND, cc = t % CD_NCAND;
+            sp[jj][cc] = jj < nj ? P[(j0 + jj) * CD_NCAND + cc] : 0.0;
+        }
+        __syncthreads();
+        double a[CD_PASS_JC / 4];
+#pragma unroll
+        for (int s = 0; s < CD_PASS_JC / 4; ++s) {
+            const int jj = 4 * s + g;
+            a[s] = (rowok && jj < nj) ? L[(j0 + jj) * ldl + rowA] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < CD_PASS_JC / 4; ++s)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sp[4 * s + g][16 * nb + r16], acc[nb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int c = 16 * nb + r16;
+        if (c >= nc) continue;
+        const int64_t q = cand[c];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t I = tile0 + 16 * w + g + 4 * e;     // f64 MFMA output rows g + 4e
+            if (I >= npairs) continue;
+            double base;
+            if constexpr (DENSE) {
+                base = V[q * ldv + I];
+            } else {
+                base = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[q], pt.Px[q], pt.Py[q],
+                              pt.Pz[q], pt.K[q]);
+            }
+            R[(int64_t)c * ldr + I] = base - acc[nb][e];
+        }
     }
 }
 
 __global__ void max_reduce_kernel(int64_t n, const double *__restrict__ x, double *__restrict__ out)
 {
-    __shared__ double sh[CD_SEL_BLOCK / 64];
+    __shared__ double sh[CD_AUX_NT / 64];
     double m = -INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += CD_SEL_BLOCK) m = fmax(m, x[i]);
-    m = block_max<CD_SEL_BLOCK>(m, sh);
+    for (int64_t i = threadIdx.x; i < n; i += CD_AUX_NT) m = fmax(m, x[i]);
+    m = block_max<CD_AUX_NT>(m, sh);
     if (threadIdx.x == 0) *out = m;
 }
 
@@ -387,6 +788,15 @@ int setup_pairs(cds_ctx *ctx, int32_t nbf, const double *centres, const double *
                        ctx->stream, nbf, centres, alpha, np, *pt);
     CDS_LAUNCHED(ctx);
     return CDS_OK;
+}
+
+template <int VW, bool DENSE>
+void launch_step(cds_ctx *ctx, dim3 grid, const CdBufs &b, const CdParams &cp, int r, int sr, int sw, int sz,
+                 int64_t k, int64_t k0, int bsteps, const PairTable &pt, const double *V, int64_t ldv, double *L,
+                 int64_t ldl, const double *R, int64_t ldr, const int64_t *cand, CdState *st, int64_t *piv)
+{
+    hipLaunchKernelGGL((cd_step_kernel<VW, DENSE>), grid, dim3(CD_NT), 0, ctx->stream, b, cp, r, sr, sw, sz, k,
+                       k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
 }
 
 int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
@@ -410,46 +820,71 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     if (!dense) CDS_CALL(setup_pairs(ctx, nbf, centres, alpha, &pt));
 
     const int vw = (ldl % 2 == 0 && cds_aligned(L, 16)) ? 2 : 1;
-    const int64_t rows_per_block = (int64_t)CD_BLOCK * vw;
-    const int64_t ntile_part = cds_ceil_div(npairs, rows_per_block);
-    const int64_t npad = ntile_part * rows_per_block;
-    const int64_t ntile_fin = cds_ceil_div(npairs, CD_FIN_TILE);
-    const int64_t max_split = cds_ceil_div(max_vec, CD_JCHUNK);
+    const int bsteps = ctx->cd_lookahead;
+    const int64_t ntile = cds_ceil_div(npairs, CD_TILE);
+    const int64_t tps = cds_ceil_div(ntile, CD_NSUP);
+    const int64_t ldr = cds_ceil_div(npairs, 64) * 64;
 
+    // workspace: D copy, ERI diagonal, candidate rows P (max_vec x NCAND), residual columns R
     void *w_part, *w_tile, *w_mask, *w_state;
-    CDS_CALL(cds_ws(ctx, WS_CD_PART, (size_t)std::max<int64_t>(max_split, 1) * npad * 8 + npairs * 8,
-                    &w_part));
-    CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile_fin * 8 + 64, &w_tile));
-    CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)npairs, &w_mask));
-    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState), &w_state));
-    double *part = (double *)w_part;
-    double *tmax = (double *)w_tile, *tmin = tmax + ntile_fin;
-    double *dscratch = tmin + ntile_fin;       // one double: max diagonal
-    unsigned char *mask = (unsigned char *)w_mask;
+    const size_t nP = (size_t)max_vec * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
+    CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR) * 8 + 256, &w_part));
+    CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)6 * ntile * 8 + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
+    CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)2 * npairs, &w_mask));
+    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + 64, &w_state));
+    double *D1 = (double *)w_part;
+    double *diag = D1 + npairs;
+    double *Pc = diag + npairs;
+    double *Rc = Pc + (bsteps > 0 ? nP : 0);
+    CdBufs bf;
+    bf.D[0] = D;
+    bf.D[1] = D1;
+    bf.mask[0] = (unsigned char *)w_mask;
+    bf.mask[1] = bf.mask[0] + npairs;
+    double *tb = (double *)w_tile;
+    bf.tmax[0] = tb;
+    bf.tmax[1] = tb + ntile;
+    bf.tmin[0] = tb + 2 * ntile;
+    bf.tmin[1] = tb + 3 * ntile;
+    bf.targ[0] = (int64_t *)(tb + 4 * ntile);
+    bf.targ[1] = (int64_t *)(tb + 5 * ntile);
+    unsigned long long *sb = (unsigned long long *)(tb + 6 * ntile);
+    for (int i = 0; i < 3; ++i) {
+        bf.smax[i] = sb + i * CD_NSUP;
+        bf.smin[i] = sb + (3 + i) * CD_NSUP;
+    }
+    bf.ntile = ntile;
+    bf.tps = tps;
+    double *dscratch = (double *)(sb + 6 * CD_NSUP);
     CdState *st = (CdState *)w_state;
+    int64_t *cand = (int64_t *)(st + 1);
 
     // largest ERI diagonal (for the default tie window / PSD tolerance)
-    double *diag = part + (size_t)std::max<int64_t>(max_split, 1) * npad;
     if (dense)
-        hipLaunchKernelGGL(dense_diag_kernel, dim3(nb), dim3(256), 0, ctx->stream, npairs, V, ldv,
-                           diag);
+        hipLaunchKernelGGL(dense_diag_kernel, dim3(nb), dim3(256), 0, ctx->stream, npairs, V, ldv, diag);
     else
         hipLaunchKernelGGL(eri_diag_kernel, dim3(nb), dim3(256), 0, ctx->stream, npairs, pt, diag);
     CDS_LAUNCHED(ctx);
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(CD_SEL_BLOCK), 0, ctx->stream, npairs,
-                       diag, dscratch);
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, npairs, diag, dscratch);
     CDS_LAUNCHED(ctx);
     void *hp;
     CDS_CALL(cds_pinned(ctx, 256, &hp));
     CDS_HIP(ctx, hipMemcpyAsync(hp, dscratch, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const double vmax = *(double *)hp;
-    if (tau < 0) tau = 1e-10 * vmax;
-    if (psd_tol < 0) psd_tol = 1e3 * DBL_EPSILON * vmax;
+    CdParams cp;
+    cp.npairs = npairs;
+    cp.max_vec = max_vec;
+    cp.delta = delta;
+    cp.tau = tau < 0 ? 1e-10 * vmax : tau;
+    cp.psd_tol = psd_tol < 0 ? 1e3 * DBL_EPSILON * vmax : psd_tol;
 
     CdsTimer tall;
     CDS_CALL(cds_timer_start(ctx, &tall));
-    CDS_HIP(ctx, hipMemsetAsync(mask, 0, (size_t)npairs, ctx->stream));
+    CDS_HIP(ctx, hipMemsetAsync(bf.mask[0], 0, (size_t)npairs, ctx->stream));
+    // super-tile buffers 0 and 1 start empty (2 is reset by the first step)
+    CDS_HIP(ctx, hipMemsetAsync(bf.smax[0], 0, (size_t)3 * CD_NSUP * 8, ctx->stream));
+    CDS_HIP(ctx, hipMemsetAsync(bf.smin[0], 0xff, (size_t)3 * CD_NSUP * 8, ctx->stream));
     CdState st0 = {};
     st0.k = nvec_in;
     *(CdState *)hp = st0;
@@ -458,19 +893,16 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         CDS_HIP(ctx, hipMemcpyAsync(D, diag, (size_t)npairs * 8, hipMemcpyDeviceToDevice, ctx->stream));
     } else {
         hipLaunchKernelGGL(mark_pivots_kernel, dim3((unsigned)cds_ceil_div(nvec_in, 256)), dim3(256),
-                           0, ctx->stream, nvec_in, piv, npairs, mask);
+                           0, ctx->stream, nvec_in, piv, npairs, bf.mask[0]);
         CDS_LAUNCHED(ctx);
     }
-    hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)ntile_fin), dim3(CD_FIN_TILE), 0, ctx->stream,
-                       npairs, D, mask, tmax, tmin);
-    CDS_LAUNCHED(ctx);
-    hipLaunchKernelGGL(cd_select_kernel, dim3(1), dim3(CD_SEL_BLOCK), 0, ctx->stream, 0, ntile_fin,
-                       tmax, tmin, D, mask, npairs, delta, tau, psd_tol, max_vec, st, piv);
+    hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)ntile), dim3(CD_TILE), 0, ctx->stream, bf, npairs);
     CDS_LAUNCHED(ctx);
 
-    int64_t k = nvec_in;
+    int64_t k = nvec_in, k0 = nvec_in;
     int batch = 8;
     CdState hs = {};
+    const dim3 grid((unsigned)ntile);
     for (;;) {
         CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
         CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -479,42 +911,73 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         if (hs.k != k)
             return cds_fail(ctx, CDS_EDEVICE, "CD state out of step (device k=%lld host k=%lld)",
                             (long long)hs.k, (long long)k);
-        for (int b = 0; b < batch && k < max_vec; ++b, ++k) {
-            const int nsplit = (int)cds_ceil_div(k, CD_JCHUNK);
-            if (nsplit > 0) {
-                CdsTimer tk;
-                if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tk));
-                dim3 grid((unsigned)ntile_part, (unsigned)nsplit);
-                if (vw == 2)
-                    hipLaunchKernelGGL(cd_partial_kernel<2>, grid, dim3(CD_BLOCK), 0, ctx->stream, L,
-                                       ldl, npairs, npad, st, part);
-                else
-                    hipLaunchKernelGGL(cd_partial_kernel<1>, grid, dim3(CD_BLOCK), 0, ctx->stream, L,
-                                       ldl, npairs, npad, st, part);
+        if (k > max_vec)
+            return cds_fail(ctx, CDS_EDEVICE, "CD did not terminate at max_vec=%lld", (long long)max_vec);
+        // steps k <= max_vec: the step at k == max_vec only records the termination (CAP or
+        // convergence) and writes no vector
+        for (int bi = 0; bi < batch && k <= max_vec; ++bi, ++k) {
+            const int64_t s = k - nvec_in;
+            const int r = (int)(s & 1), sr = (int)(s % 3), sw = (int)((s + 1) % 3), sz = (int)((s + 2) % 3);
+            if (bsteps > 0 && s % bsteps == 0 && k < max_vec) {
+                // look-ahead block start: candidates, their rows, one pass over L
+                k0 = k;
+                hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
+                                   st, cand);
                 CDS_LAUNCHED(ctx);
-                if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
+                if (k > 0) {
+                    hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div(k * CD_NCAND, 256)), dim3(256),
+                                       0, ctx->stream, (const double *)L, ldl, k, (const CdState *)st,
+                                       (const int64_t *)cand, Pc);
+                    CDS_LAUNCHED(ctx);
+                }
+                CdsTimer tp;
+                if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
+                if (dense)
+                    hipLaunchKernelGGL(cd_pass_kernel<true>, grid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                                       (const double *)L, ldl, npairs, k, (const CdState *)st,
+                                       (const int64_t *)cand, (const double *)Pc, Rc, ldr);
+                else
+                    hipLaunchKernelGGL(cd_pass_kernel<false>, grid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                                       (const double *)L, ldl, npairs, k, (const CdState *)st,
+                                       (const int64_t *)cand, (const double *)Pc, Rc, ldr);
+                CDS_LAUNCHED(ctx);
+                if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
+                ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)k + 8.0 * CD_NCAND * (double)npairs;
+                ctx->stats.flops_cd_pass += 2.0 * (double)npairs * (double)k * CD_NCAND;
+                ctx->stats.n_cd_pass += 1;
             }
-            if (dense)
-                hipLaunchKernelGGL(cd_finalize_kernel<true>, dim3((unsigned)ntile_fin),
-                                   dim3(CD_FIN_TILE), 0, ctx->stream, pt, V, ldv, L, ldl, npairs, npad,
-                                   part, nsplit, D, mask, st, tmax, tmin);
-            else
-                hipLaunchKernelGGL(cd_finalize_kernel<false>, dim3((unsigned)ntile_fin),
-                                   dim3(CD_FIN_TILE), 0, ctx->stream, pt, V, ldv, L, ldl, npairs, npad,
-                                   part, nsplit, D, mask, st, tmax, tmin);
+            CdsTimer tk;
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tk));
+            if (dense) {
+                if (vw == 2)
+                    launch_step<2, true>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
+                                         ldr, cand, st, piv);
+                else
+                    launch_step<1, true>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
+                                         ldr, cand, st, piv);
+            } else {
+                if (vw == 2)
+                    launch_step<2, false>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
+                                          ldr, cand, st, piv);
+                else
+                    launch_step<1, false>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
+                                          ldr, cand, st, piv);
+            }
             CDS_LAUNCHED(ctx);
-            hipLaunchKernelGGL(cd_select_kernel, dim3(1), dim3(CD_SEL_BLOCK), 0, ctx->stream, 1,
-                               ntile_fin, tmax, tmin, D, mask, npairs, delta, tau, psd_tol, max_vec,
-                               st, piv);
-            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
         }
         if (batch < 64) batch *= 2;
     }
+    // the residual diagonal of the final state lives in the buffer of parity (k - nvec_in)
+    if ((hs.k - nvec_in) & 1)
+        CDS_HIP(ctx, hipMemcpyAsync(D, D1, (size_t)npairs * 8, hipMemcpyDeviceToDevice, ctx->stream));
     CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_cd_ms));
-    // algorithmic bytes of the steps made: L read (8 npairs k) + column/D/pair traffic
+    // algorithmic bytes of the steps made (plain left-looking count): 8 npairs k + 64 npairs
     for (int64_t j = nvec_in; j < hs.k; ++j)
         ctx->stats.bytes_cd += 8.0 * (double)npairs * (double)j + 64.0 * (double)npairs;
     ctx->stats.n_cd_steps += hs.k - nvec_in;
+    ctx->stats.n_cd_miss += hs.nmiss;
+    ctx->stats.bytes_cd_step += hs.bytes;
     CDS_CALL(cds_timers_flush(ctx));
     *h_nvec = hs.k;
     *h_dmax = hs.dmax;
@@ -523,7 +986,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         return cds_fail(ctx, CDS_ECAP, "max_vec=%lld reached with D_max=%g > delta=%g",
                         (long long)max_vec, hs.dmax, delta);
     if (hs.status == CDS_CD_NOTPSD)
-        return cds_fail(ctx, CDS_ENOTPSD, "residual diagonal below -%g", psd_tol);
+        return cds_fail(ctx, CDS_ENOTPSD, "residual diagonal below -%g", cp.psd_tol);
     return CDS_OK;
 }
 
@@ -566,6 +1029,15 @@ int cds_cholesky_dense(cds_ctx *ctx, int64_t npairs, const double *V, int64_t ld
 {
     return cholesky_impl(ctx, true, 0, nullptr, nullptr, npairs, V, ldv, delta, tau, psd_tol,
                          max_vec, L, ldl, piv, D, nvec_in, h_nvec, h_dmax, h_status);
+}
+
+int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (block_steps < 0 || block_steps > 256)
+        return cds_fail(ctx, CDS_EINVAL, "block_steps must be in [0, 256]");
+    ctx->cd_lookahead = block_steps;
+    return CDS_OK;
 }
 
 int cds_set_kernel_timing(cds_ctx *ctx, int32_t on)

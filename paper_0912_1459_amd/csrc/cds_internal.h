@@ -54,7 +54,8 @@ struct cds_ctx {
     std::vector<CdsTimer> pending;   // recorded event pairs not yet accumulated
     std::vector<hipEvent_t> free_events;
     bool broken = false;
-    bool kernel_timing = false;      // time every CD partial-GEMV launch with events
+    bool kernel_timing = false;      // time every CD step / pass launch with events
+    int cd_lookahead = 16;           // Cholesky look-ahead block length (0: plain steps)
 };
 
 // error helpers -------------------------------------------------------------

@@ -78,9 +78,144 @@ __device__ __forceinline__ void flush_partials(double (*acc)[2], int T, double *
         }
 }
 
-// part A: block (a = blockIdx.x, s = blockIdx.y), elements (i, j), d = w + e_a - e_i - e_j
-template <typename GT, int MODE>
-__global__ __launch_bounds__(EP_NT) void part_a_kernel(EpArgs e)
+// ---------------------------------------------------------------------------
+// Pair-symmetrised epilogues.  Both exchange partners of Eq. (SE) share one
+// denominator (d is symmetric in i, j and in a, b), so each unordered pair
+// contributes R/d with R = U_uv + U_vu = 2(g_uv^2 + g_vu^2 - g_uv g_vu) (u != v)
+// or R = g_uu^2.  SIGMA mode accumulates sum_t R/d_t and -R/d_t^2 for TT trial
+// energies; RESIDUE mode stores R once (residue layout: part A [a][j(j+1)/2+i],
+// part B [a][(b-a)*nocc + i], b >= a).
+// ---------------------------------------------------------------------------
+
+// part A (2h1p), block (a = blockIdx.x, s = blockIdx.y): X^a[i][j] = G[s][i][a*nocc + j].
+// 32 x 32 tile pairs (IB <= JB) of X^a and its transpose are staged in LDS so both
+// partners are read with coalesced loads.  d = w + e_a - e_i - e_j.
+template <typename GT, int MODE, int TT>
+__global__ __launch_bounds__(EP_NT) void pair_a_kernel(EpArgs e)
+{
+    __shared__ double sh[EP_NT / 64];
+    __shared__ double eo[1024];
+    __shared__ double t1[32][33], t2[32][33];
+    const int a = blockIdx.x, s = blockIdx.y, nocc = e.nocc;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
+    const double ea = e.eps[nocc + a];
+    const int64_t gbase = (int64_t)s * e.nmo * e.nvo + (int64_t)a * nocc;   // + i*nvo + j
+    double acc[TT > 0 ? TT : 1][2];
+    double w[TT > 0 ? TT : 1];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+        acc[t][0] = acc[t][1] = 0.0;
+        w[t] = e.omega[s * e.T + (t < e.T ? t : e.T - 1)];
+    }
+    const int nb = (nocc + 31) / 32;
+    for (int IB = 0; IB < nb; ++IB)
+        for (int JB = IB; JB < nb; ++JB) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < 1024; q += EP_NT) {
+                const int r = q >> 5, c = q & 31;
+                const int i1 = IB * 32 + r, j1 = JB * 32 + c;   // t1[r][c] = X[i1][j1]
+                const int i2 = JB * 32 + r, j2 = IB * 32 + c;   // t2[r][c] = X[i2][j2]
+                t1[r][c] = (i1 < nocc && j1 < nocc) ? ld<GT>(e.G, gbase + (int64_t)i1 * e.nvo + j1) : 0.0;
+                t2[r][c] = (i2 < nocc && j2 < nocc) ? ld<GT>(e.G, gbase + (int64_t)i2 * e.nvo + j2) : 0.0;
+            }
+            __syncthreads();
+            for (int q = threadIdx.x; q < 1024; q += EP_NT) {
+                const int r = q >> 5, c = q & 31;
+                const int i = IB * 32 + r, j = JB * 32 + c;
+                if (i >= nocc || j >= nocc || (IB == JB && r > c)) continue;
+                const double x = t1[r][c], xt = t2[c][r];
+                const double R = (i == j) ? x * x : 2.0 * (x * x + xt * xt - x * xt);
+                if constexpr (MODE == EP_SIGMA) {
+                    const double dd = ea - eo[i] - eo[j];
+#pragma unroll
+                    for (int t = 0; t < TT; ++t) {
+                        const double id = 1.0 / (w[t] + dd);
+                        const double ri = R * id;
+                        acc[t][0] += ri;
+                        acc[t][1] -= ri * id;
+                    }
+                } else {
+                    const int64_t pp = (int64_t)j * (j + 1) / 2 + i;
+                    ((GT *)e.R)[(int64_t)s * e.nres + (int64_t)a * (nocc * (nocc + 1) / 2) + pp] = (GT)R;
+                }
+            }
+        }
+    if constexpr (MODE == EP_SIGMA) {
+        double *dst = e.part + (((int64_t)s * (e.nblkA + e.nblkB) + a) * e.T) * 2;
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double v = block_sum<EP_NT>(acc[t][c], sh);
+                if (threadIdx.x == 0 && t < e.T) dst[t * 2 + c] = v;
+            }
+    }
+}
+
+// part B (2p1h): y_{i;ab} = G[s][nocc+a][b*nocc+i], partner y_{i;ba} = G[s][nocc+b][a*nocc+i];
+// d = w + e_i - e_a - e_b.  Block blk handles a = blk and a = nvirt-1-blk over b >= a
+// (equal work per block); both partners are contiguous in i.
+template <typename GT, int MODE, int TT>
+__global__ __launch_bounds__(EP_NT) void pair_b_kernel(EpArgs e)
+{
+    __shared__ double sh[EP_NT / 64];
+    __shared__ double eo[1024];
+    const int s = blockIdx.y, nocc = e.nocc, nvirt = e.nvirt, blk = blockIdx.x;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
+    __syncthreads();
+    const double *ev = e.eps + nocc;
+    const int64_t gs0 = (int64_t)s * e.nmo * e.nvo;
+    double acc[TT > 0 ? TT : 1][2];
+    double w[TT > 0 ? TT : 1];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+        acc[t][0] = acc[t][1] = 0.0;
+        w[t] = e.omega[s * e.T + (t < e.T ? t : e.T - 1)];
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const int a = pass == 0 ? blk : nvirt - 1 - blk;
+        if (pass == 1 && a == blk) break;
+        const double ea = ev[a];
+        const int64_t base_a = gs0 + (int64_t)(nocc + a) * e.nvo;
+        const int64_t nitem = (int64_t)(nvirt - a) * nocc;
+        const int64_t roff = (int64_t)s * e.nres + e.offB +
+                             (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
+        for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
+            const int bo = (int)(q / nocc), i = (int)(q - (int64_t)bo * nocc);
+            const int b = a + bo;
+            const double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
+            const double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
+            const double R = (bo == 0) ? y * y : 2.0 * (y * y + yt * yt - y * yt);
+            if constexpr (MODE == EP_SIGMA) {
+                const double dd = eo[i] - ea - ev[b];
+#pragma unroll
+                for (int t = 0; t < TT; ++t) {
+                    const double id = 1.0 / (w[t] + dd);
+                    const double ri = R * id;
+                    acc[t][0] += ri;
+                    acc[t][1] -= ri * id;
+                }
+            } else {
+                ((GT *)e.R)[roff + q] = (GT)R;
+            }
+        }
+    }
+    if constexpr (MODE == EP_SIGMA) {
+        double *dst = e.part + (((int64_t)s * (e.nblkA + e.nblkB) + e.nblkA + blk) * e.T) * 2;
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double v = block_sum<EP_NT>(acc[t][c], sh);
+                if (threadIdx.x == 0 && t < e.T) dst[t * 2 + c] = v;
+            }
+    }
+}
+
+// Gradient weights, part A (block per (a, s)): W = gscale (4 x_ij - 2 x_ji) / d for every
+// ordered element; thread i owns e-bar_i (row sums), the block sums e-bar_a.
+template <typename GT>
+__global__ __launch_bounds__(EP_NT) void grad_a_kernel(EpArgs e)
 {
     __shared__ double sh[EP_NT / 64];
     __shared__ double eo[1024];
@@ -88,167 +223,84 @@ __global__ __launch_bounds__(EP_NT) void part_a_kernel(EpArgs e)
     for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
     __syncthreads();
     const double ea = e.eps[nocc + a];
-    const int64_t gbase = (int64_t)s * e.nmo * e.nvo + (int64_t)a * nocc;   // + i*nvo + j
-    double acc[TMAX][2];
-    double w[TMAX];
-    const int T = (MODE == EP_SIGMA || MODE == EP_GRAD) ? e.T : 0;
-    for (int t = 0; t < T; ++t) {
-        acc[t][0] = acc[t][1] = 0.0;
-        w[t] = e.omega[s * e.T + t];
-    }
-    if constexpr (MODE == EP_GRAD) {
-        // thread i owns e-bar_i (row sums); block sums e-bar_a
-        const double gs = e.gscale[s];
-        double sa = 0.0;
-        for (int i = threadIdx.x; i < nocc; i += EP_NT) {
-            double si = 0.0;
-            for (int j = 0; j < nocc; ++j) {
-                double x = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
-                double xt = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
-                double d = w[0] + ea - eo[i] - eo[j];
-                double u = (2.0 * x - xt) * x, ut = (2.0 * xt - x) * xt;
-                double id = 1.0 / d;
-                ((GT *)e.W)[gbase + (int64_t)i * e.nvo + j] = (GT)(gs * (4.0 * x - 2.0 * xt) * id);
-                si += (u + ut) * id * id;     // d symmetric in (i, j)
-                sa -= u * id * id;
-            }
-            e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + i] = gs * si;
+    const int64_t gbase = (int64_t)s * e.nmo * e.nvo + (int64_t)a * nocc;
+    const double w0 = e.omega[s];
+    const double gs = e.gscale[s];
+    double sa = 0.0;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) {
+        double si = 0.0;
+        for (int j = 0; j < nocc; ++j) {
+            double x = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
+            double xt = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
+            double d = w0 + ea - eo[i] - eo[j];
+            double u = (2.0 * x - xt) * x, ut = (2.0 * xt - x) * xt;
+            double id = 1.0 / d;
+            ((GT *)e.W)[gbase + (int64_t)i * e.nvo + j] = (GT)(gs * (4.0 * x - 2.0 * xt) * id);
+            si += (u + ut) * id * id;     // d symmetric in (i, j)
+            sa -= u * id * id;
         }
-        sa = block_sum<EP_NT>(sa, sh);
-        if (threadIdx.x == 0) e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + nocc] = gs * sa;
-        return;
+        e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + i] = gs * si;
     }
-    const int64_t nij = (int64_t)nocc * nocc;
-    for (int64_t q = threadIdx.x; q < nij; q += EP_NT) {
-        const int i = (int)(q / nocc), j = (int)(q - (int64_t)i * nocc);
-        if (MODE == EP_RESIDUE && i > j) continue;
-        double x = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
-        double xt = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
-        if constexpr (MODE == EP_SIGMA) {
-            double u = (2.0 * x - xt) * x;
-            double dd = ea - eo[i] - eo[j];
-            for (int t = 0; t < T; ++t) {
-                double id = 1.0 / (w[t] + dd);
-                double ui = u * id;
-                acc[t][0] += ui;
-                acc[t][1] -= ui * id;
-            }
-        } else {
-            double r = (i == j) ? x * x : 2.0 * (x * x + xt * xt - x * xt);
-            int64_t p = (int64_t)j * (j + 1) / 2 + i;     // packed (i <= j)
-            ((GT *)e.R)[(int64_t)s * e.nres + (int64_t)a * (nocc * (nocc + 1) / 2) + p] = (GT)r;
-        }
-    }
-    if constexpr (MODE == EP_SIGMA)
-        flush_partials<EP_NT>(acc, T, e.part + (((int64_t)s * (e.nblkA + e.nblkB) + a) * e.T) * 2, sh);
+    sa = block_sum<EP_NT>(sa, sh);
+    if (threadIdx.x == 0) e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + nocc] = gs * sa;
 }
 
-// part B: y_{i;ab} = G[s][nocc+a][b*nocc+i], partner y_{i;ba} = G[s][nocc+b][a*nocc+i],
-// d = w + e_i - e_a - e_b.  SIGMA / GRAD: block per (s, a) over all (b, i).
-// RESIDUE: block blk handles a = blk and a = nvirt-1-blk over b >= a (balanced).
-template <typename GT, int MODE>
-__global__ __launch_bounds__(EP_NT) void part_b_kernel(EpArgs e)
+// Gradient weights, part B (block per (a, s)) over all (b, i); per-i sums are owned by
+// fixed threads (i = tid % nocc) and combined in a fixed order.
+template <typename GT>
+__global__ __launch_bounds__(EP_NT) void grad_b_kernel(EpArgs e)
 {
     __shared__ double sh[EP_NT / 64];
     __shared__ double eo[1024];
     __shared__ double acc_i[1024];
-    const int s = blockIdx.y, nocc = e.nocc, nvirt = e.nvirt;
-    for (int i = threadIdx.x; i < nocc; i += EP_NT) eo[i] = e.eps[i];
+    const int s = blockIdx.y, nocc = e.nocc, nvirt = e.nvirt, a = blockIdx.x;
+    for (int i = threadIdx.x; i < nocc; i += EP_NT) {
+        eo[i] = e.eps[i];
+        acc_i[i] = 0.0;
+    }
     __syncthreads();
     const double *ev = e.eps + nocc;
     const int64_t gs0 = (int64_t)s * e.nmo * e.nvo;
-    double acc[TMAX][2];
-    double w[TMAX];
-    const int T = (MODE == EP_SIGMA || MODE == EP_GRAD) ? e.T : 0;
-    for (int t = 0; t < T; ++t) {
-        acc[t][0] = acc[t][1] = 0.0;
-        w[t] = e.omega[s * e.T + t];
-    }
-    if constexpr (MODE == EP_RESIDUE) {
-        const int blk = blockIdx.x;
-        for (int pass = 0; pass < 2; ++pass) {
-            const int a = pass == 0 ? blk : nvirt - 1 - blk;
-            if (pass == 1 && a == blk) break;
-            const int64_t base_a = gs0 + (int64_t)(nocc + a) * e.nvo;
-            const int64_t nitem = (int64_t)(nvirt - a) * nocc;
-            const int64_t roff = (int64_t)s * e.nres + e.offB +
-                                 (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
-            for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
-                const int b = a + (int)(q / nocc), i = (int)(q - (int64_t)(b - a) * nocc);
-                double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
-                double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
-                double r = (a == b) ? y * y : 2.0 * (y * y + yt * yt - y * yt);
-                ((GT *)e.R)[roff + q] = (GT)r;
-            }
-        }
-        return;
-    }
-    const int a = blockIdx.x;
     const double ea = ev[a];
     const int64_t base_a = gs0 + (int64_t)(nocc + a) * e.nvo;
-    const int64_t nitem = (int64_t)nvirt * nocc;
-    if constexpr (MODE == EP_GRAD) {
-        const double gsc = e.gscale[s];
-        for (int i = threadIdx.x; i < nocc; i += EP_NT) acc_i[i] = 0.0;
-        __syncthreads();
-        // threads own fixed i (i = tid % nocc) so that per-i sums are deterministic
-        const int per = EP_NT / nocc > 0 ? EP_NT / nocc : 1;
-        const int i0 = threadIdx.x % nocc, bsub = threadIdx.x / nocc;
-        double sa = 0.0, si = 0.0;
-        if (bsub < per) {
-            for (int i = i0; i < nocc; i += (nocc > EP_NT ? EP_NT : nocc)) {
-                double sii = 0.0;
-                for (int b = bsub; b < nvirt; b += per) {
-                    double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
-                    double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
-                    double d = w[0] + eo[i] - ea - ev[b];
-                    double id = 1.0 / d;
-                    double u = (2.0 * y - yt) * y, ut = (2.0 * yt - y) * yt;
-                    ((GT *)e.W)[base_a + (int64_t)b * nocc + i] = (GT)(gsc * (4.0 * y - 2.0 * yt) * id);
-                    sii -= u * id * id;           // role i of element (a, b, i)
-                    sa += (u + ut) * id * id;     // roles a of (a,b,i) and b of (b,a,i)
-                }
-                if (nocc > EP_NT) {
-                    si = sii;
-                    e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + i] = gsc * si;
-                } else {
-                    si = sii;
-                }
+    const double gsc = e.gscale[s];
+    const double w0 = e.omega[s];
+    const int per = EP_NT / nocc > 0 ? EP_NT / nocc : 1;
+    const int i0 = threadIdx.x % nocc, bsub = threadIdx.x / nocc;
+    double sa = 0.0, si = 0.0;
+    if (bsub < per) {
+        for (int i = i0; i < nocc; i += (nocc > EP_NT ? EP_NT : nocc)) {
+            double sii = 0.0;
+            for (int b = bsub; b < nvirt; b += per) {
+                double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
+                double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
+                double d = w0 + eo[i] - ea - ev[b];
+                double id = 1.0 / d;
+                double u = (2.0 * y - yt) * y, ut = (2.0 * yt - y) * yt;
+                ((GT *)e.W)[base_a + (int64_t)b * nocc + i] = (GT)(gsc * (4.0 * y - 2.0 * yt) * id);
+                sii -= u * id * id;           // role i of element (a, b, i)
+                sa += (u + ut) * id * id;     // roles a of (a,b,i) and b of (b,a,i)
             }
+            si = sii;
+            if (nocc > EP_NT) e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + i] = gsc * si;
         }
-        if (nocc <= EP_NT) {
-            // combine the `per` threads sharing each i in fixed order
-            for (int k = 0; k < per; ++k) {
-                __syncthreads();
-                if (bsub == k && bsub < per) acc_i[i0] += si;
-            }
+    }
+    if (nocc <= EP_NT) {
+        for (int k = 0; k < per; ++k) {
             __syncthreads();
-            for (int i = threadIdx.x; i < nocc; i += EP_NT)
-                e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + i] = gsc * acc_i[i];
+            if (bsub == k && bsub < per) acc_i[i0] += si;
         }
-        sa = block_sum<EP_NT>(sa, sh);
-        if (threadIdx.x == 0) e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + nocc] = gsc * sa;
-        return;
+        __syncthreads();
+        for (int i = threadIdx.x; i < nocc; i += EP_NT)
+            e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + i] = gsc * acc_i[i];
     }
-    for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
-        const int b = (int)(q / nocc), i = (int)(q - (int64_t)b * nocc);
-        double y = ld<GT>(e.G, base_a + q);
-        double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
-        double u = (2.0 * y - yt) * y;
-        double dd = eo[i] - ea - ev[b];
-        for (int t = 0; t < T; ++t) {
-            double id = 1.0 / (w[t] + dd);
-            double ui = u * id;
-            acc[t][0] += ui;
-            acc[t][1] -= ui * id;
-        }
-    }
-    flush_partials<EP_NT>(acc, T, e.part + (((int64_t)s * (e.nblkA + e.nblkB) + e.nblkA + a) * e.T) * 2, sh);
+    sa = block_sum<EP_NT>(sa, sh);
+    if (threadIdx.x == 0) e.epsB[((int64_t)s * nvirt + a) * (nocc + 1) + nocc] = gsc * sa;
 }
 
-// Newton sweep over stored residues: Sigma(w) = sum R / (w - pole), one trial per target.
-// Blocks [0, nvirt) handle part A of a = blockIdx.x; blocks [nvirt, nvirt + ceil(nvirt/2))
-// handle the balanced part-B pairs.
+// Newton sweep over stored residues: Sigma(w) = sum R / (w - pole), one energy per target.
+// Blocks [0, nvirt) sum part A of a = blockIdx.x; blocks [nvirt, nvirt + ceil(nvirt/2)) the
+// balanced part-B pairs, in the residue layout written above.
 template <typename RT>
 __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__restrict__ active)
 {
@@ -260,22 +312,23 @@ __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__res
     const double *ev = e.eps + nocc;
     const double w = e.omega[s];
     const RT *R = (const RT *)e.R + (int64_t)s * e.nres;
-    double acc[1][2] = {{0.0, 0.0}};
+    double s0 = 0.0, s1 = 0.0;
     const int blk = blockIdx.x;
     if (blk < nvirt) {
         const int a = blk;
-        const int64_t npair = (int64_t)nocc * (nocc + 1) / 2;
+        const int npair = nocc * (nocc + 1) / 2;
         const RT *Ra = R + (int64_t)a * npair;
         const double ea = ev[a];
-        for (int64_t p = threadIdx.x; p < npair; p += EP_NT) {
-            int64_t j = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+        for (int p = threadIdx.x; p < npair; p += EP_NT) {
+            // p = j(j+1)/2 + i, i <= j (float square root, then exact integer correction)
+            int j = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
             if (j * (j + 1) / 2 > p) --j;
             if ((j + 1) * (j + 2) / 2 <= p) ++j;
-            const int64_t i = p - j * (j + 1) / 2;
-            double id = 1.0 / (w + ea - eo[i] - eo[j]);
-            double ri = (double)Ra[p] * id;
-            acc[0][0] += ri;
-            acc[0][1] -= ri * id;
+            const int i = p - j * (j + 1) / 2;
+            const double id = 1.0 / (w + ea - eo[i] - eo[j]);
+            const double ri = (double)Ra[p] * id;
+            s0 += ri;
+            s1 -= ri * id;
         }
     } else {
         const int pb = blk - nvirt;
@@ -286,15 +339,21 @@ __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__res
             const RT *Rb = R + e.offB + (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
             const double ea = ev[a];
             for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
-                const int b = a + (int)(q / nocc), i = (int)(q - (int64_t)(b - a) * nocc);
-                double id = 1.0 / (w + eo[i] - ea - ev[b]);
-                double ri = (double)Rb[q] * id;
-                acc[0][0] += ri;
-                acc[0][1] -= ri * id;
+                const int bo = (int)(q / nocc), i = (int)(q - (int64_t)bo * nocc);
+                const double id = 1.0 / (w + eo[i] - ea - ev[a + bo]);
+                const double ri = (double)Rb[q] * id;
+                s0 += ri;
+                s1 -= ri * id;
             }
         }
     }
-    flush_partials<EP_NT>(acc, 1, e.part + ((int64_t)blockIdx.y * (e.nblkA + e.nblkB) + blk) * 2, sh);
+    s0 = block_sum<EP_NT>(s0, sh);
+    s1 = block_sum<EP_NT>(s1, sh);
+    if (threadIdx.x == 0) {
+        double *dst = e.part + ((int64_t)blockIdx.y * (e.nblkA + e.nblkB) + blk) * 2;
+        dst[0] = s0;
+        dst[1] = s1;
+    }
 }
 
 // out[s][t][c] = sum over blocks of part[s][blk][t][c] in block order
@@ -377,20 +436,44 @@ int contract_chunk(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const v
     return CDS_OK;
 }
 
+template <typename GT, int MODE, int TT>
+void launch_pairs(cds_ctx *ctx, const SigmaShape &sh, EpArgs &e)
+{
+    dim3 ga((unsigned)sh.nvirt, (unsigned)e.nsc);
+    dim3 gb((unsigned)((sh.nvirt + 1) / 2), (unsigned)e.nsc);
+    hipLaunchKernelGGL((pair_a_kernel<GT, MODE, TT>), ga, dim3(EP_NT), 0, ctx->stream, e);
+    hipLaunchKernelGGL((pair_b_kernel<GT, MODE, TT>), gb, dim3(EP_NT), 0, ctx->stream, e);
+}
+
+template <typename GT, int MODE>
+int launch_epilogue_t(cds_ctx *ctx, const SigmaShape &sh, EpArgs &e)
+{
+    if (MODE == EP_RESIDUE) launch_pairs<GT, EP_RESIDUE, 0>(ctx, sh, e);
+    else if (e.T <= 1) launch_pairs<GT, EP_SIGMA, 1>(ctx, sh, e);
+    else if (e.T <= 2) launch_pairs<GT, EP_SIGMA, 2>(ctx, sh, e);
+    else if (e.T <= 4) launch_pairs<GT, EP_SIGMA, 4>(ctx, sh, e);
+    else if (e.T <= 8) launch_pairs<GT, EP_SIGMA, 8>(ctx, sh, e);
+    else launch_pairs<GT, EP_SIGMA, 16>(ctx, sh, e);
+    CDS_LAUNCHED(ctx);
+    return CDS_OK;
+}
+
 template <int MODE>
 int launch_epilogue(cds_ctx *ctx, const SigmaShape &sh, EpArgs &e, bool fp64)
 {
-    dim3 ga((unsigned)sh.nvirt, (unsigned)e.nsc);
-    dim3 gb((unsigned)(MODE == EP_RESIDUE ? (sh.nvirt + 1) / 2 : sh.nvirt), (unsigned)e.nsc);
-    if (fp64) {
-        hipLaunchKernelGGL((part_a_kernel<double, MODE>), ga, dim3(EP_NT), 0, ctx->stream, e);
-        hipLaunchKernelGGL((part_b_kernel<double, MODE>), gb, dim3(EP_NT), 0, ctx->stream, e);
-    } else {
-        hipLaunchKernelGGL((part_a_kernel<float, MODE>), ga, dim3(EP_NT), 0, ctx->stream, e);
-        hipLaunchKernelGGL((part_b_kernel<float, MODE>), gb, dim3(EP_NT), 0, ctx->stream, e);
+    if (MODE == EP_GRAD) {
+        dim3 g((unsigned)sh.nvirt, (unsigned)e.nsc);
+        if (fp64) {
+            hipLaunchKernelGGL(grad_a_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e);
+            hipLaunchKernelGGL(grad_b_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e);
+        } else {
+            hipLaunchKernelGGL(grad_a_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e);
+            hipLaunchKernelGGL(grad_b_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e);
+        }
+        CDS_LAUNCHED(ctx);
+        return CDS_OK;
     }
-    CDS_LAUNCHED(ctx);
-    return CDS_OK;
+    return fp64 ? launch_epilogue_t<double, MODE>(ctx, sh, e) : launch_epilogue_t<float, MODE>(ctx, sh, e);
 }
 
 // Sigma, Sigma' for all targets at T energies each (device omega [nsel][T]) -> host out [nsel][T][2]
@@ -401,7 +484,7 @@ int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void 
     const size_t es = sh.prec == CDS_PREC_FP64 ? 8 : 4;
     void *G, *part, *out;
     CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * sh.nmo * sh.nvo * es, &G));
-    const int nblk = 2 * sh.nvirt;
+    const int nblk = sh.nvirt + (sh.nvirt + 1) / 2;
     CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)csz * nblk * T * 2 * 8, &part));
     CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)sh.nsel * T * 2 * 8, &out));
     for (int s0 = 0; s0 < sh.nsel; s0 += csz) {
@@ -419,7 +502,7 @@ int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void 
         e.T = T;
         e.part = (double *)part;
         e.nblkA = sh.nvirt;
-        e.nblkB = sh.nvirt;
+        e.nblkB = (sh.nvirt + 1) / 2;
         CdsTimer t;
         CDS_CALL(cds_timer_start(ctx, &t));
         CDS_CALL(launch_epilogue<EP_SIGMA>(ctx, sh, e, sh.prec == CDS_PREC_FP64));

@@ -77,18 +77,48 @@ def test_cd_on_demand(cds, name, delta):
     assert got.dmax <= delta
 
 
-def test_cd_resume_matches_direct(cds):
+@pytest.mark.parametrize("lookahead", [0, 16])
+def test_cd_resume_matches_direct(cds, lookahead):
     w = workload("small_cage")
-    log("cd resume small_cage")
+    log(f"cd resume small_cage lookahead={lookahead}")
     c, a = _dev(w.centres), _dev(w.alpha)
-    direct = cds.cholesky(1e-6, centres=c, alpha=a, max_vec=2000)
-    first = cds.cholesky(1e-4, centres=c, alpha=a, max_vec=2000)
+    ctx = cds.Context(0)
+    ctx.set_cd_lookahead(lookahead)
+    direct = cds.cholesky(1e-6, centres=c, alpha=a, max_vec=2000, ctx=ctx)
+    first = cds.cholesky(1e-4, centres=c, alpha=a, max_vec=2000, ctx=ctx)
     assert np.array_equal(first.piv[: first.nvec].cpu().numpy(), direct.piv[: first.nvec].cpu().numpy())
-    res = cds.cholesky(1e-6, centres=c, alpha=a, max_vec=2000, resume=first)
+    res = cds.cholesky(1e-6, centres=c, alpha=a, max_vec=2000, resume=first, ctx=ctx)
     assert res.nvec == direct.nvec
     assert torch.equal(res.piv[: res.nvec], direct.piv[: direct.nvec])
-    assert torch.equal(res.L, direct.L)
-    assert torch.equal(res.D, direct.D)
+    if lookahead == 0:
+        # plain steps: resumed and direct runs are bitwise identical
+        assert torch.equal(res.L, direct.L)
+        assert torch.equal(res.D, direct.D)
+    else:
+        # look-ahead blocks start at different steps: same pivots, vectors equal to rounding
+        ref = oracle_cd("small_cage", 1e-6)
+        tol = torch.as_tensor(cd_tolerance(ref, E.eri_diagonal(w.centres, w.alpha).max()), device="cuda")
+        assert torch.all((res.L - direct.L).abs().max(dim=1).values <= tol)
+
+
+@pytest.mark.parametrize("name,delta", [("small_cage", 1e-6), ("c60", 1e-6)])
+def test_cd_plain_equals_lookahead(cds, name, delta):
+    w = workload(name)
+    log(f"cd plain vs look-ahead {name}")
+    c, a = _dev(w.centres), _dev(w.alpha)
+    ctx0 = cds.Context(0)
+    ctx0.set_cd_lookahead(0)
+    plain = cds.cholesky(delta, centres=c, alpha=a, ctx=ctx0)
+    ctx1 = cds.Context(0)
+    ctx1.set_cd_lookahead(8)
+    la = cds.cholesky(delta, centres=c, alpha=a, ctx=ctx1)
+    st = ctx1.stats()
+    log(f"  look-ahead 8: {st['n_cd_pass']} passes, {st['n_cd_miss']} misses of {la.nvec} steps")
+    assert la.nvec == plain.nvec
+    assert torch.equal(la.piv[: la.nvec], plain.piv[: plain.nvec])
+    ref = oracle_cd(name, delta)
+    tol = torch.as_tensor(cd_tolerance(ref, E.eri_diagonal(w.centres, w.alpha).max()), device="cuda")
+    assert torch.all((la.L - plain.L).abs().max(dim=1).values <= tol)
 
 
 def test_cd_cap_status_and_resume(cds):
