@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 HARTREE_EV = 27.211396
 HBM_PEAK_GBS = 8000.0
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
-FP64_VALU_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flops/clk/CU (fused multiply-add)
+FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix peak
 METRIC = "quasi-particle solves/s + contraction TFLOP/s, FP32/BF16x3 vs FP64 at ≤1 meV"
 
 
@@ -41,6 +41,24 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-targets", type=int, default=4, help="targets in the oracle Newton sample")
     return p.parse_args()
+
+
+def committed_traffic() -> dict:
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, per
+    kernel, if the Cholesky source is unchanged since the counters were taken; else {}."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cd_kernels_c60_traffic.json")
+    src = os.path.join(ROOT, "paper_0912_1459_amd", "csrc", "cd.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return {}
+    if rec.get("cd_hip_sha256") != sha:
+        return {}
+    return {k: v["hbm_bytes_per_launch"] for k, v in rec.get("kernels", {}).items()}
 
 
 def cpu_baseline(w, delta: float, conv: float, ntarget: int) -> dict:
@@ -97,8 +115,9 @@ def main():
     for _ in range(args.warmup):
         step(args.prec)
     torch.cuda.synchronize()
+
+    # timed region: K whole-path steps, no per-kernel events
     ctx.reset_stats()
-    ctx.set_kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -110,43 +129,55 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    st = ctx.stats()
-    ctx.set_kernel_timing(False)
+    st_run = ctx.stats()
     ms_per_step = gpu_ms / args.steps
     value = nsel * args.steps / (gpu_ms / 1e3)
 
-    # Cholesky kernels: the per-step kernel (GEMV over the vectors made since the look-ahead
-    # block started, or all of them on a miss) and the look-ahead pass (one FP64 read of L for
-    # up to 64 candidate columns).  The roofline object describes the one with more device time.
+    # the same K steps again with HIP events around every Cholesky step-kernel and pass
+    # launch (on the library's stream): per-launch durations for the roofline
+    ctx.reset_stats()
+    ctx.set_kernel_timing(True)
+    for _ in range(args.steps):
+        step(args.prec)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ctx.set_kernel_timing(False)
+
     M = cd.nvec
     npairs = w.npairs
-    steps_t = st["t_cd_kernel_ms"] / 1e3 / args.steps
-    pass_t = st["t_cd_pass_ms"] / 1e3 / args.steps
-    n_pass = st["n_cd_pass"] / args.steps
-    pass_bytes = st["bytes_cd_pass"] / args.steps
-    pass_flops = st["flops_cd_pass"] / args.steps
+    n_step = st["n_cd_step_launch"]
+    n_pass = st["n_cd_pass_launch"]
+    t_step = st["t_cd_kernel_ms"] / 1e3
+    t_pass = st["t_cd_pass_ms"] / 1e3
     cd_kernels = {
-        "step": {"launches": M, "total_ms": round(steps_t * 1e3, 3), "avg_us": round(steps_t / M * 1e6, 3)},
-        "pass": {"launches": n_pass, "total_ms": round(pass_t * 1e3, 3),
-                 "avg_us": round(pass_t / max(n_pass, 1) * 1e6, 3),
-                 "gbs": round(pass_bytes / pass_t / 1e9, 1) if pass_t > 0 else None,
-                 "tflops_fp64": round(pass_flops / pass_t / 1e12, 2) if pass_t > 0 else None},
-        "misses": st["n_cd_miss"] / args.steps,
+        "step": {"launches_per_cd": n_step / args.steps, "total_ms_per_cd": round(t_step * 1e3 / args.steps, 3),
+                 "avg_us": round(t_step / max(n_step, 1) * 1e6, 3),
+                 "algorithmic_gbs": round(st["bytes_cd_step"] / t_step / 1e9, 1) if t_step > 0 else None},
+        "pass": {"launches_per_cd": n_pass / args.steps, "total_ms_per_cd": round(t_pass * 1e3 / args.steps, 3),
+                 "avg_us": round(t_pass / max(n_pass, 1) * 1e6, 3),
+                 "gbs": round(st["bytes_cd_pass"] / t_pass / 1e9, 1) if t_pass > 0 else None,
+                 "tflops_fp64": round(st["flops_cd_pass"] / t_pass / 1e12, 2) if t_pass > 0 else None},
+        "misses_per_cd": st["n_cd_miss"] / args.steps,
     }
-    if pass_t >= steps_t:
-        tf = pass_flops / pass_t / 1e12
-        gbs = pass_bytes / pass_t / 1e9
-        # intensity 2*64 flops per 8 bytes of L: above the FP64 ridge (78.6 TF / 8 TB/s)
-        roofline = {"kernel": "cd_pass_kernel", "bound": "alu", "achieved": round(tf, 2),
-                    "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP64_VALU_TFLOPS, 4),
-                    "traffic": None, "launches": n_pass, "avg_launch_us": cd_kernels["pass"]["avg_us"],
-                    "hbm_gbs": round(gbs, 1)}
+    traffic = committed_traffic()
+    if t_pass >= t_step:
+        # 2 flops per vector, pair row and candidate: 16 flops per byte of L, above the FP64
+        # MFMA ridge (78.6 TF / 8 TB/s)
+        per_launch = st["flops_cd_pass"] / max(n_pass, 1)
+        avg = t_pass / max(n_pass, 1)
+        roofline = {"kernel": "cd_pass_kernel", "bound": "mfma", "achieved": round(per_launch / avg / 1e12, 2),
+                    "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(per_launch / avg / 1e12 / FP64_MFMA_TFLOPS, 4),
+                    "traffic": traffic.get("cd_pass_kernel"), "launches": n_pass / args.steps,
+                    "avg_launch_us": round(avg * 1e6, 3), "units": "2 x pairs x vectors x 64 flops per launch"}
     else:
-        step_bytes = 8.0 * npairs * M * (M - 1) / 2.0
-        roofline = {"kernel": "cd_step_kernel", "bound": "hbm",
-                    "achieved": round(step_bytes / steps_t / 1e9, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(step_bytes / steps_t / 1e9 / HBM_PEAK_GBS, 4),
-                    "traffic": None, "launches": M, "avg_launch_us": cd_kernels["step"]["avg_us"]}
+        per_launch = st["bytes_cd_step"] / max(n_step, 1)
+        avg = t_step / max(n_step, 1)
+        roofline = {"kernel": "cd_step_kernel", "bound": "hbm", "achieved": round(per_launch / avg / 1e9, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4),
+                    "traffic": traffic.get("cd_step_kernel"), "launches": n_step / args.steps,
+                    "avg_launch_us": round(avg * 1e6, 3),
+                    "units": "pairs x (8 B per vector subtracted + 34..66 B) per launch"}
 
     # per-precision contraction throughput and accuracy against the FP64 GPU path
     ref_cd, ref_B, ref_qp = step("fp64")
@@ -200,10 +231,10 @@ def main():
                                 f"{nsel} targets, Newton Delta={conv:g}"),
                    "nvec": M, "prec": args.prec},
         "roofline": roofline,
-        "cd": {"ms": round(st["t_cd_ms"] / args.steps, 3), "steps": M, "kernels": cd_kernels,
-               "plain_algorithm_gbs": round(st["bytes_cd"] / args.steps
-                                            / (st["t_cd_ms"] / args.steps / 1e3) / 1e9, 1)},
-        "phases_ms": {k: round(st[k] / args.steps, 3) for k in
+        "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M, "kernels": cd_kernels,
+               # bytes the plain one-vector-per-step algorithm streams, over the whole decomposition
+               "plain_algorithm_equivalent_gbs": round(st_run["bytes_cd"] / (st_run["t_cd_ms"] / 1e3) / 1e9, 1)},
+        "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
                       ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")},
         "precision": prec_report,
         "wall_s": round(wall, 3),

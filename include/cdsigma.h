@@ -78,7 +78,7 @@ typedef struct cds_ctx cds_ctx;
 /* Per-context accumulated device times (HIP events on the context stream),
  * algorithmic bytes and flops.  Reset by cds_reset_stats(). */
 typedef struct cds_stats {
-    double t_cd_ms;          /* pivoted Cholesky: all step kernels            */
+    double t_cd_ms;          /* pivoted Cholesky: the whole decomposition     */
     double t_cd_kernel_ms;   /* Cholesky step-kernel time (with kernel timing on) */
     double t_transform_ms;   /* AO->MO transform                              */
     double t_contract_ms;    /* contraction GEMM launches                     */
@@ -91,12 +91,16 @@ typedef struct cds_stats {
     int64_t n_contract;
     int64_t n_newton_iter;
     double t_cd_pass_ms;     /* look-ahead pass kernels (with kernel timing on) */
-    double bytes_cd_pass;    /* bytes those passes read/write: 8 npairs (k0 + ncand) */
-    int64_t n_cd_pass;       /* look-ahead blocks started                     */
+    double bytes_cd_pass;    /* bytes those passes read/write: 8 npairs (k0 + 64) */
+    int64_t n_cd_pass;       /* look-ahead passes that did work               */
     int64_t n_cd_miss;       /* steps whose pivot was not a look-ahead candidate */
     double flops_cd_pass;    /* nominal pass flops: 2 npairs k0 (64 candidates) */
-    double bytes_cd_step;    /* bytes the step kernels moved: 8 npairs (k - first
-                                vector subtracted) + 42 npairs per step         */
+    double bytes_cd_step;    /* algorithmic bytes of the step kernels: per step and
+                                pair row 8 per vector subtracted + 26 (D, mask,
+                                L_k) + 8 (column from R or V) or 40 (pair data) */
+    int64_t n_cd_step_launch; /* step-kernel launches (a few past the last step
+                                 return at once)                                */
+    int64_t n_cd_pass_launch; /* look-ahead pass launches                       */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`

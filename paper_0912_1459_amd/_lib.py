@@ -40,6 +40,7 @@ class Stats(ctypes.Structure):
         ("t_cd_pass_ms", ctypes.c_double), ("bytes_cd_pass", ctypes.c_double),
         ("n_cd_pass", ctypes.c_int64), ("n_cd_miss", ctypes.c_int64),
         ("flops_cd_pass", ctypes.c_double), ("bytes_cd_step", ctypes.c_double),
+        ("n_cd_step_launch", ctypes.c_int64), ("n_cd_pass_launch", ctypes.c_int64),
     ]
 
 

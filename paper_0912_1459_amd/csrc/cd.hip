@@ -59,7 +59,7 @@ struct CdState {
     int32_t ncand;   // candidates of the current look-ahead block
     int32_t pad;
     int64_t nmiss;   // steps whose pivot was not a candidate
-    double bytes;    // bytes the step kernels read and wrote (8 npairs (k - jstart) + 42 npairs)
+    double bytes;    // bytes the step kernels must move (algorithmic, per the formula at the update)
 };
 
 struct CdBufs {
@@ -288,6 +288,7 @@ enum { PICK_GO = -100 };
 
 struct Pick {
     int status;      // PICK_GO or a CDS_CD_* termination
+    int slot;        // the pivot's look-ahead candidate slot, -1 if none
     double mx;       // largest non-pivot residual diagonal
     int64_t p;       // pivot
     double dp;       // its residual diagonal
@@ -318,6 +319,7 @@ __device__ Pick cd_pick_wave(const CdBufs &b, int r, int sr, const CdParams &cp,
     pk.mx = mx;
     pk.p = -1;
     pk.dp = 0.0;
+    pk.slot = -1;
     pk.status = PICK_GO;
     if (mn < -cp.psd_tol) pk.status = CDS_CD_NOTPSD;
     else if (mx == -INFINITY) pk.status = CDS_CD_FULLRANK;
@@ -413,7 +415,6 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     __shared__ double shv[CD_NT / 64];
     __shared__ int64_t shi[CD_NT / 64];
     __shared__ Pick spk;
-    __shared__ int sslot;
     if (st->done) return;
     const int rl = threadIdx.x % RL, jg = threadIdx.x / RL;
     const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
@@ -445,7 +446,18 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
         m_old = b.mask[r][If];
     }
     if (threadIdx.x < 64) {
-        const Pick pk0 = cd_pick_wave(b, r, sr, cp, k);
+        // candidate list of the current look-ahead block (CD_NCAND == 64: one per lane)
+        int64_t cl = -1;
+        int nc = 0;
+        if (bsteps > 0) {
+            nc = st->ncand;
+            cl = cand[threadIdx.x];
+        }
+        Pick pk0 = cd_pick_wave(b, r, sr, cp, k);
+        if (pk0.status == PICK_GO) {
+            const unsigned long long hit = __ballot((int)threadIdx.x < nc && cl == pk0.p);
+            pk0.slot = hit ? __ffsll((long long)hit) - 1 : -1;
+        }
         if (threadIdx.x == 0) spk = pk0;
     }
     __syncthreads();
@@ -461,11 +473,20 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     }
     const int64_t p = pk.p;
     const double sq = sqrt(pk.dp);
-    if (threadIdx.x == 0) sslot = -1;
-    __syncthreads();
-    if (bsteps > 0 && threadIdx.x < st->ncand && cand[threadIdx.x] == p) sslot = threadIdx.x;
-    __syncthreads();
-    const int slot = sslot;
+    const int slot = pk.slot;
+    // this row's entry of the pivot column (residual from the look-ahead pass on a hit),
+    // issued before the pivot-row gather so the two loads overlap
+    double cfin = 0.0;
+    if (threadIdx.x < CD_TILE && If < cp.npairs && !m_old && If != p) {
+        if (slot >= 0) {
+            cfin = R[(int64_t)slot * ldr + If];
+        } else if constexpr (DENSE) {
+            cfin = V[p * ldv + If];
+        } else {
+            cfin = eri_pp(pt.p[If], pt.Px[If], pt.Py[If], pt.Pz[If], pt.K[If], pt.p[p], pt.Px[p], pt.Py[p],
+                          pt.Pz[p], pt.K[p]);
+        }
+    }
     double acc[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) acc[v] = 0.0;
@@ -555,15 +576,7 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
             dn = 0.0;
             m = 1;
         } else {
-            double c;
-            if (slot >= 0) {
-                c = R[(int64_t)slot * ldr + I];
-            } else if constexpr (DENSE) {
-                c = V[p * ldv + I];
-            } else {
-                c = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[p], pt.Px[p],
-                           pt.Py[p], pt.Pz[p], pt.K[p]);
-            }
+            double c = cfin;
             double s = 0.0;
 #pragma unroll
             for (int g = 0; g < JG; ++g) s += red[g][threadIdx.x];
@@ -597,7 +610,10 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
             st->k = k + 1;
             st->dmax = pk.mx;
             if (bsteps > 0 && slot < 0) st->nmiss += 1;
-            st->bytes += 8.0 * (double)cp.npairs * (double)(k - (slot >= 0 ? k0 : 0)) + 42.0 * (double)cp.npairs;
+            // per row: 8 B per vector subtracted; D, mask read and written and L_k written
+            // (34 B); the column entry from R or V (8 B) or the pair table (40 B, on demand)
+            const double col = (slot >= 0 || DENSE) ? 8.0 : 40.0;
+            st->bytes += (double)cp.npairs * (8.0 * (double)(k - (slot >= 0 ? k0 : 0)) + 26.0 + col);
         }
     }
 }
@@ -621,7 +637,10 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     }
     __syncthreads();
     const Pick pk = spk;
-    if (pk.status != PICK_GO) return;            // the step kernel records the termination
+    if (pk.status != PICK_GO) {                  // the step kernel records the termination
+        if (threadIdx.x == 0) st->ncand = 0;     // gather and pass have nothing to do
+        return;
+    }
     const int64_t p = pk.p;
     const int want = CD_NCAND - 1;
     const int64_t ntile = b.ntile;
@@ -648,14 +667,33 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
             atomicAdd(&hist[(u >> shift) & 0xFF], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int need = s_need, q = 255;
-            for (; q > 0; --q) {
-                if ((int)hist[q] >= need) break;
-                need -= hist[q];
+        if (threadIdx.x < 64) {
+            // digit q = the largest with (count of keys >= q) >= need; need -= count above q.
+            // Lane l holds bins 4l..4l+3; suffix sums over lanes locate q's lane.
+            const int l = threadIdx.x, need = s_need;
+            const int h0 = hist[4 * l], h1 = hist[4 * l + 1], h2 = hist[4 * l + 2], h3 = hist[4 * l + 3];
+            const int own = h0 + h1 + h2 + h3;
+            int S = own;                                   // sum over lanes >= l
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_down(S, o, 64);
+                if (l + o < 64) S += v;
             }
-            s_prefix = (prefix << 8) | (unsigned long long)q;
-            s_need = need;
+            const unsigned long long ok = __ballot(S >= need);
+            if (ok == 0ull) {
+                if (l == 0) {                              // fewer keys than wanted: take all
+                    s_prefix = prefix << 8;
+                    s_need = need - (S - h0);
+                }
+            } else if (l == 63 - __clzll((long long)ok)) {
+                int rem = need - (S - own);
+                int q;
+                if (h3 >= rem) q = 3;
+                else if (h2 >= (rem -= h3)) q = 2;
+                else if (h1 >= (rem -= h2)) q = 1;
+                else { rem -= h1; q = 0; }
+                s_prefix = (prefix << 8) | (unsigned long long)(4 * l + q);
+                s_need = rem;
+            }
         }
         __syncthreads();
     }
@@ -694,7 +732,7 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
 __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
                                  const int64_t *__restrict__ cand, double *__restrict__ P)
 {
-    if (st->done) return;
+    if (st->done || st->ncand == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t j = e / CD_NCAND;
     const int c = (int)(e % CD_NCAND);
@@ -712,7 +750,7 @@ __global__ __launch_bounds__(256) void cd_pass_kernel(
     const double *__restrict__ P, double *__restrict__ R, int64_t ldr)
 {
     __shared__ double sp[CD_PASS_JC][CD_NCAND];
-    if (st->done) return;
+    if (st->done || st->ncand == 0) return;
     const int nc = st->ncand;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
@@ -942,9 +980,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                        (const int64_t *)cand, (const double *)Pc, Rc, ldr);
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
-                ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)k + 8.0 * CD_NCAND * (double)npairs;
-                ctx->stats.flops_cd_pass += 2.0 * (double)npairs * (double)k * CD_NCAND;
-                ctx->stats.n_cd_pass += 1;
+                ctx->stats.n_cd_pass_launch += 1;
             }
             CdsTimer tk;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tk));
@@ -965,6 +1001,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             }
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
+            ctx->stats.n_cd_step_launch += 1;
         }
         if (batch < 64) batch *= 2;
     }
@@ -976,6 +1013,14 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     for (int64_t j = nvec_in; j < hs.k; ++j)
         ctx->stats.bytes_cd += 8.0 * (double)npairs * (double)j + 64.0 * (double)npairs;
     ctx->stats.n_cd_steps += hs.k - nvec_in;
+    // passes that did work: block starts before the final k (8 npairs B per vector read, one
+    // row of R written per candidate; 2 flops per vector, pair and candidate slot)
+    if (bsteps > 0)
+        for (int64_t j = nvec_in; j < hs.k; j += bsteps) {
+            ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)j + 8.0 * CD_NCAND * (double)npairs;
+            ctx->stats.flops_cd_pass += 2.0 * (double)npairs * (double)j * CD_NCAND;
+            ctx->stats.n_cd_pass += 1;
+        }
     ctx->stats.n_cd_miss += hs.nmiss;
     ctx->stats.bytes_cd_step += hs.bytes;
     CDS_CALL(cds_timers_flush(ctx));
