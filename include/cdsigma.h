@@ -112,9 +112,9 @@ void cds_destroy(cds_ctx *ctx);
 const char *cds_last_error(const cds_ctx *ctx);
 int cds_get_stats(const cds_ctx *ctx, cds_stats *out);
 int cds_reset_stats(cds_ctx *ctx);
-/* 1: time every step-kernel and look-ahead-pass launch of the Cholesky
- * decomposition with HIP events (cds_stats.t_cd_kernel_ms, t_cd_pass_ms);
- * 0 (default): off. */
+/* 1: time the step kernels (one HIP event pair per run of consecutive step
+ * launches) and every look-ahead pass of the Cholesky decomposition
+ * (cds_stats.t_cd_kernel_ms, t_cd_pass_ms); 0 (default): off. */
 int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
 /* Look-ahead of the pivoted Cholesky: every block_steps steps one pass over L
  * forms the residual columns of up to 64 candidate pivots (the next pivot and
@@ -122,6 +122,11 @@ int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
  * subtract the vectors made since.  0 disables it (each step streams all of L).
  * Default 16; valid range [0, 256]. */
 int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
+/* Pivot search of the Cholesky steps: 0 (default) = one sweep over the records
+ * of all 64-row tiles when there are at most 1024 tiles, else hierarchical;
+ * 1 = always hierarchical (64 super-tile maxima, then tiles, then rows).  The
+ * pivots are the same either way. */
+int cds_set_cd_pivot_search(cds_ctx *ctx, int32_t hierarchical);
 /* Library version string (static). */
 const char *cds_version(void);
 

@@ -101,6 +101,11 @@ class Context:
         """Cholesky look-ahead block length (0: plain one-vector-per-step streaming)."""
         self.check(self.lib.cds_set_cd_lookahead(self.h, int(block_steps)))
 
+    def set_cd_pivot_search(self, hierarchical: bool):
+        """Cholesky pivot search: False = automatic (flat sweep up to 1024 tiles), True = always
+        through the super-tile keys."""
+        self.check(self.lib.cds_set_cd_pivot_search(self.h, int(bool(hierarchical))))
+
 
 _default = {}
 

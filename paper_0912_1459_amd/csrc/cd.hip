@@ -16,14 +16,16 @@
 //     cd_pass    R[c][I] = V[I][cand_c] - sum_{j<k0} L[j][I] P[j][c]  (one read of L,
 //                FP64 MFMA)
 //   every step k, ONE launch (cd_step), each 64-row block:
-//     - picks the pivot itself from the previous step's statistics (64 super-tile
-//       maxima kept with order-preserving integer atomics, then one super-tile's
-//       tiles, then one tile's rows); every block reaches the same pivot;
+//     - picks the pivot itself from the previous step's tile records (largest and
+//       smallest residual of each 64-row tile, and its lowest row within tau of its
+//       largest): one sweep over all records, or for many tiles 64 super-tile maxima
+//       kept with order-preserving integer atomics first; every block reaches the
+//       same pivot;
 //     - c_I = R[slot][I] - sum_{k0<=j<k} L[j][I] L[j][p] when p is candidate `slot`,
 //       else V_Ip - sum_{j<k} L[j][I] L[j][p] (a miss);
 //     - writes L[k], the next residual diagonal and pivot mask, tile statistics.
-//   D, the mask and the tile statistics are double-buffered and the super-tile
-//   statistics triple-buffered by step parity, so no block reads what another
+//   D, the mask and the tile records are double-buffered and the super-tile
+//   keys triple-buffered by step parity, so no block reads what another
 //   block of the same launch writes: no fences or grid barriers.
 //
 // Device layout (HBM): pair table SoA p, Px, Py, Pz, K (5 x npairs FP64); L vector-
@@ -45,7 +47,10 @@ constexpr int CD_PCHUNK = 1024;         // pivot-row entries staged in LDS per c
 constexpr int CD_AUX_NT = 1024;         // threads of the one-block kernels
 constexpr int CD_NSUP = 64;             // super-tiles of the hierarchical pivot search
 constexpr int CD_NCAND = 64;            // candidate residual columns per look-ahead block
-constexpr int CD_PASS_JC = 64;          // candidate-row entries staged per pass chunk
+constexpr int CD_PASS_JC = 32;          // candidate-row entries staged per pass chunk
+constexpr int CD_TPT = 4;               // tile records per thread in the flat pivot search
+constexpr int CD_CAND_MAXTILE = 8192;   // tiles the candidate selection handles (look-ahead
+                                        // is off above 8192 * 64 pairs)
 
 struct PairTable {
     double *p, *Px, *Py, *Pz, *K;
@@ -60,17 +65,26 @@ struct CdState {
     int32_t pad;
     int64_t nmiss;   // steps whose pivot was not a candidate
     double bytes;    // bytes the step kernels must move (algorithmic, per the formula at the update)
+    int64_t kdone;   // step whose launch found a termination rule (INT64_MAX before): later
+                     // launches return at once; blocks of that same launch all still see it
+                     // as not earlier than their step, so no block splits on it
+};
+
+// Per 64-row tile, over its non-pivot rows: the largest and smallest residual diagonal,
+// and the lowest row whose residual is within tau of the largest (with that residual).
+struct TileStat {
+    double mx, mn, dfirst;
+    int64_t first;                      // -1: no non-pivot row
 };
 
 struct CdBufs {
     double *D[2];                       // residual diagonal, by parity
     unsigned char *mask[2];             // pivot mask, by parity
-    double *tmax[2];                    // per-tile max of non-pivot D
-    int64_t *targ[2];                   // its row (lowest index on ties)
-    double *tmin[2];                    // per-tile min of non-pivot D
+    TileStat *ts[2];                    // tile records, by parity
     unsigned long long *smax[3];        // super-tile max keys (atomicMax), triple-buffered
     unsigned long long *smin[3];        // super-tile min keys (atomicMin)
     int64_t ntile, tps;                 // tiles; tiles per super-tile
+    int flat;                           // 1: pivot search over all tile records (no keys)
 };
 
 struct CdParams {
@@ -294,6 +308,13 @@ struct Pick {
     double dp;       // its residual diagonal
 };
 
+struct PickShared {
+    double v[2 * 16];
+    int64_t i[16];
+    TileStat rec;
+    Pick pk;
+};
+
 __device__ __forceinline__ double wave_max(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -304,12 +325,52 @@ __device__ __forceinline__ double wave_min(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
     return v;
 }
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
 
-// Largest non-pivot D from the super-tile keys, termination tests, then the lowest index
-// I (not a pivot) with D_I >= D_max - tau: first super-tile, then first tile, then first
-// row, each found with one wave-wide ballot.  Executed by the 64 lanes of ONE wave; every
-// block that calls it on the same buffers gets the same answer.
-__device__ Pick cd_pick_wave(const CdBufs &b, int r, int sr, const CdParams &cp, int64_t k)
+__device__ __forceinline__ int pick_status(double mx, double mn, const CdParams &cp, int64_t k)
+{
+    if (mn < -cp.psd_tol) return CDS_CD_NOTPSD;
+    if (mx == -INFINITY) return CDS_CD_FULLRANK;
+    if (mx <= cp.delta) return CDS_CD_CONVERGED;
+    if (k >= cp.max_vec) return CDS_CD_CAP;
+    return PICK_GO;
+}
+
+// Within tile t (whose largest residual is >= thresh): the lowest non-pivot row with
+// D >= thresh.  One wave.  The tile record names it directly when the tile holds the
+// overall maximum (its own window is then the same); otherwise the tile's rows are read.
+__device__ __forceinline__ void pick_in_tile(const CdBufs &b, int r, const CdParams &cp, int64_t t,
+                                             const TileStat &rec, double mx, double thresh, Pick &pk)
+{
+    if (rec.mx == mx) {
+        pk.p = rec.first;
+        pk.dp = rec.dfirst;
+        return;
+    }
+    const int l = threadIdx.x & 63;
+    const int64_t I = t * CD_TILE + l;
+    const double d = I < cp.npairs ? b.D[r][I] : -INFINITY;
+    const bool ok = I < cp.npairs && !b.mask[r][I] && d >= thresh;
+    const unsigned long long bp = __ballot(ok);
+    if (!bp) {
+        pk.status = CDS_CD_NOTPSD;                 // only with non-finite residuals
+        return;
+    }
+    const int lp = __ffsll((long long)bp) - 1;
+    pk.p = t * CD_TILE + lp;
+    pk.dp = __shfl(d, lp, 64);
+}
+
+// Hierarchical search for large tile counts (one wave): 64 super-tile keys, then the first
+// super-tile's tile records, then one tile.
+__device__ Pick cd_pick_super(const CdBufs &b, int r, int sr, const CdParams &cp, int64_t k)
 {
     const int l = threadIdx.x & 63;               // CD_NSUP == 64: one super-tile per lane
     const double v = okey_max(b.smax[sr][l]);
@@ -320,43 +381,117 @@ __device__ Pick cd_pick_wave(const CdBufs &b, int r, int sr, const CdParams &cp,
     pk.p = -1;
     pk.dp = 0.0;
     pk.slot = -1;
-    pk.status = PICK_GO;
-    if (mn < -cp.psd_tol) pk.status = CDS_CD_NOTPSD;
-    else if (mx == -INFINITY) pk.status = CDS_CD_FULLRANK;
-    else if (mx <= cp.delta) pk.status = CDS_CD_CONVERGED;
-    else if (k >= cp.max_vec) pk.status = CDS_CD_CAP;
+    pk.status = pick_status(mx, mn, cp, k);
     if (pk.status != PICK_GO) return pk;
     const double thresh = mx - cp.tau;
     const unsigned long long bs = __ballot(v >= thresh);
-    const int64_t sidx = __ffsll((long long)bs) - 1;
     int64_t t = -1;
     if (bs) {
+        const int64_t sidx = __ffsll((long long)bs) - 1;
         const int64_t t0 = sidx * b.tps, t1 = min(b.ntile, t0 + b.tps);
         for (int64_t u0 = t0; u0 < t1; u0 += 64) {
             const int64_t u = u0 + l;
-            const unsigned long long bt = __ballot(u < t1 && b.tmax[r][u] >= thresh);
+            const unsigned long long bt = __ballot(u < t1 && b.ts[r][u].mx >= thresh);
             if (bt) {
                 t = u0 + __ffsll((long long)bt) - 1;
                 break;
             }
         }
     }
-    if (t < 0) {                                  // only with non-finite residuals
+    if (t < 0) {
         pk.status = CDS_CD_NOTPSD;
         return pk;
     }
-    const int64_t I = t * CD_TILE + l;
-    const double d = I < cp.npairs ? b.D[r][I] : -INFINITY;
-    const bool ok = I < cp.npairs && !b.mask[r][I] && d >= thresh;
-    const unsigned long long bp = __ballot(ok);
-    if (!bp) {
-        pk.status = CDS_CD_NOTPSD;
-        return pk;
-    }
-    const int lp = __ffsll((long long)bp) - 1;
-    pk.p = t * CD_TILE + lp;
-    pk.dp = __shfl(d, lp, 64);
+    const TileStat rec = b.ts[r][t];
+    pick_in_tile(b, r, cp, t, rec, mx, thresh, pk);
     return pk;
+}
+
+// Pivot of step k from the tile records of parity r (every thread of the block calls it;
+// the result is the same in every block).  Up to NT * CD_TPT tiles the records are read
+// in one sweep by the whole block; beyond that the super-tile keys lead the way.
+template <int NT>
+__device__ Pick cd_pick(const CdBufs &b, int r, int sr, const CdParams &cp, int64_t k, PickShared &sh)
+{
+    constexpr int NW = NT / 64;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (!b.flat) {
+        if (w == 0) {
+            const Pick pk = cd_pick_super(b, r, sr, cp, k);
+            if (l == 0) sh.pk = pk;
+        }
+        __syncthreads();
+        return sh.pk;
+    }
+    TileStat rc[CD_TPT];
+    double lmx = -INFINITY, lmn = INFINITY;
+#pragma unroll
+    for (int i = 0; i < CD_TPT; ++i) {
+        const int64_t u = threadIdx.x + (int64_t)NT * i;
+        if (u < b.ntile) {
+            rc[i] = b.ts[r][u];
+        } else {
+            rc[i].mx = -INFINITY;
+            rc[i].mn = INFINITY;
+            rc[i].dfirst = 0.0;
+            rc[i].first = -1;
+        }
+        lmx = fmax(lmx, rc[i].mx);
+        lmn = fmin(lmn, rc[i].mn);
+    }
+    lmx = wave_max(lmx);
+    lmn = wave_min(lmn);
+    if (l == 0) {
+        sh.v[w] = lmx;
+        sh.v[NW + w] = lmn;
+    }
+    __syncthreads();
+    double mx = -INFINITY, mn = INFINITY;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        mx = fmax(mx, sh.v[q]);
+        mn = fmin(mn, sh.v[NW + q]);
+    }
+    Pick pk;
+    pk.mx = mx;
+    pk.p = -1;
+    pk.dp = 0.0;
+    pk.slot = -1;
+    pk.status = pick_status(mx, mn, cp, k);
+    if (pk.status != PICK_GO) return pk;          // uniform over the block
+    const double thresh = mx - cp.tau;
+    int64_t tf = INT64_MAX;
+#pragma unroll
+    for (int i = CD_TPT - 1; i >= 0; --i)
+        if (rc[i].mx >= thresh) tf = threadIdx.x + (int64_t)NT * i;
+    tf = wave_min_i64(tf);
+    if (l == 0) sh.i[w] = tf;
+    __syncthreads();
+    int64_t t = INT64_MAX;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t = sh.i[q] < t ? sh.i[q] : t;
+    if (t == INT64_MAX) {
+        pk.status = CDS_CD_NOTPSD;                 // only with non-finite residuals
+        return pk;
+    }
+    if (threadIdx.x == t % NT) {
+#pragma unroll
+        for (int i = 0; i < CD_TPT; ++i)
+            if (t == threadIdx.x + (int64_t)NT * i) sh.rec = rc[i];
+    }
+    __syncthreads();
+    const TileStat rec = sh.rec;
+    if (rec.mx == mx) {                            // the usual case: no further read
+        pk.p = rec.first;
+        pk.dp = rec.dfirst;
+        return pk;
+    }
+    if (w == 0) {
+        pick_in_tile(b, r, cp, t, rec, mx, thresh, pk);
+        if (l == 0) sh.pk = pk;
+    }
+    __syncthreads();
+    return sh.pk;
 }
 
 __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, int64_t npairs,
@@ -369,36 +504,47 @@ __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, i
     }
 }
 
-// tile and super-tile statistics of D[0] / mask[0] (start or resume)
-__global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, int64_t npairs)
+// Record of one 64-row tile from its rows' new residuals (one wave; `active` = a non-pivot
+// row): largest and smallest residual, and the lowest row within tau of the largest.
+__device__ __forceinline__ void tile_record(const CdBufs &b, int w, int sw, const CdParams &cp, int64_t tile,
+                                            bool active, double dn)
 {
-    __shared__ double shv[1], sh[1];
-    __shared__ int64_t shi[1];
+    const int l = threadIdx.x & 63;
+    const double tmx = wave_max(active ? dn : -INFINITY);
+    const double tmn = wave_min(active ? dn : INFINITY);
+    const unsigned long long fb = __ballot(active && dn >= tmx - cp.tau);
+    const int fl = fb ? __ffsll((long long)fb) - 1 : 0;
+    const double df = __shfl(dn, fl, 64);
+    if (l == 0) {
+        TileStat s;
+        s.mx = tmx;
+        s.mn = tmn;
+        s.dfirst = fb ? df : 0.0;
+        s.first = fb ? tile * CD_TILE + fl : -1;
+        b.ts[w][tile] = s;
+        if (!b.flat) {
+            const int64_t sidx = tile / b.tps;
+            if (tmx != -INFINITY) atomicMax(&b.smax[sw][sidx], okey(tmx));
+            if (tmn != INFINITY) atomicMin(&b.smin[sw][sidx], okey(tmn));
+        }
+    }
+}
+
+// tile records (and super-tile keys) of D[0] / mask[0] (start or resume)
+__global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, CdParams cp)
+{
     const int64_t I = (int64_t)blockIdx.x * CD_TILE + threadIdx.x;
-    double mx = -INFINITY, mn = INFINITY;
-    int64_t ix = INT64_MAX;
-    if (I < npairs && !b.mask[0][I]) {
-        mx = mn = b.D[0][I];
-        ix = I;
-    }
-    block_argmax<CD_TILE>(mx, ix, shv, shi);
-    mn = block_min<CD_TILE>(mn, sh);
-    if (threadIdx.x == 0) {
-        b.tmax[0][blockIdx.x] = mx;
-        b.targ[0][blockIdx.x] = ix;
-        b.tmin[0][blockIdx.x] = mn;
-        const int64_t sidx = blockIdx.x / b.tps;
-        if (mx != -INFINITY) atomicMax(&b.smax[0][sidx], okey(mx));
-        if (mn != INFINITY) atomicMin(&b.smin[0][sidx], okey(mn));
-    }
+    const bool active = I < cp.npairs && !b.mask[0][I];
+    const double d = active ? b.D[0][I] : 0.0;
+    tile_record(b, 0, 0, cp, blockIdx.x, active, d);
 }
 
 // One Cholesky step (one launch).  Block = CD_TILE rows; thread (jg, rl): rows I0..I0+VW-1,
 // vectors j = jstart + jg, + JG, ...; partial sums combined in LDS in fixed order.
-// r/w: read/write parity of D, mask and tile stats; sr/sw/sz: super-tile buffers read,
+// r/w: read/write parity of D, mask and tile records; sr/sw/sz: super-tile buffers read,
 // written (atomics) and reset for the step after next.  Loads that do not depend on the
-// pivot (the vectors made since the block start, D, mask) are issued before wave 0
-// finishes the pivot search.
+// pivot (the vectors made since the block start, D, mask, the candidate list) are issued
+// before the pivot search.
 template <int VW, bool DENSE>
 __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     CdBufs b, CdParams cp, int r, int sr, int sw, int sz, int64_t k, int64_t k0, int bsteps,
@@ -411,11 +557,9 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     constexpr int NPF = 2;                      // prefetched vectors per thread
     __shared__ double sp[CD_PCHUNK];
     __shared__ double red[JG][CD_TILE];
-    __shared__ double shd[CD_NT / 64];
-    __shared__ double shv[CD_NT / 64];
-    __shared__ int64_t shi[CD_NT / 64];
-    __shared__ Pick spk;
-    if (st->done) return;
+    __shared__ PickShared psh;
+    __shared__ int sslot;
+    const int64_t kdone = st->kdone;
     const int rl = threadIdx.x % RL, jg = threadIdx.x / RL;
     const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
     const int64_t I0 = tile0 + (int64_t)VW * rl;
@@ -445,35 +589,33 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
         d_old = b.D[r][If];
         m_old = b.mask[r][If];
     }
-    if (threadIdx.x < 64) {
-        // candidate list of the current look-ahead block (CD_NCAND == 64: one per lane)
-        int64_t cl = -1;
-        int nc = 0;
-        if (bsteps > 0) {
-            nc = st->ncand;
-            cl = cand[threadIdx.x];
-        }
-        Pick pk0 = cd_pick_wave(b, r, sr, cp, k);
-        if (pk0.status == PICK_GO) {
-            const unsigned long long hit = __ballot((int)threadIdx.x < nc && cl == pk0.p);
-            pk0.slot = hit ? __ffsll((long long)hit) - 1 : -1;
-        }
-        if (threadIdx.x == 0) spk = pk0;
+    // candidate list of the current look-ahead block (CD_NCAND == 64: one per lane of wave 0)
+    int64_t cl = -1;
+    int nc = 0;
+    if (bsteps > 0 && threadIdx.x < 64) {
+        nc = st->ncand;
+        cl = cand[threadIdx.x];
     }
-    __syncthreads();
-    const Pick pk = spk;
+    if (kdone < k) return;
+    Pick pk = cd_pick<CD_NT>(b, r, sr, cp, k, psh);
     if (pk.status != PICK_GO) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->k = k;
             st->dmax = pk.mx;
             st->status = pk.status;
+            st->kdone = k;
             st->done = 1;
         }
         return;
     }
     const int64_t p = pk.p;
     const double sq = sqrt(pk.dp);
-    const int slot = pk.slot;
+    if (threadIdx.x < 64) {
+        const unsigned long long hit = __ballot((int)threadIdx.x < nc && cl == p);
+        if (threadIdx.x == 0) sslot = hit ? __ffsll((long long)hit) - 1 : -1;
+    }
+    __syncthreads();
+    const int slot = sslot;
     // this row's entry of the pivot column (residual from the look-ahead pass on a hit),
     // issued before the pivot-row gather so the two loads overlap
     double cfin = 0.0;
@@ -562,46 +704,36 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     for (int v = 0; v < VW; ++v) red[jg][VW * rl + v] = acc[v];
     __syncthreads();
     const int w = 1 - r;
-    double mx = -INFINITY, mn = INFINITY;
-    int64_t ix = INT64_MAX;
-    if (threadIdx.x < CD_TILE && If < cp.npairs) {
+    if (threadIdx.x < CD_TILE) {                         // wave 0: the tile's 64 rows
         const int64_t I = If;
-        double l, dn;
-        unsigned char m = m_old;
-        if (m) {
-            l = 0.0;                          // earlier pivot: exactly zero
-            dn = d_old;
-        } else if (I == p) {
-            l = sq;                           // the pivot's own entry
-            dn = 0.0;
-            m = 1;
-        } else {
-            double c = cfin;
-            double s = 0.0;
+        bool active = false;
+        double dn = 0.0;
+        if (I < cp.npairs) {
+            double l;
+            unsigned char m = m_old;
+            if (m) {
+                l = 0.0;                          // earlier pivot: exactly zero
+                dn = d_old;
+            } else if (I == p) {
+                l = sq;                           // the pivot's own entry
+                dn = 0.0;
+                m = 1;
+            } else {
+                double s = 0.0;
 #pragma unroll
-            for (int g = 0; g < JG; ++g) s += red[g][threadIdx.x];
-            c -= s;
-            l = c / sq;
-            dn = d_old - l * l;
-            mx = mn = dn;
-            ix = I;
+                for (int g = 0; g < JG; ++g) s += red[g][threadIdx.x];
+                l = (cfin - s) / sq;
+                dn = d_old - l * l;
+                active = true;
+            }
+            L[k * ldl + I] = l;
+            b.D[w][I] = dn;
+            b.mask[w][I] = m;
         }
-        L[k * ldl + I] = l;
-        b.D[w][I] = dn;
-        b.mask[w][I] = m;
-    }
-    block_argmax<CD_NT>(mx, ix, shv, shi);
-    mn = block_min<CD_NT>(mn, shd);
-    if (threadIdx.x == 0) {
-        b.tmax[w][blockIdx.x] = mx;
-        b.targ[w][blockIdx.x] = ix;
-        b.tmin[w][blockIdx.x] = mn;
-        const int64_t sidx = blockIdx.x / b.tps;
-        if (mx != -INFINITY) atomicMax(&b.smax[sw][sidx], okey(mx));
-        if (mn != INFINITY) atomicMin(&b.smin[sw][sidx], okey(mn));
+        tile_record(b, w, sw, cp, blockIdx.x, active, dn);
     }
     if (blockIdx.x == 0) {
-        if (threadIdx.x < CD_NSUP) {
+        if (!b.flat && threadIdx.x < CD_NSUP) {
             b.smax[sz][threadIdx.x] = 0ull;
             b.smin[sz][threadIdx.x] = ~0ull;
         }
@@ -618,59 +750,33 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     }
 }
 
-// Look-ahead block start (one block): candidates = this step's pivot, then the argmax rows
-// of the tiles whose largest residual diagonal is among the top CD_NCAND-1 (threshold from
-// a 4-pass radix select on the IEEE bits of the tile maxima; ties at the threshold resolved
-// by lowest tile index), in a deterministic order.
-__global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams cp, int r, int sr, int64_t k,
-                                                            CdState *st, int64_t *__restrict__ cand)
+// Boundary of the top `want` nonzero keys held in registers (KPT per thread, 0 = no key):
+// four 8-bit radix passes over the key bits; returns the top 32 bits of the boundary key.
+// Every thread of the block calls it.
+template <int NT, int KPT>
+__device__ unsigned long long radix_boundary(const unsigned long long (&u)[KPT], int want, unsigned int *hist,
+                                             unsigned long long *s_prefix, int *s_need)
 {
-    __shared__ int shs[CD_AUX_NT / 64 + 1];
-    __shared__ unsigned int hist[256];
-    __shared__ unsigned long long s_prefix;
-    __shared__ int s_need;
-    __shared__ Pick spk;
-    if (st->done) return;
-    if (threadIdx.x < 64) {
-        const Pick pk0 = cd_pick_wave(b, r, sr, cp, k);
-        if (threadIdx.x == 0) spk = pk0;
-    }
-    __syncthreads();
-    const Pick pk = spk;
-    if (pk.status != PICK_GO) {                  // the step kernel records the termination
-        if (threadIdx.x == 0) st->ncand = 0;     // gather and pass have nothing to do
-        return;
-    }
-    const int64_t p = pk.p;
-    const int want = CD_NCAND - 1;
-    const int64_t ntile = b.ntile;
-    const double *tmax = b.tmax[r];
-    const int64_t *targ = b.targ[r];
-    auto key = [&](int64_t t) -> unsigned long long {
-        double v = tmax[t];
-        if (!(v > 0.0) || targ[t] == p) return 0ull;
-        return (unsigned long long)__double_as_longlong(v);
-    };
     if (threadIdx.x == 0) {
-        s_prefix = 0ull;
-        s_need = want;
+        *s_prefix = 0ull;
+        *s_need = want;
     }
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 56 - 8 * pass;
-        for (int q = threadIdx.x; q < 256; q += CD_AUX_NT) hist[q] = 0;
+        for (int q = threadIdx.x; q < 256; q += NT) hist[q] = 0;
         __syncthreads();
-        const unsigned long long prefix = s_prefix;
-        for (int64_t t = threadIdx.x; t < ntile; t += CD_AUX_NT) {
-            unsigned long long u = key(t);
-            if (u == 0ull) continue;
-            if (pass > 0 && (u >> (shift + 8)) != prefix) continue;
-            atomicAdd(&hist[(u >> shift) & 0xFF], 1u);
+        const unsigned long long prefix = *s_prefix;
+#pragma unroll
+        for (int e = 0; e < KPT; ++e) {
+            if (u[e] == 0ull) continue;
+            if (pass > 0 && (u[e] >> (shift + 8)) != prefix) continue;
+            atomicAdd(&hist[(u[e] >> shift) & 0xFF], 1u);
         }
         __syncthreads();
         if (threadIdx.x < 64) {
             // digit q = the largest with (count of keys >= q) >= need; need -= count above q.
             // Lane l holds bins 4l..4l+3; suffix sums over lanes locate q's lane.
-            const int l = threadIdx.x, need = s_need;
+            const int l = threadIdx.x, need = *s_need;
             const int h0 = hist[4 * l], h1 = hist[4 * l + 1], h2 = hist[4 * l + 2], h3 = hist[4 * l + 3];
             const int own = h0 + h1 + h2 + h3;
             int S = own;                                   // sum over lanes >= l
@@ -681,8 +787,8 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
             const unsigned long long ok = __ballot(S >= need);
             if (ok == 0ull) {
                 if (l == 0) {                              // fewer keys than wanted: take all
-                    s_prefix = prefix << 8;
-                    s_need = need - (S - h0);
+                    *s_prefix = prefix << 8;
+                    *s_need = need - (S - h0);
                 }
             } else if (l == 63 - __clzll((long long)ok)) {
                 int rem = need - (S - own);
@@ -691,41 +797,125 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
                 else if (h2 >= (rem -= h3)) q = 2;
                 else if (h1 >= (rem -= h2)) q = 1;
                 else { rem -= h1; q = 0; }
-                s_prefix = (prefix << 8) | (unsigned long long)(4 * l + q);
-                s_need = rem;
+                *s_prefix = (prefix << 8) | (unsigned long long)(4 * l + q);
+                *s_need = rem;
             }
         }
         __syncthreads();
     }
-    const unsigned long long thr = s_prefix;     // top 32 bits of the boundary key
-    const int64_t per = (ntile + CD_AUX_NT - 1) / CD_AUX_NT;
-    const int64_t t0 = threadIdx.x * per, t1 = min(ntile, t0 + per);
+    return *s_prefix;
+}
+
+// Writes the ids of the top `want` keys to out[] in a deterministic order (keys above the
+// boundary first, then boundary keys, each by id); ids are threadIdx.x * KPT + e.  Returns
+// how many were written.
+template <int NT, int KPT, typename F>
+__device__ int select_top(const unsigned long long (&u)[KPT], int want, unsigned int *hist,
+                          unsigned long long *s_prefix, int *s_need, int *shs, F &&emit)
+{
+    const unsigned long long thr = radix_boundary<NT, KPT>(u, want, hist, s_prefix, s_need);
     int na = 0, nbd = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        unsigned long long u = key(t);
-        if (u == 0ull) continue;
-        if ((u >> 32) > thr) ++na;
-        else if ((u >> 32) == thr) ++nbd;
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+        if (u[e] == 0ull) continue;
+        if ((u[e] >> 32) > thr) ++na;
+        else if ((u[e] >> 32) == thr) ++nbd;
     }
     int tot_a, tot_b;
-    int ia = block_excl_scan<CD_AUX_NT>(na, shs, &tot_a);
-    int ib = block_excl_scan<CD_AUX_NT>(nbd, shs, &tot_b);
+    int ia = block_excl_scan<NT>(na, shs, &tot_a);
+    int ib = block_excl_scan<NT>(nbd, shs, &tot_b);
     const int nabove = min(tot_a, want);
-    for (int64_t t = t0; t < t1; ++t) {
-        unsigned long long u = key(t);
-        if (u == 0ull) continue;
-        if ((u >> 32) > thr) {
-            if (ia < want) cand[1 + ia] = targ[t];
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+        if (u[e] == 0ull) continue;
+        const int id = threadIdx.x * KPT + e;
+        if ((u[e] >> 32) > thr) {
+            if (ia < want) emit(ia, id);
             ++ia;
-        } else if ((u >> 32) == thr) {
-            if (nabove + ib < want) cand[1 + nabove + ib] = targ[t];
+        } else if ((u[e] >> 32) == thr) {
+            if (nabove + ib < want) emit(nabove + ib, id);
             ++ib;
         }
     }
+    return min(nabove + tot_b, want);
+}
+
+// Look-ahead block start (one block): candidates = this step's pivot, then the rows with
+// the largest residual diagonals (CD_NCAND - 1 of them).  Those rows lie in the CD_NCAND
+// tiles with the largest tile maxima, so the tiles are selected first (keys from the tile
+// records), then the rows of those tiles; both selections are exact top-k on the IEEE
+// bits (ties at the boundary by lowest position), deterministic.
+__global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams cp, int r, int sr, int64_t k,
+                                                            CdState *st, int64_t *__restrict__ cand)
+{
+    constexpr int TK = CD_CAND_MAXTILE / CD_AUX_NT;           // tile keys per thread
+    constexpr int RK = CD_NCAND * CD_TILE / CD_AUX_NT;        // row keys per thread
+    __shared__ PickShared psh;
+    __shared__ unsigned int hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_need;
+    __shared__ int shs[CD_AUX_NT / 64 + 1];
+    __shared__ int64_t stile[CD_NCAND];
+    if (st->done) return;
+    const Pick pk = cd_pick<CD_AUX_NT>(b, r, sr, cp, k, psh);
+    if (pk.status != PICK_GO) {                  // the step kernel records the termination
+        if (threadIdx.x == 0) st->ncand = 0;     // gather and pass have nothing to do
+        return;
+    }
+    const int64_t p = pk.p;
+    const TileStat *ts = b.ts[r];
+    unsigned long long u[TK];
+#pragma unroll
+    for (int e = 0; e < TK; ++e) {
+        const int64_t t = (int64_t)threadIdx.x * TK + e;
+        const double v = t < b.ntile ? ts[t].mx : 0.0;
+        u[e] = v > 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
+    }
+    const int ntsel = select_top<CD_AUX_NT, TK>(u, CD_NCAND, hist, &s_prefix, &s_need, shs,
+                                                 [&](int pos, int id) { stile[pos] = id; });
+    __syncthreads();
+    unsigned long long v[RK];
+#pragma unroll
+    for (int e = 0; e < RK; ++e) {
+        const int i = threadIdx.x * RK + e;
+        const int slot = i / CD_TILE;
+        v[e] = 0ull;
+        if (slot < ntsel) {
+            const int64_t I = stile[slot] * CD_TILE + i % CD_TILE;
+            if (I < cp.npairs && I != p && !b.mask[r][I]) {
+                const double d = b.D[r][I];
+                if (d > 0.0) v[e] = (unsigned long long)__double_as_longlong(d);
+            }
+        }
+    }
+    const int nrow = select_top<CD_AUX_NT, RK>(v, CD_NCAND - 1, hist, &s_prefix, &s_need, shs, [&](int pos, int id) {
+        cand[1 + pos] = stile[id / CD_TILE] * CD_TILE + id % CD_TILE;
+    });
     if (threadIdx.x == 0) {
         cand[0] = p;
-        st->ncand = 1 + min(nabove + tot_b, want);
+        st->ncand = 1 + nrow;
     }
+}
+
+// Base of the candidate residual columns: R[c][I] = V[I][cand_c] (grid: row blocks x
+// candidates); the pass then subtracts the projection on the earlier vectors.
+template <bool DENSE>
+__global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, int64_t ldv, int64_t npairs,
+                                  const CdState *__restrict__ st, const int64_t *__restrict__ cand,
+                                  double *__restrict__ R, int64_t ldr)
+{
+    const int c = blockIdx.y;
+    if (st->done || c >= st->ncand) return;
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= npairs) return;
+    const int64_t q = cand[c];
+    double v;
+    if constexpr (DENSE) {
+        v = V[q * ldv + I];
+    } else {
+        v = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[q], pt.Px[q], pt.Py[q], pt.Pz[q], pt.K[q]);
+    }
+    R[(int64_t)c * ldr + I] = v;
 }
 
 // P[j][c] = L[j][cand_c], j < k0, c < ncand (one thread per entry)
@@ -740,16 +930,21 @@ __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int6
     P[e] = c < st->ncand ? L[j * ldl + cand[c]] : 0.0;
 }
 
-// R[c][I] = V[I][cand_c] - sum_{j<k0} L[j][I] P[j][c] for all candidates, one read of L.
+// R[c][I] -= sum_{j<k0} L[j][I] P[j][c] for all candidates (R holds V[I][cand_c]), one
+// read of L.
 // Block = 64 rows x 4 waves; wave w: rows [16w, 16w+16) x 64 candidates = 4 f64 MFMA blocks
 // (v_mfma_f64_16x16x4f64: A = L rows (lane l: row l%16, k l/16), B = P from LDS).
-template <bool DENSE>
-__global__ __launch_bounds__(256) void cd_pass_kernel(
-    PairTable pt, const double *__restrict__ V, int64_t ldv, const double *__restrict__ L, int64_t ldl,
-    int64_t npairs, int64_t k0, const CdState *__restrict__ st, const int64_t *__restrict__ cand,
-    const double *__restrict__ P, double *__restrict__ R, int64_t ldr)
+// Software-pipelined over chunks of CD_PASS_JC vectors: the L fragments and P rows of
+// chunk c+1 are loaded into registers while the MFMAs of chunk c run; P goes to the other
+// half of a double-buffered LDS tile after them, so one barrier per chunk suffices.
+__global__ __launch_bounds__(256) void cd_pass_kernel(const double *__restrict__ L, int64_t ldl, int64_t npairs,
+                                                      int64_t k0, const CdState *__restrict__ st,
+                                                      const double *__restrict__ P, double *__restrict__ R,
+                                                      int64_t ldr)
 {
-    __shared__ double sp[CD_PASS_JC][CD_NCAND];
+    constexpr int NS = CD_PASS_JC / 4;                     // MFMA k-steps per chunk
+    constexpr int NPT = CD_PASS_JC * CD_NCAND / 256;       // P entries per thread per chunk
+    __shared__ double sp[2][CD_PASS_JC][CD_NCAND];
     if (st->done || st->ncand == 0) return;
     const int nc = st->ncand;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -757,46 +952,80 @@ __global__ __launch_bounds__(256) void cd_pass_kernel(
     const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
     const int64_t rowA = tile0 + 16 * w + r16;
     const bool rowok = rowA < npairs;
+    const int64_t nchunk = (k0 + CD_PASS_JC - 1) / CD_PASS_JC;
     doublex4 acc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = doublex4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t j0 = 0; j0 < k0; j0 += CD_PASS_JC) {
-        const int nj = (int)min((int64_t)CD_PASS_JC, k0 - j0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < CD_PASS_JC * CD_NCAND; t += 256) {
-            const int jj = t / CD_NCAND, cc = t % CD_NCAND;
-            sp[jj][cc] = jj < nj ? P[(j0 + jj) * CD_NCAND + cc] : 0.0;
-        }
-        __syncthreads();
-        double a[CD_PASS_JC / 4];
+
+    auto load_a = [&](int64_t c, double *a) {
+        const int64_t j0 = c * CD_PASS_JC;
 #pragma unroll
-        for (int s = 0; s < CD_PASS_JC / 4; ++s) {
-            const int jj = 4 * s + g;
-            a[s] = (rowok && jj < nj) ? L[(j0 + jj) * ldl + rowA] : 0.0;
+        for (int s = 0; s < NS; ++s) {
+            const int64_t j = j0 + 4 * s + g;
+            a[s] = (rowok && j < k0) ? L[j * ldl + rowA] : 0.0;
         }
+    };
+    auto load_p = [&](int64_t c, double *pn) {
+        const int64_t j0 = c * CD_PASS_JC;
 #pragma unroll
-        for (int s = 0; s < CD_PASS_JC / 4; ++s)
+        for (int i = 0; i < NPT; ++i) {
+            const int t = threadIdx.x + 256 * i;
+            const int64_t j = j0 + t / CD_NCAND;
+            pn[i] = j < k0 ? P[j * CD_NCAND + t % CD_NCAND] : 0.0;
+        }
+    };
+    auto store_p = [&](int buf, const double *pn) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int t = threadIdx.x + 256 * i;
+            sp[buf][t / CD_NCAND][t % CD_NCAND] = pn[i];
+        }
+    };
+    auto mfma_chunk = [&](int buf, const double *a) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sp[4 * s + g][16 * nb + r16], acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sp[buf][4 * s + g][16 * nb + r16], acc[nb],
+                                                               0, 0, 0);
+    };
+
+    double a0[NS], a1[NS], pn[NPT];
+    if (nchunk > 0) {
+        load_a(0, a0);
+        load_p(0, pn);
+        store_p(0, pn);
+    }
+    for (int64_t c = 0; c < nchunk; c += 2) {
+        // chunk c from (a0, sp[0]); prefetch chunk c+1 into (a1, sp[1])
+        __syncthreads();
+        const bool n1 = c + 1 < nchunk;
+        if (n1) {
+            load_a(c + 1, a1);
+            load_p(c + 1, pn);
+        }
+        mfma_chunk(0, a0);
+        if (n1) store_p(1, pn);
+        if (!n1) break;
+        // chunk c+1 from (a1, sp[1]); prefetch chunk c+2 into (a0, sp[0])
+        __syncthreads();
+        const bool n2 = c + 2 < nchunk;
+        if (n2) {
+            load_a(c + 2, a0);
+            load_p(c + 2, pn);
+        }
+        mfma_chunk(1, a1);
+        if (n2) store_p(0, pn);
     }
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
         const int c = 16 * nb + r16;
         if (c >= nc) continue;
-        const int64_t q = cand[c];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t I = tile0 + 16 * w + g + 4 * e;     // f64 MFMA output rows g + 4e
             if (I >= npairs) continue;
-            double base;
-            if constexpr (DENSE) {
-                base = V[q * ldv + I];
-            } else {
-                base = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[q], pt.Px[q], pt.Py[q],
-                              pt.Pz[q], pt.K[q]);
-            }
-            R[(int64_t)c * ldr + I] = base - acc[nb][e];
+            R[(int64_t)c * ldr + I] -= acc[nb][e];            // base V[I][cand_c] from cd_candcol
         }
     }
 }
@@ -858,8 +1087,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     if (!dense) CDS_CALL(setup_pairs(ctx, nbf, centres, alpha, &pt));
 
     const int vw = (ldl % 2 == 0 && cds_aligned(L, 16)) ? 2 : 1;
-    const int bsteps = ctx->cd_lookahead;
     const int64_t ntile = cds_ceil_div(npairs, CD_TILE);
+    const int bsteps = ntile <= CD_CAND_MAXTILE ? ctx->cd_lookahead : 0;
     const int64_t tps = cds_ceil_div(ntile, CD_NSUP);
     const int64_t ldr = cds_ceil_div(npairs, 64) * 64;
 
@@ -867,7 +1096,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     void *w_part, *w_tile, *w_mask, *w_state;
     const size_t nP = (size_t)max_vec * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
     CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR) * 8 + 256, &w_part));
-    CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)6 * ntile * 8 + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
+    CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
     CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)2 * npairs, &w_mask));
     CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + 64, &w_state));
     double *D1 = (double *)w_part;
@@ -879,20 +1108,16 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     bf.D[1] = D1;
     bf.mask[0] = (unsigned char *)w_mask;
     bf.mask[1] = bf.mask[0] + npairs;
-    double *tb = (double *)w_tile;
-    bf.tmax[0] = tb;
-    bf.tmax[1] = tb + ntile;
-    bf.tmin[0] = tb + 2 * ntile;
-    bf.tmin[1] = tb + 3 * ntile;
-    bf.targ[0] = (int64_t *)(tb + 4 * ntile);
-    bf.targ[1] = (int64_t *)(tb + 5 * ntile);
-    unsigned long long *sb = (unsigned long long *)(tb + 6 * ntile);
+    bf.ts[0] = (TileStat *)w_tile;
+    bf.ts[1] = bf.ts[0] + ntile;
+    unsigned long long *sb = (unsigned long long *)(bf.ts[1] + ntile);
     for (int i = 0; i < 3; ++i) {
         bf.smax[i] = sb + i * CD_NSUP;
         bf.smin[i] = sb + (3 + i) * CD_NSUP;
     }
     bf.ntile = ntile;
     bf.tps = tps;
+    bf.flat = (ntile <= (int64_t)CD_NT * CD_TPT && !ctx->cd_hier_search) ? 1 : 0;
     double *dscratch = (double *)(sb + 6 * CD_NSUP);
     CdState *st = (CdState *)w_state;
     int64_t *cand = (int64_t *)(st + 1);
@@ -925,6 +1150,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     CDS_HIP(ctx, hipMemsetAsync(bf.smin[0], 0xff, (size_t)3 * CD_NSUP * 8, ctx->stream));
     CdState st0 = {};
     st0.k = nvec_in;
+    st0.kdone = INT64_MAX;
     *(CdState *)hp = st0;
     CDS_HIP(ctx, hipMemcpyAsync(st, hp, sizeof(CdState), hipMemcpyHostToDevice, ctx->stream));
     if (nvec_in == 0) {
@@ -934,13 +1160,15 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                            0, ctx->stream, nvec_in, piv, npairs, bf.mask[0]);
         CDS_LAUNCHED(ctx);
     }
-    hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)ntile), dim3(CD_TILE), 0, ctx->stream, bf, npairs);
+    hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)ntile), dim3(CD_TILE), 0, ctx->stream, bf, cp);
     CDS_LAUNCHED(ctx);
 
     int64_t k = nvec_in, k0 = nvec_in;
-    int batch = 8;
+    int batch = 16;                     // batch ends fall on look-ahead block starts (16, 32, 64)
     CdState hs = {};
     const dim3 grid((unsigned)ntile);
+    CdsTimer tk;
+    bool run_timed = false;
     for (;;) {
         CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
         CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -958,6 +1186,10 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             const int r = (int)(s & 1), sr = (int)(s % 3), sw = (int)((s + 1) % 3), sz = (int)((s + 2) % 3);
             if (bsteps > 0 && s % bsteps == 0 && k < max_vec) {
                 // look-ahead block start: candidates, their rows, one pass over L
+                if (run_timed) {
+                    CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
+                    run_timed = false;
+                }
                 k0 = k;
                 hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
                                    st, cand);
@@ -968,22 +1200,28 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                        (const int64_t *)cand, Pc);
                     CDS_LAUNCHED(ctx);
                 }
+                const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCAND);
+                if (dense)
+                    hipLaunchKernelGGL(cd_candcol_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
+                                       (const CdState *)st, (const int64_t *)cand, Rc, ldr);
+                else
+                    hipLaunchKernelGGL(cd_candcol_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
+                                       (const CdState *)st, (const int64_t *)cand, Rc, ldr);
+                CDS_LAUNCHED(ctx);
                 CdsTimer tp;
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
-                if (dense)
-                    hipLaunchKernelGGL(cd_pass_kernel<true>, grid, dim3(256), 0, ctx->stream, pt, V, ldv,
-                                       (const double *)L, ldl, npairs, k, (const CdState *)st,
-                                       (const int64_t *)cand, (const double *)Pc, Rc, ldr);
-                else
-                    hipLaunchKernelGGL(cd_pass_kernel<false>, grid, dim3(256), 0, ctx->stream, pt, V, ldv,
-                                       (const double *)L, ldl, npairs, k, (const CdState *)st,
-                                       (const int64_t *)cand, (const double *)Pc, Rc, ldr);
+                hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs, k,
+                                   (const CdState *)st, (const double *)Pc, Rc, ldr);
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
                 ctx->stats.n_cd_pass_launch += 1;
             }
-            CdsTimer tk;
-            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tk));
+            // one event pair around each run of consecutive step launches (a pair around
+            // every launch would add its own overhead to each)
+            if (ctx->kernel_timing && !run_timed) {
+                CDS_CALL(cds_timer_start(ctx, &tk));
+                run_timed = true;
+            }
             if (dense) {
                 if (vw == 2)
                     launch_step<2, true>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
@@ -1000,8 +1238,11 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                           ldr, cand, st, piv);
             }
             CDS_LAUNCHED(ctx);
-            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
             ctx->stats.n_cd_step_launch += 1;
+        }
+        if (run_timed) {
+            CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
+            run_timed = false;
         }
         if (batch < 64) batch *= 2;
     }
@@ -1082,6 +1323,15 @@ int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps)
     if (block_steps < 0 || block_steps > 256)
         return cds_fail(ctx, CDS_EINVAL, "block_steps must be in [0, 256]");
     ctx->cd_lookahead = block_steps;
+    return CDS_OK;
+}
+
+int cds_set_cd_pivot_search(cds_ctx *ctx, int32_t hierarchical)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (hierarchical != 0 && hierarchical != 1)
+        return cds_fail(ctx, CDS_EINVAL, "hierarchical must be 0 or 1");
+    ctx->cd_hier_search = hierarchical;
     return CDS_OK;
 }
 

@@ -56,6 +56,7 @@ struct cds_ctx {
     bool broken = false;
     bool kernel_timing = false;      // time every CD step / pass launch with events
     int cd_lookahead = 16;           // Cholesky look-ahead block length (0: plain steps)
+    int cd_hier_search = 0;          // 1: pivot search always through super-tile keys
 };
 
 // error helpers -------------------------------------------------------------

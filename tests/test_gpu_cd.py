@@ -121,6 +121,23 @@ def test_cd_plain_equals_lookahead(cds, name, delta):
     assert torch.all((la.L - plain.L).abs().max(dim=1).values <= tol)
 
 
+@pytest.mark.parametrize("name,delta,lookahead", [("plain", 1e-8, 16), ("c60", 1e-6, 16), ("c60", 1e-4, 0)])
+def test_cd_hierarchical_search(cds, name, delta, lookahead):
+    # pivot search through the super-tile keys (the path of large pair counts) on workloads
+    # small enough for the oracle: same pivots, same vectors to rounding
+    w = workload(name)
+    log(f"cd hierarchical pivot search {name} delta={delta} lookahead={lookahead}")
+    ctx = cds.Context(0)
+    ctx.set_cd_pivot_search(True)
+    ctx.set_cd_lookahead(lookahead)
+    ref = oracle_cd(name, delta)
+    got = cds.cholesky(delta, centres=_dev(w.centres), alpha=_dev(w.alpha), ctx=ctx)
+    assert got.status == 0 and got.nvec == ref.M
+    assert np.array_equal(got.piv[: got.nvec].cpu().numpy(), ref.piv)
+    tol = cd_tolerance(ref, E.eri_diagonal(w.centres, w.alpha).max())
+    assert np.all(np.abs(got.L.cpu().numpy().T - ref.L).max(axis=0) <= tol)
+
+
 def test_cd_cap_status_and_resume(cds):
     w = workload("plain")
     log("cd cap plain")
