@@ -209,6 +209,21 @@ def main():
             "max_err_meV_vs_fp64": round(err_mev, 6),
             "newton_iters_max": int(qp_p.iters.max()),
         }
+    # MP2 correlation energy, Eq. (MP2), from the same Bvo block in each precision
+    mp2_report = {}
+    e_ref = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        B = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
+        C.mp2_energy(B, eps, ctx=ctx)            # warm
+        ctx.reset_stats()
+        e = C.mp2_energy(B, eps, ctx=ctx)
+        s2 = ctx.stats()
+        if prec == "fp64":
+            e_ref = e
+        tf = s2["flops_mp2"] / (s2["t_mp2_ms"] / 1e3) / 1e12
+        mp2_report[prec] = {"energy_Eh": e, "ms": round(s2["t_mp2_ms"], 3), "tflops": round(tf, 2),
+                            "mfma_frac": round(tf * (3 if prec == "bf16x3" else 1) / PEAKS_TFLOPS[prec], 4),
+                            "rel_err_vs_fp64": abs(e - e_ref) / abs(e_ref)}
     for prec in ("fp32", "bf16x3"):
         prec_report[prec]["contract_speedup_vs_fp64"] = round(
             prec_report["fp64"]["contract_ms"] / prec_report[prec]["contract_ms"], 2)
@@ -237,6 +252,7 @@ def main():
         "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
                       ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")},
         "precision": prec_report,
+        "mp2": mp2_report,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline:

@@ -101,6 +101,8 @@ typedef struct cds_stats {
     int64_t n_cd_step_launch; /* step-kernel launches (a few past the last step
                                  return at once)                                */
     int64_t n_cd_pass_launch; /* look-ahead pass launches                       */
+    double t_mp2_ms;         /* MP2 energies (contraction + reduction)        */
+    double flops_mp2;        /* 2 nvec x rows x columns of the MP2 contractions */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -256,6 +258,25 @@ int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec,
                           const double *L, int64_t ldl, const double *C, int32_t nmo,
                           int32_t nocc, int32_t nsel, const int32_t *h_sel, int64_t ldk,
                           const void *Bsel_bar, const void *Bvo_bar, double *C_bar);
+
+/*
+ * MP2 correlation energy, Eq. (MP2) of Sec. II.A, from the transformed
+ * Cholesky block Bvo (layout and precision `prec` of cds_transform; ldk a
+ * multiple of 64) and the orbital energies eps (device double[nmo]):
+ *   E = sum_{i,j occ; a,b virt} (2 (ai|bj) - (aj|bi)) (ai|bj) / (e_i + e_j - e_a - e_b),
+ *   (ai|bj) = sum_K B^K_ai B^K_bj.
+ * The integrals are formed by the MFMA contraction in `prec` (FP32 storage for
+ * FP32 and BF16X3) in chunks of virtual orbitals; numerators, denominators and
+ * all sums in FP64 with a fixed summation order (deterministic).  Writes E to
+ * *h_energy (host) and synchronizes the stream.  1 <= nocc < nmo,
+ * nocc <= 1024.  Errors: CDS_EINVAL (nothing written), CDS_ENOMEM, CDS_EDEVICE.
+ */
+int cds_mp2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo, int32_t nocc,
+            const void *Bvo, const double *eps, double *h_energy);
+
+/* Device workspace the context holds now (bytes, all slots); it grows on
+ * demand and is released by cds_destroy. */
+int cds_workspace_bytes(const cds_ctx *ctx, size_t *out);
 
 #ifdef __cplusplus
 }

@@ -101,6 +101,11 @@ class Context:
         """Cholesky look-ahead block length (0: plain one-vector-per-step streaming)."""
         self.check(self.lib.cds_set_cd_lookahead(self.h, int(block_steps)))
 
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t(0)
+        self.check(self.lib.cds_workspace_bytes(self.h, ctypes.byref(n)))
+        return int(n.value)
+
     def set_cd_pivot_search(self, hierarchical: bool):
         """Cholesky pivot search: False = automatic (flat sweep up to 1024 tiles), True = always
         through the super-tile keys."""
@@ -331,6 +336,16 @@ def sigma2(B: BBlocks, eps: torch.Tensor, omega: np.ndarray, ctx: Context | None
     ctx.check(ctx.lib.cds_sigma2(ctx.h, B.prec, B.nvec, B.ldk, B.nmo, B.nocc, B.nsel, vp(B.sel), _ptr(B.Bsel),
                                  _ptr(B.Bvo), _ptr(eps), T, vp(omega), vp(s), vp(ds)))
     return s, ds
+
+
+def mp2_energy(B: BBlocks, eps: torch.Tensor, ctx: Context | None = None) -> float:
+    """MP2 correlation energy, Eq. (MP2), from the Bvo block of B (its precision)."""
+    _dev(eps, torch.float64, "eps")
+    ctx = ctx or context(eps.device.index or 0)
+    out = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.cds_mp2(ctx.h, B.prec, B.nvec, B.ldk, B.nmo, B.nocc, _ptr(B.Bvo), _ptr(eps),
+                              ctypes.byref(out)))
+    return float(out.value)
 
 
 @dataclasses.dataclass

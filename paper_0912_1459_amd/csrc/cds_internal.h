@@ -34,6 +34,8 @@ enum CdsSlot {
     WS_AD_G,        // adjoint: dSigma/dG weights
     WS_AD_TMP,      // adjoint scratch
     WS_AD_TMP2,
+    WS_MP_G,        // MP2: integral chunk
+    WS_MP_S,        // MP2: per-(a, b) sums
     WS_SLOTS
 };
 

@@ -147,6 +147,15 @@ void cds_destroy(cds_ctx *ctx)
 
 const char *cds_last_error(const cds_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int cds_workspace_bytes(const cds_ctx *ctx, size_t *out)
+{
+    if (!ctx || !out) return CDS_EINVAL;
+    size_t n = 0;
+    for (int i = 0; i < WS_SLOTS; ++i) n += ctx->ws_bytes[i];
+    *out = n;
+    return CDS_OK;
+}
+
 int cds_get_stats(const cds_ctx *ctx, cds_stats *out)
 {
     if (!ctx || !out) return CDS_EINVAL;
