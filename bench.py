@@ -228,6 +228,11 @@ def main():
         prec_report[prec]["contract_speedup_vs_fp64"] = round(
             prec_report["fp64"]["contract_ms"] / prec_report[prec]["contract_ms"], 2)
 
+    # the paper's spectral-window experiment in synthetic form (untimed): window orbitals,
+    # CD-4 ... CD-8 against CD-10, FP64, Newton Delta = 1e-5
+    from paper_0912_1459_amd import sweep as SW
+    sweep = SW.report(w, prec="fp64", conv=conv) if args.workload == "c60" else None
+
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -253,6 +258,7 @@ def main():
                       ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")},
         "precision": prec_report,
         "mp2": mp2_report,
+        "sweep": sweep,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline:

@@ -149,8 +149,9 @@ int cds_eri_columns(cds_ctx *ctx, int32_t nbf, const double *centres, const doub
  * Columns are evaluated on demand from the basis (no npairs^2 storage).
  *
  * Each step picks the pivot p = the lowest pair index I (not yet a pivot)
- * with D_I >= D_max - tau, where D is the residual diagonal and D_max its
- * largest non-pivot entry; forms c = V[:,p] - L[:, :k] L[p, :k]^T;
+ * with D_I >= D_max - min(tau, D_max / 100), where D is the residual diagonal
+ * and D_max its largest non-pivot entry (a tie window: symmetry-equivalent
+ * pairs have equal diagonals up to rounding); forms c = V[:,p] - L[:, :k] L[p, :k]^T;
  * L[:,k] = c / sqrt(D_p) with L[p,k] = sqrt(D_p) and exactly 0 on earlier
  * pivots; D -= L[:,k]^2; D_p = 0.  It stops when D_max <= delta, after
  * max_vec vectors, or when every pair is a pivot.

@@ -166,10 +166,12 @@ int orc_pivoted_cd(int64_t npairs, const double *V, int32_t nbf, const double *c
         if (!any) { status = 2; break; }
         if (dm <= delta) { status = 0; break; }
         if (k >= max_vec) { status = 1; break; }
-        /* pivot: lowest index within tau of the maximum */
+        /* pivot: lowest index within the tie window of the maximum; the window is tau
+         * but at most 1% of the maximum, so it stays a tie window as delta nears tau */
+        const double win = fmin(tau, 1e-2 * dm);
         int64_t p = -1;
         for (int64_t I = 0; I < npairs; ++I)
-            if (!is_piv[I] && D[I] >= dm - tau) { p = I; break; }
+            if (!is_piv[I] && D[I] >= dm - win) { p = I; break; }
         double dp = D[p];
         double sq = sqrt(dp);
         /* residual column c_I = V_Ip - sum_{j<k} L_Ij L_pj */

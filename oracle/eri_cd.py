@@ -101,7 +101,8 @@ class CDResult:
 
 
 def default_tau(diag_max: float) -> float:
-    """Tie window for the pivot choice: 1e-10 of the largest ERI diagonal."""
+    """Tie window for the pivot choice: 1e-10 of the largest ERI diagonal (the C code caps
+    it at 1% of the current largest residual diagonal)."""
     return 1e-10 * diag_max
 
 
@@ -129,6 +130,8 @@ def pivoted_cd(delta: float, *, V: np.ndarray | None = None, centres=None, alpha
     grow = max_vec is None
     if grow:
         max_vec = max(64, 12 * (nbf if nbf else int(np.sqrt(2 * npairs))))
+        if resume is not None:
+            max_vec = max(max_vec, 2 * resume.M)
     max_vec = min(max_vec, npairs)
     if resume is not None and resume._Lfull is not None and resume._Lfull.shape[1] >= max_vec:
         Lfull = resume._Lfull
@@ -153,7 +156,7 @@ def pivoted_cd(delta: float, *, V: np.ndarray | None = None, centres=None, alpha
     if psd_tol is None:
         psd_tol = 1e3 * np.finfo(np.float64).eps * dmx
     st = lib().orc_pivoted_cd(npairs, _p(V) if V is not None else None, nbf, cptr, aptr,
-                              float(delta), float(tau), float(psd_tol), int(max_vec), int(max_vec),
+                              float(delta), float(tau), float(psd_tol), int(max_vec), int(Lfull.shape[1]),
                               _p(Lfull), _p(piv), _p(D), _p(nvec), _p(dmax))
     M = int(nvec[0])
     res = CDResult(Lfull[:, :M], piv[:M].copy(), D, float(dmax[0]), int(st), Lfull)

@@ -3,7 +3,7 @@
 // columns of normalized s-Gaussians evaluated on demand (Eq. (integral),
 // closed form through the Boys function F0).
 //
-// Each step k picks the pivot p (lowest index within tau of the largest residual
+// Each step k picks the pivot p (lowest index within the tie window of the largest residual
 // diagonal), forms the residual column c = V[:,p] - sum_{j<k} L[j] L[j][p], sets
 // L[k] = c / sqrt(D_p) and updates D.  Done literally, step k streams k*npairs*8
 // bytes of L.  This implementation forms the same residual columns with a
@@ -17,7 +17,7 @@
 //                FP64 MFMA)
 //   every step k, ONE launch (cd_step), each 64-row block:
 //     - picks the pivot itself from the previous step's tile records (largest and
-//       smallest residual of each 64-row tile, and its lowest row within tau of its
+//       smallest residual of each 64-row tile, and its lowest row within the tie window of its
 //       largest): one sweep over all records, or for many tiles 64 super-tile maxima
 //       kept with order-preserving integer atomics first; every block reaches the
 //       same pivot;
@@ -71,7 +71,8 @@ struct CdState {
 };
 
 // Per 64-row tile, over its non-pivot rows: the largest and smallest residual diagonal,
-// and the lowest row whose residual is within tau of the largest (with that residual).
+// and the lowest row whose residual is within the tie window of the largest (with that
+// residual).
 struct TileStat {
     double mx, mn, dfirst;
     int64_t first;                      // -1: no non-pivot row
@@ -334,6 +335,10 @@ __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
     return v;
 }
 
+// Tie window of the pivot rule: tau, but at most 1% of the largest residual, so that near
+// the end of a decomposition to a threshold close to tau it still only separates ties.
+__device__ __forceinline__ double tie_window(double mx, double tau) { return fmin(tau, 1e-2 * mx); }
+
 __device__ __forceinline__ int pick_status(double mx, double mn, const CdParams &cp, int64_t k)
 {
     if (mn < -cp.psd_tol) return CDS_CD_NOTPSD;
@@ -383,7 +388,7 @@ __device__ Pick cd_pick_super(const CdBufs &b, int r, int sr, const CdParams &cp
     pk.slot = -1;
     pk.status = pick_status(mx, mn, cp, k);
     if (pk.status != PICK_GO) return pk;
-    const double thresh = mx - cp.tau;
+    const double thresh = mx - tie_window(mx, cp.tau);
     const unsigned long long bs = __ballot(v >= thresh);
     int64_t t = -1;
     if (bs) {
@@ -459,7 +464,7 @@ __device__ Pick cd_pick(const CdBufs &b, int r, int sr, const CdParams &cp, int6
     pk.slot = -1;
     pk.status = pick_status(mx, mn, cp, k);
     if (pk.status != PICK_GO) return pk;          // uniform over the block
-    const double thresh = mx - cp.tau;
+    const double thresh = mx - tie_window(mx, cp.tau);
     int64_t tf = INT64_MAX;
 #pragma unroll
     for (int i = CD_TPT - 1; i >= 0; --i)
@@ -505,14 +510,14 @@ __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, i
 }
 
 // Record of one 64-row tile from its rows' new residuals (one wave; `active` = a non-pivot
-// row): largest and smallest residual, and the lowest row within tau of the largest.
+// row): largest and smallest residual, and the lowest row within the tie window of the largest.
 __device__ __forceinline__ void tile_record(const CdBufs &b, int w, int sw, const CdParams &cp, int64_t tile,
                                             bool active, double dn)
 {
     const int l = threadIdx.x & 63;
     const double tmx = wave_max(active ? dn : -INFINITY);
     const double tmn = wave_min(active ? dn : INFINITY);
-    const unsigned long long fb = __ballot(active && dn >= tmx - cp.tau);
+    const unsigned long long fb = __ballot(active && dn >= tmx - tie_window(tmx, cp.tau));
     const int fl = fb ? __ffsll((long long)fb) - 1 : 0;
     const double df = __shfl(dn, fl, 64);
     if (l == 0) {
