@@ -59,7 +59,7 @@ def test_cd_dense_plain(cds, delta):
 
 
 @pytest.mark.parametrize("name,delta", [("plain", 1e-6), ("small_cage", 1e-6), ("c60", 1e-4),
-                                        ("c60", 1e-6)])
+                                        ("c60", 1e-6), ("c60", 1e-8)])
 def test_cd_on_demand(cds, name, delta):
     w = workload(name)
     log(f"cd on-demand {name} delta={delta}")
