@@ -43,6 +43,10 @@ def parse():
     return p.parse_args()
 
 
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def committed_traffic() -> dict:
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, per
     kernel, if the Cholesky source is unchanged since the counters were taken; else {}."""
@@ -103,18 +107,25 @@ def main():
     eps = torch.tensor(w.eps, device=dev)
     stream = torch.cuda.current_stream()
     ctx = C.Context(0, stream)
+    if args.workload == "large":
+        # C = S^-1/2 Q with lambda_min(S) ~ 2e-7: rounding inside an FP32 or split-bf16
+        # transform would be amplified ~1/lambda_min, so the transform runs in FP64 and only
+        # the blocks are rounded for the contraction
+        ctx.set_transform_fp64(True)
     nsel = len(w.targets)
-    max_vec = 12 * w.nbf
+    max_vec = (12 if args.workload == "c60" else 6) * w.nbf     # grows by resuming if short
 
     def step(prec):
-        cd = C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, ctx=ctx)
+        cd = C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, grow=True, ctx=ctx)
         B = C.transform(cd.Lbuf, cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
         qp = C.qp_solve(B, eps, conv=conv, mode="residues", ctx=ctx)
         return cd, B, qp
 
+    progress(f"{args.workload}: {w.npairs} pairs, warm-up")
     for _ in range(args.warmup):
         step(args.prec)
     torch.cuda.synchronize()
+    progress("timed steps")
 
     # timed region: K whole-path steps, no per-kernel events
     ctx.reset_stats()
@@ -135,6 +146,7 @@ def main():
 
     # the same K steps again with HIP events around every Cholesky step-kernel and pass
     # launch (on the library's stream): per-launch durations for the roofline
+    progress(f"{ms_per_step:.1f} ms per step; kernel-timing pass")
     ctx.reset_stats()
     ctx.set_kernel_timing(True)
     for _ in range(args.steps):
@@ -179,6 +191,7 @@ def main():
                     "avg_launch_us": round(avg * 1e6, 3),
                     "units": "pairs x (8 B per vector subtracted + 34..66 B) per launch"}
 
+    progress("precision report")
     # per-precision contraction throughput and accuracy against the FP64 GPU path
     ref_cd, ref_B, ref_qp = step("fp64")
     prec_report = {}
@@ -209,6 +222,28 @@ def main():
             "max_err_meV_vs_fp64": round(err_mev, 6),
             "newton_iters_max": int(qp_p.iters.max()),
         }
+    progress("backward pass")
+    # backward pass: adjoint of the solve (FP64 and FP32 blocks) and of the transform, for the
+    # cotangent of the sum of all quasi-particle energies
+    backward = {}
+    for prec in ("fp64", "fp32"):
+        B = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
+        qp_p = C.qp_solve(B, eps, conv=1e-10, mode="residues", ctx=ctx)
+        ob = np.ones(nsel)
+        C.qp_adjoint(B, eps, qp_p.omega, ob, ctx=ctx)                     # warm
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        gs, gv, ge = C.qp_adjoint(B, eps, qp_p.omega, ob, ctx=ctx)
+        torch.cuda.synchronize()
+        tb1 = time.perf_counter()
+        C.transform_adjoint(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, gs, gv, B.ldk, ctx=ctx)
+        torch.cuda.synchronize()
+        tb2 = time.perf_counter()
+        backward[prec] = {"qp_adjoint_ms": round((tb1 - tb0) * 1e3, 3),
+                          "transform_adjoint_ms": round((tb2 - tb1) * 1e3, 3)}
+        del B, gs, gv, ge
+
+    progress("MP2")
     # MP2 correlation energy, Eq. (MP2), from the same Bvo block in each precision
     mp2_report = {}
     e_ref = None
@@ -257,11 +292,12 @@ def main():
         "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
                       ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")},
         "precision": prec_report,
+        "backward": backward,
         "mp2": mp2_report,
         "sweep": sweep,
         "wall_s": round(wall, 3),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c60":
         out["cpu_baseline"] = cpu_baseline(w, delta, conv, args.cpu_targets)
     print(json.dumps(out))
 

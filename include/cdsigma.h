@@ -124,11 +124,17 @@ int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
  * subtract the vectors made since.  0 disables it (each step streams all of L).
  * Default 16; valid range [0, 256]. */
 int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
-/* Pivot search of the Cholesky steps: 0 (default) = one sweep over the records
- * of all 64-row tiles when there are at most 1024 tiles, else hierarchical;
- * 1 = always hierarchical (64 super-tile maxima, then tiles, then rows).  The
- * pivots are the same either way. */
-int cds_set_cd_pivot_search(cds_ctx *ctx, int32_t hierarchical);
+/* Cholesky code path by problem size: 0 (default) = automatic; 1 = the path of
+ * large pair counts at any size (pivot search through 64 super-tile maxima,
+ * then tiles, then rows, instead of one sweep over all 64-row tile records; four
+ * tiles per step block instead of one).  Automatic: the sweep up to 1024 tiles,
+ * one tile per block up to 1280 tiles.  Results are the same either way. */
+int cds_set_cd_large_path(cds_ctx *ctx, int32_t on);
+/* Working precision of cds_transform for FP32 and BF16X3 outputs: 0 (default)
+ * runs its GEMMs in the output precision; 1 runs them in FP64 and rounds only
+ * the output blocks (for ill-conditioned MO coefficients, where rounding inside
+ * the transform is amplified by about 1 / lambda_min of the overlap matrix). */
+int cds_set_transform_fp64(cds_ctx *ctx, int32_t on);
 /* Library version string (static). */
 const char *cds_version(void);
 

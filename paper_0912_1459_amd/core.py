@@ -106,10 +106,14 @@ class Context:
         self.check(self.lib.cds_workspace_bytes(self.h, ctypes.byref(n)))
         return int(n.value)
 
-    def set_cd_pivot_search(self, hierarchical: bool):
-        """Cholesky pivot search: False = automatic (flat sweep up to 1024 tiles), True = always
-        through the super-tile keys."""
-        self.check(self.lib.cds_set_cd_pivot_search(self.h, int(bool(hierarchical))))
+    def set_transform_fp64(self, on: bool):
+        """FP32/bf16x3 transforms computed in FP64 with only the output rounded (True)."""
+        self.check(self.lib.cds_set_transform_fp64(self.h, int(bool(on))))
+
+    def set_cd_large_path(self, on: bool):
+        """Cholesky code path of large pair counts (hierarchical pivot search, four tiles per
+        step block) at any size (True), or chosen by size (False)."""
+        self.check(self.lib.cds_set_cd_large_path(self.h, int(bool(on))))
 
 
 _default = {}

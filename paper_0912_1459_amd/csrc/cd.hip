@@ -49,6 +49,7 @@ constexpr int CD_NSUP = 64;             // super-tiles of the hierarchical pivot
 constexpr int CD_NCAND = 64;            // candidate residual columns per look-ahead block
 constexpr int CD_PASS_JC = 32;          // candidate-row entries staged per pass chunk
 constexpr int CD_TPT = 4;               // tile records per thread in the flat pivot search
+constexpr int CD_ONE_TILE_MAX = 1280;   // tiles up to which a step block holds one tile
 constexpr int CD_CAND_MAXTILE = 8192;   // tiles the candidate selection handles (look-ahead
                                         // is off above 8192 * 64 pairs)
 
@@ -544,29 +545,34 @@ __global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, CdParams 
     tile_record(b, 0, 0, cp, blockIdx.x, active, d);
 }
 
-// One Cholesky step (one launch).  Block = CD_TILE rows; thread (jg, rl): rows I0..I0+VW-1,
-// vectors j = jstart + jg, + JG, ...; partial sums combined in LDS in fixed order.
+// One Cholesky step (one launch).  Block = TB tiles (64 TB rows); thread (jg, rl): rows
+// I0..I0+VW-1, vectors j = jstart + jg, + JG, ...; partial sums combined in LDS in fixed
+// order; wave w finalizes tile w of the block.  TB > 1 for large pair counts, so that the
+// per-block pivot search runs once for several tiles and the grid fits the chip in one
+// round.
 // r/w: read/write parity of D, mask and tile records; sr/sw/sz: super-tile buffers read,
 // written (atomics) and reset for the step after next.  Loads that do not depend on the
 // pivot (the vectors made since the block start, D, mask, the candidate list) are issued
 // before the pivot search.
-template <int VW, bool DENSE>
+template <int VW, int TB, bool DENSE>
 __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     CdBufs b, CdParams cp, int r, int sr, int sw, int sz, int64_t k, int64_t k0, int bsteps,
     PairTable pt, const double *__restrict__ V, int64_t ldv, double *__restrict__ L, int64_t ldl,
     const double *__restrict__ R, int64_t ldr, const int64_t *__restrict__ cand, CdState *st,
     int64_t *__restrict__ piv)
 {
-    constexpr int RL = CD_TILE / VW;            // row lanes
+    constexpr int NR = CD_TILE * TB;            // rows per block
+    constexpr int RL = NR / VW;                 // row lanes
     constexpr int JG = CD_NT / RL;              // vector groups
-    constexpr int NPF = 2;                      // prefetched vectors per thread
+    constexpr int NPF = JG >= 8 ? 2 : 16 / JG;  // prefetched vectors per thread (a 16-step block)
+    static_assert(JG >= 1 && CD_NT % RL == 0 && TB * 64 <= CD_NT, "step kernel shape");
     __shared__ double sp[CD_PCHUNK];
-    __shared__ double red[JG][CD_TILE];
+    __shared__ double red[JG][NR];
     __shared__ PickShared psh;
     __shared__ int sslot;
     const int64_t kdone = st->kdone;
     const int rl = threadIdx.x % RL, jg = threadIdx.x / RL;
-    const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
+    const int64_t tile0 = (int64_t)blockIdx.x * NR;
     const int64_t I0 = tile0 + (int64_t)VW * rl;
     const bool rows_ok = I0 < cp.npairs;
     // prefetch (independent of the pivot)
@@ -587,10 +593,10 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
             }
         }
     }
-    const int64_t If = tile0 + threadIdx.x;              // finalize row of threads < CD_TILE
+    const int64_t If = tile0 + threadIdx.x;              // finalize row of threads < NR
     double d_old = 0.0;
     unsigned char m_old = 1;
-    if (threadIdx.x < CD_TILE && If < cp.npairs) {
+    if (threadIdx.x < NR && If < cp.npairs) {
         d_old = b.D[r][If];
         m_old = b.mask[r][If];
     }
@@ -624,7 +630,7 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     // this row's entry of the pivot column (residual from the look-ahead pass on a hit),
     // issued before the pivot-row gather so the two loads overlap
     double cfin = 0.0;
-    if (threadIdx.x < CD_TILE && If < cp.npairs && !m_old && If != p) {
+    if (threadIdx.x < NR && If < cp.npairs && !m_old && If != p) {
         if (slot >= 0) {
             cfin = R[(int64_t)slot * ldr + If];
         } else if constexpr (DENSE) {
@@ -709,7 +715,7 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     for (int v = 0; v < VW; ++v) red[jg][VW * rl + v] = acc[v];
     __syncthreads();
     const int w = 1 - r;
-    if (threadIdx.x < CD_TILE) {                         // wave 0: the tile's 64 rows
+    if (threadIdx.x < NR) {                              // wave t: tile t of the block
         const int64_t I = If;
         bool active = false;
         double dn = 0.0;
@@ -735,7 +741,8 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
             b.D[w][I] = dn;
             b.mask[w][I] = m;
         }
-        tile_record(b, w, sw, cp, blockIdx.x, active, dn);
+        const int64_t tile = (int64_t)blockIdx.x * TB + (threadIdx.x >> 6);
+        if (tile < b.ntile) tile_record(b, w, sw, cp, tile, active, dn);
     }
     if (blockIdx.x == 0) {
         if (!b.flat && threadIdx.x < CD_NSUP) {
@@ -1062,13 +1069,32 @@ int setup_pairs(cds_ctx *ctx, int32_t nbf, const double *centres, const double *
     return CDS_OK;
 }
 
-template <int VW, bool DENSE>
-void launch_step(cds_ctx *ctx, dim3 grid, const CdBufs &b, const CdParams &cp, int r, int sr, int sw, int sz,
+template <int VW, int TB, bool DENSE>
+void launch_step(cds_ctx *ctx, const CdBufs &b, const CdParams &cp, int r, int sr, int sw, int sz,
                  int64_t k, int64_t k0, int bsteps, const PairTable &pt, const double *V, int64_t ldv, double *L,
                  int64_t ldl, const double *R, int64_t ldr, const int64_t *cand, CdState *st, int64_t *piv)
 {
-    hipLaunchKernelGGL((cd_step_kernel<VW, DENSE>), grid, dim3(CD_NT), 0, ctx->stream, b, cp, r, sr, sw, sz, k,
-                       k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+    const dim3 grid((unsigned)cds_ceil_div(b.ntile, TB));
+    hipLaunchKernelGGL((cd_step_kernel<VW, TB, DENSE>), grid, dim3(CD_NT), 0, ctx->stream, b, cp, r, sr, sw, sz,
+                       k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+}
+
+// step-kernel shape: rows per thread (16-byte loads when the layout allows) and tiles per
+// block (4 once one tile per block would need more than one round of blocks on the chip)
+template <bool DENSE>
+void launch_step_any(cds_ctx *ctx, int vw, int tb, const CdBufs &b, const CdParams &cp, int r, int sr, int sw,
+                     int sz, int64_t k, int64_t k0, int bsteps, const PairTable &pt, const double *V, int64_t ldv,
+                     double *L, int64_t ldl, const double *R, int64_t ldr, const int64_t *cand, CdState *st,
+                     int64_t *piv)
+{
+    if (vw == 2 && tb == 4)
+        launch_step<2, 4, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+    else if (vw == 2)
+        launch_step<2, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+    else if (tb == 4)
+        launch_step<1, 4, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+    else
+        launch_step<1, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
 }
 
 int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
@@ -1092,6 +1118,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     if (!dense) CDS_CALL(setup_pairs(ctx, nbf, centres, alpha, &pt));
 
     const int vw = (ldl % 2 == 0 && cds_aligned(L, 16)) ? 2 : 1;
+    const int tb = (cds_ceil_div(npairs, CD_TILE) > CD_ONE_TILE_MAX || ctx->cd_large_path) ? 4 : 1;
     const int64_t ntile = cds_ceil_div(npairs, CD_TILE);
     const int bsteps = ntile <= CD_CAND_MAXTILE ? ctx->cd_lookahead : 0;
     const int64_t tps = cds_ceil_div(ntile, CD_NSUP);
@@ -1122,7 +1149,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     }
     bf.ntile = ntile;
     bf.tps = tps;
-    bf.flat = (ntile <= (int64_t)CD_NT * CD_TPT && !ctx->cd_hier_search) ? 1 : 0;
+    bf.flat = (ntile <= (int64_t)CD_NT * CD_TPT && !ctx->cd_large_path) ? 1 : 0;
     double *dscratch = (double *)(sb + 6 * CD_NSUP);
     CdState *st = (CdState *)w_state;
     int64_t *cand = (int64_t *)(st + 1);
@@ -1227,21 +1254,12 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 CDS_CALL(cds_timer_start(ctx, &tk));
                 run_timed = true;
             }
-            if (dense) {
-                if (vw == 2)
-                    launch_step<2, true>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
-                                         ldr, cand, st, piv);
-                else
-                    launch_step<1, true>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
-                                         ldr, cand, st, piv);
-            } else {
-                if (vw == 2)
-                    launch_step<2, false>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
-                                          ldr, cand, st, piv);
-                else
-                    launch_step<1, false>(ctx, grid, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
-                                          ldr, cand, st, piv);
-            }
+            if (dense)
+                launch_step_any<true>(ctx, vw, tb, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc, ldr,
+                                      cand, st, piv);
+            else
+                launch_step_any<false>(ctx, vw, tb, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc, ldr,
+                                       cand, st, piv);
             CDS_LAUNCHED(ctx);
             ctx->stats.n_cd_step_launch += 1;
         }
@@ -1331,12 +1349,11 @@ int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps)
     return CDS_OK;
 }
 
-int cds_set_cd_pivot_search(cds_ctx *ctx, int32_t hierarchical)
+int cds_set_cd_large_path(cds_ctx *ctx, int32_t on)
 {
     if (!ctx) return CDS_EINVAL;
-    if (hierarchical != 0 && hierarchical != 1)
-        return cds_fail(ctx, CDS_EINVAL, "hierarchical must be 0 or 1");
-    ctx->cd_hier_search = hierarchical;
+    if (on != 0 && on != 1) return cds_fail(ctx, CDS_EINVAL, "on must be 0 or 1");
+    ctx->cd_large_path = on;
     return CDS_OK;
 }
 

@@ -58,7 +58,8 @@ struct cds_ctx {
     bool broken = false;
     bool kernel_timing = false;      // time every CD step / pass launch with events
     int cd_lookahead = 16;           // Cholesky look-ahead block length (0: plain steps)
-    int cd_hier_search = 0;          // 1: pivot search always through super-tile keys
+    int cd_large_path = 0;           // 1: Cholesky code path of large pair counts at any size
+    int transform_fp64 = 0;          // 1: transform GEMMs in FP64, output rounded to its precision
 };
 
 // error helpers -------------------------------------------------------------

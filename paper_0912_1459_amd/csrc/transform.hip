@@ -165,7 +165,9 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     const int np_ = (int)(cds_ceil_div(nbf, 64) * 64);
     const int64_t nvo = (int64_t)nvirt * nocc, nselr = (int64_t)nsel * nmo;
     const int64_t nrows = nvo + nselr;
-    const size_t es = wsize(prec);
+    // working precision of the GEMMs; the output is rounded to `prec` in the last pass
+    const int wp = ctx->transform_fp64 ? CDS_PREC_FP64 : prec;
+    const size_t es = wsize(wp);
     const int kbatch = (int)std::min<int64_t>(KBATCH_MAX, nvec);
 
     // workspace: Ct + CX (+ sel list), Lu batch, T batch (+ split copy), Bk batch
@@ -175,8 +177,8 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     const int64_t nLu = (int64_t)kbatch * nbf * np_;
     CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)nLu * es, &wlu));
     const int64_t nT = (int64_t)kbatch * nx * np_;
-    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)nT * es * (prec == CDS_PREC_BF16X3 ? 2 : 1), &wt));
-    CDS_CALL(cds_ws(ctx, WS_TR_B, (size_t)kbatch * nrows * (prec == CDS_PREC_FP64 ? 8 : 4), &wb));
+    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)nT * es * (wp == CDS_PREC_BF16X3 ? 2 : 1), &wt));
+    CDS_CALL(cds_ws(ctx, WS_TR_B, (size_t)kbatch * nrows * (wp == CDS_PREC_FP64 ? 8 : 4), &wb));
 
     unsigned char *Ct = (unsigned char *)wcx;
     unsigned char *CX = Ct + nCt * es;
@@ -187,7 +189,7 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     {
         int64_t n = (int64_t)(nmo + nx) * np_;
         hipLaunchKernelGGL(coef_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0, ctx->stream,
-                           C, nbf, nmo, nocc, nsel, dsel, np_, (void *)Ct, (void *)CX, prec, planeCt,
+                           C, nbf, nmo, nocc, nsel, dsel, np_, (void *)Ct, (void *)CX, wp, planeCt,
                            planeCX);
         CDS_LAUNCHED(ctx);
     }
@@ -196,7 +198,7 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     // T: working float output, and (bf16) a split copy after it
     float *Tf = (float *)wt;
     __bf16 *Ts = (__bf16 *)((unsigned char *)wt + (size_t)nT * 4);
-    CDS_HIP(ctx, hipMemsetAsync(wt, 0, (size_t)nT * es * (prec == CDS_PREC_BF16X3 ? 2 : 1), ctx->stream));
+    CDS_HIP(ctx, hipMemsetAsync(wt, 0, (size_t)nT * es * (wp == CDS_PREC_BF16X3 ? 2 : 1), ctx->stream));
 
     // zero padding of B beyond nvec
     if (ldk > nvec) {
@@ -208,13 +210,13 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
         CDS_LAUNCHED(ctx);
     }
 
-    const int gprec = prec;   // GEMM precision
+    const int gprec = wp;     // GEMM precision
     for (int64_t k0 = 0; k0 < nvec; k0 += kbatch) {
         const int nkb = (int)std::min<int64_t>(kbatch, nvec - k0);
         {
             int64_t n = (int64_t)nkb * nbf * np_;
             hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
-                               ctx->stream, L, ldl, k0, nkb, nbf, np_, wlu, prec, (int64_t)nkb * nbf * np_);
+                               ctx->stream, L, ldl, k0, nkb, nbf, np_, wlu, wp, (int64_t)nkb * nbf * np_);
             CDS_LAUNCHED(ctx);
         }
         const int64_t planeLu = (int64_t)nkb * nbf * np_;
@@ -223,10 +225,10 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
         g1.M = nx; g1.N = nbf; g1.K = np_; g1.batch = nkb;
         g1.A = CX; g1.sAm = np_; g1.sAk = 1; g1.sAb = 0;
         g1.B = wlu; g1.sBn = np_; g1.sBk = 1; g1.sBb = (int64_t)nbf * np_;
-        void *Tout = (prec == CDS_PREC_FP64) ? wt : (void *)Tf;
+        void *Tout = (wp == CDS_PREC_FP64) ? wt : (void *)Tf;
         g1.C = Tout; g1.sCm = np_; g1.sCn = 1; g1.sCb = (int64_t)nx * np_;
         g1.alpha = 1.0; g1.beta = 0.0;
-        if (prec == CDS_PREC_BF16X3) {
+        if (wp == CDS_PREC_BF16X3) {
             CDS_CALL(cds_gemm_ex(ctx, gprec, g1, (const __bf16 *)CX + planeCX, (const __bf16 *)wlu + planeLu));
             int64_t n = (int64_t)nkb * nx * np_;
             hipLaunchKernelGGL(split_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
@@ -235,10 +237,10 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
         } else {
             CDS_CALL(cds_gemm_ex(ctx, gprec, g1, nullptr, nullptr));
         }
-        const void *Tin = (prec == CDS_PREC_BF16X3) ? (const void *)Ts : (const void *)Tout;
+        const void *Tin = (wp == CDS_PREC_BF16X3) ? (const void *)Ts : (const void *)Tout;
         const int64_t planeT = (int64_t)nkb * nx * np_;
-        const size_t tes = (prec == CDS_PREC_FP64) ? 8 : (prec == CDS_PREC_FP32 ? 4 : 2);
-        const size_t ces = (prec == CDS_PREC_FP64) ? 8 : (prec == CDS_PREC_FP32 ? 4 : 2);
+        const size_t tes = (wp == CDS_PREC_FP64) ? 8 : (wp == CDS_PREC_FP32 ? 4 : 2);
+        const size_t ces = tes;
         // Bk[kb][a][i] = sum_mu Ct[nocc+a][mu] T[kb][i][mu]
         GemmDesc g2 = {};
         g2.M = nvirt; g2.N = nocc; g2.K = np_; g2.batch = nkb;
@@ -252,10 +254,10 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
         g3.A = (const unsigned char *)Tin + (size_t)nocc * np_ * tes; g3.sAm = np_; g3.sAk = 1;
         g3.sAb = (int64_t)nx * np_;
         g3.B = Ct; g3.sBn = np_; g3.sBk = 1; g3.sBb = 0;
-        g3.C = (unsigned char *)wb + (size_t)nvo * (prec == CDS_PREC_FP64 ? 8 : 4);
+        g3.C = (unsigned char *)wb + (size_t)nvo * (wp == CDS_PREC_FP64 ? 8 : 4);
         g3.sCm = nmo; g3.sCn = 1; g3.sCb = nrows;
         g3.alpha = 1.0; g3.beta = 0.0;
-        if (prec == CDS_PREC_BF16X3) {
+        if (wp == CDS_PREC_BF16X3) {
             CDS_CALL(cds_gemm_ex(ctx, gprec, g2, (const __bf16 *)Ct + planeCt + (int64_t)nocc * np_,
                                  Ts + planeT));
             CDS_CALL(cds_gemm_ex(ctx, gprec, g3, Ts + planeT + (int64_t)nocc * np_,
@@ -265,7 +267,7 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
             CDS_CALL(cds_gemm_ex(ctx, gprec, g3, nullptr, nullptr));
         }
         dim3 tg((unsigned)cds_ceil_div(nrows, 32), (unsigned)cds_ceil_div(nkb, 32));
-        if (prec == CDS_PREC_FP64)
+        if (wp == CDS_PREC_FP64)
             hipLaunchKernelGGL(transpose_out_kernel<double>, tg, dim3(256), 0, ctx->stream,
                                (const double *)wb, nrows, nkb, k0, nvo, Bvo, Bsel, ldk, prec, nvo * ldk,
                                nselr * ldk);
@@ -276,5 +278,13 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
         CDS_LAUNCHED(ctx);
     }
     CDS_CALL(cds_timer_stop(ctx, &tm, &ctx->stats.t_transform_ms));
+    return CDS_OK;
+}
+
+extern "C" int cds_set_transform_fp64(cds_ctx *ctx, int32_t on)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (on != 0 && on != 1) return cds_fail(ctx, CDS_EINVAL, "on must be 0 or 1");
+    ctx->transform_fp64 = on;
     return CDS_OK;
 }

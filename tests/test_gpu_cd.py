@@ -122,13 +122,14 @@ def test_cd_plain_equals_lookahead(cds, name, delta):
 
 
 @pytest.mark.parametrize("name,delta,lookahead", [("plain", 1e-8, 16), ("c60", 1e-6, 16), ("c60", 1e-4, 0)])
-def test_cd_hierarchical_search(cds, name, delta, lookahead):
-    # pivot search through the super-tile keys (the path of large pair counts) on workloads
-    # small enough for the oracle: same pivots, same vectors to rounding
+def test_cd_large_path(cds, name, delta, lookahead):
+    # the code path of large pair counts (pivot search through the super-tile keys, four
+    # tiles per step block) on workloads small enough for the oracle: same pivots, same
+    # vectors to rounding
     w = workload(name)
-    log(f"cd hierarchical pivot search {name} delta={delta} lookahead={lookahead}")
+    log(f"cd large-problem path {name} delta={delta} lookahead={lookahead}")
     ctx = cds.Context(0)
-    ctx.set_cd_pivot_search(True)
+    ctx.set_cd_large_path(True)
     ctx.set_cd_lookahead(lookahead)
     ref = oracle_cd(name, delta)
     got = cds.cholesky(delta, centres=_dev(w.centres), alpha=_dev(w.alpha), ctx=ctx)

@@ -62,6 +62,26 @@ def test_transform_reduced(cds, prec, tol):
     assert np.abs(gv.cpu().numpy() - refv.transpose(1, 2, 0)).max() <= tol * scale
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-7), ("bf16x3", 2e-5)])
+def test_transform_fp64_working_precision(cds, prec, tol):
+    # GEMMs in FP64, only the output rounded: per element within one rounding of the output
+    # format (FP32: 2^-24; split bf16 from the FP32 value: about 2^-17) relative to the largest B
+    name, delta = "c60", 1e-6
+    w = workload(name)
+    log(f"transform {prec} output, FP64 working precision, {name}")
+    Ld, M = _L_on_device(name, delta)
+    refs, refv = oracle_blocks(name, delta)
+    ctx = cds.Context(0)
+    ctx.set_transform_fp64(True)
+    B = cds.transform(Ld, M, _dev(w.C), w.nocc, w.targets, prec, ctx=ctx)
+    gs, gv = B.as_float64()
+    scale = max(np.abs(refs).max(), np.abs(refv).max())
+    es = np.abs(gs.cpu().numpy() - refs.transpose(1, 2, 0)).max() / scale
+    ev = np.abs(gv.cpu().numpy() - refv.transpose(1, 2, 0)).max() / scale
+    log(f"  max error / max |B|: {max(es, ev):.2e}")
+    assert es <= tol and ev <= tol
+
+
 @pytest.mark.parametrize("name", ["plain", "c60"])
 def test_sigma2_fp64_trial_energies(cds, name):
     w = workload(name)
