@@ -131,14 +131,18 @@ void orc_eri_columns(int32_t nbf, const double *centres, const double *alpha,
  * In/out: L (npairs x ldl, row-major), piv[max_vec], D[npairs] (residual
  * diagonal; pivots hold 0), *nvec.  When *nvec > 0 on entry the call resumes
  * from that state (L, piv and D as a previous call left them).
+ * allowed: NULL, or npairs flags; only pairs with allowed[I] != 0 may become
+ * pivots (every non-pivot row is still updated) -- the inner projection of
+ * Eq. (int_approx) onto the allowed products, as in the atomic CD.
  * Returns 0 when D_max <= delta, 1 when max_vec vectors were made first,
- * 2 when every pair became a pivot, -4 when a non-pivot residual diagonal fell
- * below -psd_tol.  *dmax receives the final largest non-pivot residual diagonal.
+ * 2 when every allowed pair became a pivot, -4 when a non-pivot residual
+ * diagonal fell below -psd_tol.  *dmax receives the final largest residual
+ * diagonal among allowed non-pivots.
  */
 int orc_pivoted_cd(int64_t npairs, const double *V, int32_t nbf, const double *centres,
                    const double *alpha, double delta, double tau, double psd_tol,
                    int64_t max_vec, int64_t ldl, double *L, int64_t *piv, double *D,
-                   int64_t *nvec, double *dmax)
+                   int64_t *nvec, double *dmax, const unsigned char *allowed)
 {
     unsigned char *is_piv = (unsigned char *)calloc((size_t)npairs, 1);
     double *col = (double *)malloc((size_t)npairs * sizeof(double));
@@ -157,9 +161,10 @@ int orc_pivoted_cd(int64_t npairs, const double *V, int32_t nbf, const double *c
         int any = 0;
         for (int64_t I = 0; I < npairs; ++I)
             if (!is_piv[I]) {
+                if (D[I] < -psd_tol) status = -4;
+                if (allowed && !allowed[I]) continue;
                 any = 1;
                 if (D[I] > dm) dm = D[I];
-                if (D[I] < -psd_tol) status = -4;
             }
         *dmax = dm;
         if (status == -4) break;
@@ -171,7 +176,7 @@ int orc_pivoted_cd(int64_t npairs, const double *V, int32_t nbf, const double *c
         const double win = fmin(tau, 1e-2 * dm);
         int64_t p = -1;
         for (int64_t I = 0; I < npairs; ++I)
-            if (!is_piv[I] && D[I] >= dm - win) { p = I; break; }
+            if (!is_piv[I] && (!allowed || allowed[I]) && D[I] >= dm - win) { p = I; break; }
         double dp = D[p];
         double sq = sqrt(dp);
         /* residual column c_I = V_Ip - sum_{j<k} L_Ij L_pj */
