@@ -268,6 +268,32 @@ def main():
     from paper_0912_1459_amd import sweep as SW
     sweep = SW.report(w, prec="fp64", conv=conv) if args.workload == "c60" else None
 
+    # atomic CD (one-centre products per atom, then the inner projection onto them) against
+    # the full CD at the same delta: decomposition time and quasi-particle shift (FP64)
+    acd_report = None
+    if args.workload == "c60":
+        progress("atomic CD")
+        from paper_0912_1459_amd import acd as ACD
+        ACD.acd(centres, alpha, delta, ctx=ctx)                     # warm
+        torch.cuda.synchronize()
+        ta0 = time.perf_counter()
+        a = ACD.acd(centres, alpha, delta, ctx=ctx)
+        torch.cuda.synchronize()
+        ta1 = time.perf_counter()
+        C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, grow=True, ctx=ctx)
+        torch.cuda.synchronize()
+        ta2 = time.perf_counter()
+        Ba = C.transform(a.cd.Lbuf, a.cd.nvec, Cm, w.nocc, w.targets, "fp64", ctx=ctx)
+        qa = C.qp_solve(Ba, eps, conv=1e-10, ctx=ctx)
+        Bf = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, "fp64", ctx=ctx)
+        qf = C.qp_solve(Bf, eps, conv=1e-10, ctx=ctx)
+        acd_report = {"products": int(a.products.size), "per_atom": a.per_atom, "vectors": a.cd.nvec,
+                      "full_cd_vectors": ref_cd.nvec, "acd_ms": round((ta1 - ta0) * 1e3, 3),
+                      "full_cd_ms": round((ta2 - ta1) * 1e3, 3),
+                      "speedup": round((ta2 - ta1) / (ta1 - ta0), 2),
+                      "max_qp_shift_meV_vs_full_cd": float(np.abs(qa.omega - qf.omega).max() * HARTREE_EV * 1e3)}
+        del Ba, Bf
+
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -295,6 +321,7 @@ def main():
         "backward": backward,
         "mp2": mp2_report,
         "sweep": sweep,
+        "acd": acd_report,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline and args.workload == "c60":

@@ -192,6 +192,21 @@ int cds_cholesky_dense(cds_ctx *ctx, int64_t npairs, const double *V, int64_t ld
                        double *L, int64_t ldl, int64_t *piv, double *D, int64_t nvec_in,
                        int64_t *h_nvec, double *h_dmax, int32_t *h_status);
 
+/* Same decomposition with the pivots restricted to the pairs I with
+ * allowed[I] != 0 (device uint8[npairs]); every other non-pivot row is still
+ * updated.  The vectors then span the inner projection of Eq. (int_approx) onto
+ * the allowed products: L L^T = V[:, A] V[A, A]^-1 V[A, :] once every allowed
+ * product is a pivot (status FULLRANK) or the allowed residuals are <= delta.
+ * This is the molecular step of the atomic CD (Sec. II.A), whose allowed set
+ * holds the one-centre products chosen atom by atom.  D_max, the tie window
+ * and the termination rules range over allowed non-pivots; the PSD check over
+ * all non-pivots.  Other arguments, layouts and errors as cds_cholesky_sgauss. */
+int cds_cholesky_sgauss_subset(cds_ctx *ctx, int32_t nbf, const double *centres,
+                               const double *alpha, const uint8_t *allowed, double delta,
+                               double tau, double psd_tol, int64_t max_vec, double *L,
+                               int64_t ldl, int64_t *piv, double *D, int64_t nvec_in,
+                               int64_t *h_nvec, double *h_dmax, int32_t *h_status);
+
 /*
  * AO->MO transform of the Cholesky vectors, Eq. (transformation):
  *   B^K_pq = sum_{mu,nu} C_mu,p L^K_mu,nu C_nu,q   (all ordered AO pairs),

@@ -176,11 +176,12 @@ class CDResult:
 def cholesky(delta: float, *, centres: torch.Tensor | None = None, alpha: torch.Tensor | None = None,
              V: torch.Tensor | None = None, tau: float = -1.0, psd_tol: float = -1.0,
              max_vec: int | None = None, resume: CDResult | None = None, ctx: Context | None = None,
-             grow: bool | None = None) -> CDResult:
+             grow: bool | None = None, allowed: torch.Tensor | None = None) -> CDResult:
     """Pivoted incomplete Cholesky to threshold delta, on demand (basis) or of a dense V.
 
     With max_vec None the buffer starts at 12 vectors per basis function and grows
-    (by resuming into a larger buffer) until the decomposition finishes.
+    (by resuming into a larger buffer) until the decomposition finishes.  `allowed`
+    (device uint8 per pair, basis form only) restricts the pivots to the flagged pairs.
     """
     dense = V is not None
     if dense:
@@ -224,6 +225,14 @@ def cholesky(delta: float, *, centres: torch.Tensor | None = None, alpha: torch.
         rc = ctx.lib.cds_cholesky_dense(ctx.h, np_, _ptr(V), V.stride(0), float(delta), float(tau),
                                         float(psd_tol), max_vec, _ptr(Lbuf), ldl, _ptr(piv), _ptr(D),
                                         nvec_in, ctypes.byref(nvec), ctypes.byref(dmax), ctypes.byref(status))
+    elif allowed is not None:
+        _dev(allowed, torch.uint8, "allowed")
+        if allowed.numel() != np_:
+            raise ValueError("allowed needs one flag per pair")
+        rc = ctx.lib.cds_cholesky_sgauss_subset(ctx.h, nbf, _ptr(centres), _ptr(alpha), _ptr(allowed),
+                                                float(delta), float(tau), float(psd_tol), max_vec, _ptr(Lbuf),
+                                                ldl, _ptr(piv), _ptr(D), nvec_in, ctypes.byref(nvec),
+                                                ctypes.byref(dmax), ctypes.byref(status))
     else:
         rc = ctx.lib.cds_cholesky_sgauss(ctx.h, nbf, _ptr(centres), _ptr(alpha), float(delta), float(tau),
                                          float(psd_tol), max_vec, _ptr(Lbuf), ldl, _ptr(piv), _ptr(D),
@@ -232,7 +241,7 @@ def cholesky(delta: float, *, centres: torch.Tensor | None = None, alpha: torch.
     res = CDResult(Lbuf, piv, D, int(nvec.value), float(dmax.value), int(status.value), np_)
     if grow and res.status == A.CD_CAP and max_vec < np_:
         return cholesky(delta, centres=centres, alpha=alpha, V=V, tau=tau, psd_tol=psd_tol,
-                        max_vec=min(2 * max_vec, np_), resume=res, ctx=ctx, grow=True)
+                        max_vec=min(2 * max_vec, np_), resume=res, ctx=ctx, grow=True, allowed=allowed)
     return res
 
 

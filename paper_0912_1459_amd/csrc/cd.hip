@@ -500,6 +500,14 @@ __device__ Pick cd_pick(const CdBufs &b, int r, int sr, const CdParams &cp, int6
     return sh.pk;
 }
 
+// pivot mask of a restricted decomposition: 0 = may become a pivot, 2 = never (row updated)
+__global__ void init_mask_kernel(int64_t npairs, const unsigned char *__restrict__ allowed,
+                                 unsigned char *__restrict__ mask)
+{
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < npairs) mask[I] = allowed[I] ? 0 : 2;
+}
+
 __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, int64_t npairs,
                                    unsigned char *__restrict__ mask)
 {
@@ -510,14 +518,15 @@ __global__ void mark_pivots_kernel(int64_t n, const int64_t *__restrict__ piv, i
     }
 }
 
-// Record of one 64-row tile from its rows' new residuals (one wave; `active` = a non-pivot
-// row): largest and smallest residual, and the lowest row within the tie window of the largest.
+// Record of one 64-row tile from its rows' new residuals (one wave; `active` = a row that
+// may still become a pivot, `nonpiv` = any non-pivot row): largest residual and the lowest
+// row within the tie window of it over the active rows, smallest over the non-pivot rows.
 __device__ __forceinline__ void tile_record(const CdBufs &b, int w, int sw, const CdParams &cp, int64_t tile,
-                                            bool active, double dn)
+                                            bool active, bool nonpiv, double dn)
 {
     const int l = threadIdx.x & 63;
     const double tmx = wave_max(active ? dn : -INFINITY);
-    const double tmn = wave_min(active ? dn : INFINITY);
+    const double tmn = wave_min(nonpiv ? dn : INFINITY);
     const unsigned long long fb = __ballot(active && dn >= tmx - tie_window(tmx, cp.tau));
     const int fl = fb ? __ffsll((long long)fb) - 1 : 0;
     const double df = __shfl(dn, fl, 64);
@@ -540,9 +549,9 @@ __device__ __forceinline__ void tile_record(const CdBufs &b, int w, int sw, cons
 __global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, CdParams cp)
 {
     const int64_t I = (int64_t)blockIdx.x * CD_TILE + threadIdx.x;
-    const bool active = I < cp.npairs && !b.mask[0][I];
-    const double d = active ? b.D[0][I] : 0.0;
-    tile_record(b, 0, 0, cp, blockIdx.x, active, d);
+    const unsigned char m = I < cp.npairs ? b.mask[0][I] : 1;
+    const double d = m != 1 ? b.D[0][I] : 0.0;
+    tile_record(b, 0, 0, cp, blockIdx.x, m == 0, m != 1, d);
 }
 
 // One Cholesky step (one launch).  Block = TB tiles (64 TB rows); thread (jg, rl): rows
@@ -630,7 +639,7 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     // this row's entry of the pivot column (residual from the look-ahead pass on a hit),
     // issued before the pivot-row gather so the two loads overlap
     double cfin = 0.0;
-    if (threadIdx.x < NR && If < cp.npairs && !m_old && If != p) {
+    if (threadIdx.x < NR && If < cp.npairs && m_old != 1 && If != p) {
         if (slot >= 0) {
             cfin = R[(int64_t)slot * ldr + If];
         } else if constexpr (DENSE) {
@@ -717,12 +726,12 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     const int w = 1 - r;
     if (threadIdx.x < NR) {                              // wave t: tile t of the block
         const int64_t I = If;
-        bool active = false;
+        bool active = false, nonpiv = false;
         double dn = 0.0;
         if (I < cp.npairs) {
             double l;
             unsigned char m = m_old;
-            if (m) {
+            if (m == 1) {
                 l = 0.0;                          // earlier pivot: exactly zero
                 dn = d_old;
             } else if (I == p) {
@@ -735,14 +744,15 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
                 for (int g = 0; g < JG; ++g) s += red[g][threadIdx.x];
                 l = (cfin - s) / sq;
                 dn = d_old - l * l;
-                active = true;
+                nonpiv = true;
+                active = m == 0;                  // m == 2: updated, never a pivot
             }
             L[k * ldl + I] = l;
             b.D[w][I] = dn;
             b.mask[w][I] = m;
         }
         const int64_t tile = (int64_t)blockIdx.x * TB + (threadIdx.x >> 6);
-        if (tile < b.ntile) tile_record(b, w, sw, cp, tile, active, dn);
+        if (tile < b.ntile) tile_record(b, w, sw, cp, tile, active, nonpiv, dn);
     }
     if (blockIdx.x == 0) {
         if (!b.flat && threadIdx.x < CD_NSUP) {
@@ -1101,7 +1111,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                   const double *alpha, int64_t npairs, const double *V, int64_t ldv, double delta,
                   double tau, double psd_tol, int64_t max_vec, double *L, int64_t ldl,
                   int64_t *piv, double *D, int64_t nvec_in, int64_t *h_nvec, double *h_dmax,
-                  int32_t *h_status)
+                  int32_t *h_status, const unsigned char *allowed = nullptr)
 {
     CDS_CALL(cds_enter(ctx));
     CDS_REQUIRE(ctx, npairs >= 1, "npairs must be >= 1");
@@ -1176,7 +1186,12 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
 
     CdsTimer tall;
     CDS_CALL(cds_timer_start(ctx, &tall));
-    CDS_HIP(ctx, hipMemsetAsync(bf.mask[0], 0, (size_t)npairs, ctx->stream));
+    if (allowed) {
+        hipLaunchKernelGGL(init_mask_kernel, dim3(nb), dim3(256), 0, ctx->stream, npairs, allowed, bf.mask[0]);
+        CDS_LAUNCHED(ctx);
+    } else {
+        CDS_HIP(ctx, hipMemsetAsync(bf.mask[0], 0, (size_t)npairs, ctx->stream));
+    }
     // super-tile buffers 0 and 1 start empty (2 is reset by the first step)
     CDS_HIP(ctx, hipMemsetAsync(bf.smax[0], 0, (size_t)3 * CD_NSUP * 8, ctx->stream));
     CDS_HIP(ctx, hipMemsetAsync(bf.smin[0], 0xff, (size_t)3 * CD_NSUP * 8, ctx->stream));
@@ -1338,6 +1353,19 @@ int cds_cholesky_dense(cds_ctx *ctx, int64_t npairs, const double *V, int64_t ld
 {
     return cholesky_impl(ctx, true, 0, nullptr, nullptr, npairs, V, ldv, delta, tau, psd_tol,
                          max_vec, L, ldl, piv, D, nvec_in, h_nvec, h_dmax, h_status);
+}
+
+int cds_cholesky_sgauss_subset(cds_ctx *ctx, int32_t nbf, const double *centres, const double *alpha,
+                               const uint8_t *allowed, double delta, double tau, double psd_tol,
+                               int64_t max_vec, double *L, int64_t ldl, int64_t *piv, double *D,
+                               int64_t nvec_in, int64_t *h_nvec, double *h_dmax, int32_t *h_status)
+{
+    CDS_CALL(cds_enter(ctx));
+    CDS_REQUIRE(ctx, nbf >= 1 && centres && alpha, "need nbf >= 1, centres and alpha");
+    CDS_REQUIRE(ctx, allowed, "allowed is NULL");
+    return cholesky_impl(ctx, false, nbf, centres, alpha, cds_npairs(nbf), nullptr, 0, delta, tau,
+                         psd_tol, max_vec, L, ldl, piv, D, nvec_in, h_nvec, h_dmax, h_status,
+                         (const unsigned char *)allowed);
 }
 
 int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps)
