@@ -94,6 +94,17 @@ __global__ void sym_bar_kernel(const BT *__restrict__ bsel, const BT *__restrict
 }
 
 // Lu[kb][mu][nu] (nu padded to np_) in FP64
+// out[e] (+)= sum_{b < nb} part[b][e], b in increasing order
+__global__ void sum_parts_kernel(const double *__restrict__ part, int nb, int64_t ne, int accumulate,
+                                 double *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    double acc = accumulate ? out[e] : 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * ne + e];
+    out[e] = acc;
+}
+
 __global__ void unpack64_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, int nkb, int nbf,
                                 int np_, double *__restrict__ out)
 {
@@ -240,13 +251,16 @@ extern "C" int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, in
     CdsTimer tall;
     CDS_CALL(cds_timer_start(ctx, &tall));
     const int np_ = (int)(cds_ceil_div(nbf, 64) * 64);
-    const int kb = (int)std::min<int64_t>(32, nvec);
-    void *wl, *ws, *wk, *wsel;
+    const int kb = (int)std::min<int64_t>(64, nvec);
+    void *wl, *ws, *wk, *wsel, *wp;
     CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)kb * nbf * np_ * 8, &wl));
     CDS_CALL(cds_ws(ctx, WS_AD_TMP2, (size_t)kb * nmo * nmo * 8, &ws));
-    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)kb * nbf * nmo * 8, &wk));
+    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)kb * nmo * np_ * 8, &wk));
     CDS_CALL(cds_ws(ctx, WS_TR_CX, (size_t)nsel * 4 + 64, &wsel));
+    CDS_CALL(cds_ws(ctx, WS_AD_TMP, (size_t)kb * nbf * nmo * 8, &wp));
     CDS_HIP(ctx, hipMemcpyAsync(wsel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
+    // Wt columns nbf..np_-1 are never written: zero once so the padded K range adds nothing
+    CDS_HIP(ctx, hipMemsetAsync(wk, 0, (size_t)kb * nmo * np_ * 8, ctx->stream));
     for (int64_t k0 = 0; k0 < nvec; k0 += kb) {
         const int nkb = (int)std::min<int64_t>(kb, nvec - k0);
         int64_t n1 = (int64_t)nkb * nbf * np_;
@@ -262,22 +276,28 @@ extern "C" int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, in
                                ctx->stream, (const float *)Bsel_bar, (const float *)Bvo_bar, ldk, k0, nkb,
                                nmo, nocc, nsel, (const int32_t *)wsel, (double *)ws);
         CDS_LAUNCHED(ctx);
-        // Wk[kb][mu][p] = sum_r C[mu][r] S[kb][r][p]
+        // Wt[kb][p][nu] = sum_r S[kb][p][r] C[nu][r]   (S symmetric; both operands K-contiguous)
         GemmDesc g1 = {};
-        g1.M = nbf; g1.N = nmo; g1.K = nmo; g1.batch = nkb;
-        g1.A = C; g1.sAm = nmo; g1.sAk = 1; g1.sAb = 0;
-        g1.B = ws; g1.sBn = nmo; g1.sBk = 1; g1.sBb = (int64_t)nmo * nmo;
-        g1.C = wk; g1.sCm = nmo; g1.sCn = 1; g1.sCb = (int64_t)nbf * nmo;
+        g1.M = nmo; g1.N = nbf; g1.K = nmo; g1.batch = nkb;
+        g1.A = ws; g1.sAm = nmo; g1.sAk = 1; g1.sAb = (int64_t)nmo * nmo;
+        g1.B = C; g1.sBn = nmo; g1.sBk = 1; g1.sBb = 0;
+        g1.C = wk; g1.sCm = np_; g1.sCn = 1; g1.sCb = (int64_t)nmo * np_;
         g1.alpha = 1.0; g1.beta = 0.0;
         CDS_CALL(cds_gemm_ex(ctx, CDS_PREC_FP64, g1, nullptr, nullptr));
-        // C_bar[mu][p] += sum_{kb, nu} Lu[kb][nu][mu] Wk[kb][nu][p]   (Lu symmetric in mu, nu)
+        // part[kb][mu][p] = sum_nu Lu[kb][mu][nu] Wt[kb][p][nu]: one product per vector (the batch
+        // index splits the long reduction over (kb, nu) so the tiny output still fills the chip)
         GemmDesc g2 = {};
-        g2.M = nbf; g2.N = nmo; g2.K = (int64_t)nkb * nbf; g2.batch = 1;
-        g2.A = wl; g2.sAm = 1; g2.sAk = np_;
-        g2.B = wk; g2.sBk = nmo; g2.sBn = 1;
-        g2.C = C_bar; g2.sCm = nmo; g2.sCn = 1;
-        g2.alpha = 1.0; g2.beta = k0 == 0 ? 0.0 : 1.0;
+        g2.M = nbf; g2.N = nmo; g2.K = np_; g2.batch = nkb;
+        g2.A = wl; g2.sAm = np_; g2.sAk = 1; g2.sAb = (int64_t)nbf * np_;
+        g2.B = wk; g2.sBn = np_; g2.sBk = 1; g2.sBb = (int64_t)nmo * np_;
+        g2.C = wp; g2.sCm = nmo; g2.sCn = 1; g2.sCb = (int64_t)nbf * nmo;
+        g2.alpha = 1.0; g2.beta = 0.0;
         CDS_CALL(cds_gemm_ex(ctx, CDS_PREC_FP64, g2, nullptr, nullptr));
+        // C_bar (+)= sum_kb part[kb] in fixed order
+        const int64_t ne = (int64_t)nbf * nmo;
+        hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)cds_ceil_div(ne, 256)), dim3(256), 0, ctx->stream,
+                           (const double *)wp, nkb, ne, k0 > 0 ? 1 : 0, C_bar);
+        CDS_LAUNCHED(ctx);
     }
     CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_adjoint_ms));
     return CDS_OK;
