@@ -294,6 +294,22 @@ def main():
                       "max_qp_shift_meV_vs_full_cd": float(np.abs(qa.omega - qf.omega).max() * HARTREE_EV * 1e3)}
         del Ba, Bf
 
+    # Dyson poles over the targets (non-diagonal self-energy) against the quasi-particle ones
+    dyson_report = None
+    if nsel <= 31:
+        progress("Dyson poles")
+        Bd = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, "fp64", ctx=ctx)
+        C.dyson_solve(Bd, eps, conv=conv, ctx=ctx)                  # warm
+        ctx.reset_stats()
+        dy = C.dyson_solve(Bd, eps, conv=conv, ctx=ctx)
+        sd = ctx.stats()
+        qd = C.qp_solve(Bd, eps, conv=conv, ctx=ctx)
+        dyson_report = {"roots": nsel, "ms": round(sd["t_dyson_ms"], 3), "max_iters": int(dy.iters.max()),
+                        "converged": int((dy.status == 0).sum()),
+                        "max_shift_meV_vs_quasiparticle": float(np.abs(dy.omega - qd.omega).max() * HARTREE_EV * 1e3),
+                        "min_pole_strength": float(dy.pole.min())}
+        del Bd
+
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -322,6 +338,7 @@ def main():
         "mp2": mp2_report,
         "sweep": sweep,
         "acd": acd_report,
+        "dyson": dyson_report,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline and args.workload == "c60":

@@ -103,6 +103,7 @@ typedef struct cds_stats {
     int64_t n_cd_pass_launch; /* look-ahead pass launches                       */
     double t_mp2_ms;         /* MP2 energies (contraction + reduction)        */
     double flops_mp2;        /* 2 nvec x rows x columns of the MP2 contractions */
+    double t_dyson_ms;       /* self-energy matrices and Dyson pole searches  */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -295,6 +296,39 @@ int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec,
  */
 int cds_mp2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo, int32_t nocc,
             const void *Bvo, const double *eps, double *h_energy);
+
+/*
+ * Second-order self-energy as a matrix over the selected orbitals S = h_sel
+ * (Sec. II.B; its diagonal is Eq. (SE)):
+ *   Sigma_st(w) = sum_{a,i,j} (si|aj) (2(ti|aj) - (tj|ai)) / (w + e_a - e_i - e_j)
+ *               + sum_{i,a,b} (sa|ib) (2(ta|ib) - (tb|ia)) / (w + e_i - e_a - e_b),
+ * and dSigma_st/dw, at T trial energies h_omega[T] (host).  B blocks, eps and
+ * precisions as cds_sigma2 (ldk a multiple of 64); 1 <= nsel <= 31 (symmetric
+ * output: h_sigma, h_dsigma host double[T][nsel][nsel]).  The integrals of all
+ * selected orbitals are formed at once (at most 16 GiB).  Synchronizes.
+ */
+int cds_sigma2_matrix(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                      int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                      const void *Bvo, const double *eps, int32_t T, const double *h_omega,
+                      double *h_sigma, double *h_dsigma);
+
+/*
+ * Poles of the Dyson equation restricted to the selected orbitals,
+ * det(w - e_S - Sigma_SS(w)) = 0 (Eqs. (Dyson), (DysonSol2)), one root per
+ * selected orbital q: start at w_0 = e_q, u_0 = unit vector q; at each step
+ * diagonalise diag(e_S) + Sigma_SS(w_n), follow the eigenvector u of largest
+ * overlap with the previous one (eigenvalue lambda) and set
+ *   w_{n+1} = w_n + (lambda - w_n) P_n,   P_n = 1 / (1 - u^T Sigma'(w_n) u)
+ * (Hellmann-Feynman slope; with nsel = 1 this is Eq. (iter)) until
+ * |w_{n+1} - w_n| <= conv (Eq. (NR)).  Outputs (host, per root k): h_omega =
+ * w_{n+1}, h_pole = P_n, h_vec[k][nsel] = u, h_iters, h_status (CDS_QP_*).
+ * Other arguments as cds_sigma2_matrix.
+ */
+int cds_dyson_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                    int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                    const void *Bvo, const double *eps, double conv, int32_t max_iter,
+                    double *h_omega, double *h_pole, double *h_vec, int32_t *h_iters,
+                    int32_t *h_status);
 
 /* Device workspace the context holds now (bytes, all slots); it grows on
  * demand and is released by cds_destroy. */

@@ -29,17 +29,16 @@ from . import selfenergy as SE
 
 
 def sigma_matrix(xs, ys, eps, nocc, omega):
-    """Sigma_SS(omega) and its derivative from per-target x[a,i,j] = (qi|aj), y[i,a,b] = (qa|ib)."""
+    """Sigma_SS(omega) and its derivative from per-target x[a,i,j] = (qi|aj), y[i,a,b] = (qa|ib):
+    Sigma_pq = sum_e x_p[e] (2 x_q[e] - x_q[e~]) / d[e] over both families, e~ the element with
+    the two occupied (resp. virtual) indices exchanged; one matrix product per family."""
     d_x, d_y = SE._denominators(eps, nocc, omega)
-    n = len(xs)
-    S = np.zeros((n, n))
-    dS = np.zeros((n, n))
-    for p in range(n):
-        for q in range(n):
-            nx = xs[p] * (2.0 * xs[q] - xs[q].transpose(0, 2, 1))
-            ny = ys[p] * (2.0 * ys[q] - ys[q].transpose(0, 2, 1))
-            S[p, q] = (nx / d_x).sum() + (ny / d_y).sum()
-            dS[p, q] = -(nx / d_x ** 2).sum() - (ny / d_y ** 2).sum()
+    X = np.stack([x.ravel() for x in xs])                                   # (n, E_x)
+    Xe = np.stack([(2.0 * x - x.transpose(0, 2, 1)).ravel() for x in xs])
+    Y = np.stack([y.ravel() for y in ys])
+    Ye = np.stack([(2.0 * y - y.transpose(0, 2, 1)).ravel() for y in ys])
+    S = (X / d_x.ravel()) @ Xe.T + (Y / d_y.ravel()) @ Ye.T
+    dS = -(X / d_x.ravel() ** 2) @ Xe.T - (Y / d_y.ravel() ** 2) @ Ye.T
     return S, dS
 
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "cds_create", "cds_destroy", "cds_last_error", "cds_get_stats", "cds_reset_stats",
     "cds_set_kernel_timing", "cds_set_cd_lookahead", "cds_set_cd_large_path", "cds_set_transform_fp64", "cds_version", "cds_eri_columns", "cds_cholesky_sgauss", "cds_cholesky_sgauss_subset",
     "cds_cholesky_dense", "cds_transform", "cds_sigma2", "cds_qp_solve", "cds_qp_adjoint",
-    "cds_transform_adjoint", "cds_mp2", "cds_workspace_bytes",
+    "cds_transform_adjoint", "cds_mp2", "cds_workspace_bytes", "cds_sigma2_matrix", "cds_dyson_solve",
 ]
 
 
@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
         ("n_cd_pass", ctypes.c_int64), ("n_cd_miss", ctypes.c_int64),
         ("flops_cd_pass", ctypes.c_double), ("bytes_cd_step", ctypes.c_double),
         ("n_cd_step_launch", ctypes.c_int64), ("n_cd_pass_launch", ctypes.c_int64),
-        ("t_mp2_ms", ctypes.c_double), ("flops_mp2", ctypes.c_double),
+        ("t_mp2_ms", ctypes.c_double), ("flops_mp2", ctypes.c_double), ("t_dyson_ms", ctypes.c_double),
     ]
 
 
@@ -79,6 +79,8 @@ def load() -> ctypes.CDLL:
         "cds_qp_adjoint": (ip, [P, i32, i64, i64, i32, i32, i32, P, P, P, P, P, P, P, P, P]),
         "cds_transform_adjoint": (ip, [P, i32, i32, i64, P, i64, P, i32, i32, i32, P, i64, P, P, P]),
         "cds_mp2": (ip, [P, i32, i64, i64, i32, i32, P, P, P]),
+        "cds_sigma2_matrix": (ip, [P, i32, i64, i64, i32, i32, i32, P, P, P, P, i32, P, P, P]),
+        "cds_dyson_solve": (ip, [P, i32, i64, i64, i32, i32, i32, P, P, P, P, d, i32, P, P, P, P, P]),
         "cds_workspace_bytes": (ip, [P, ctypes.POINTER(ctypes.c_size_t)]),
     }
     for name, (res, args) in sig.items():

@@ -361,6 +361,47 @@ def mp2_energy(B: BBlocks, eps: torch.Tensor, ctx: Context | None = None) -> flo
     return float(out.value)
 
 
+def sigma2_matrix(B: BBlocks, eps: torch.Tensor, omega, ctx: Context | None = None):
+    """Sigma_SS and dSigma_SS/dw over the selected orbitals at trial energies omega (T,);
+    returns numpy (T, nsel, nsel) x 2."""
+    _dev(eps, torch.float64, "eps")
+    ctx = ctx or context(eps.device.index or 0)
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)))
+    T, n = om.shape[0], B.nsel
+    s = np.zeros((T, n, n))
+    ds = np.zeros((T, n, n))
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    ctx.check(ctx.lib.cds_sigma2_matrix(ctx.h, B.prec, B.nvec, B.ldk, B.nmo, B.nocc, n, vp(B.sel), _ptr(B.Bsel),
+                                        _ptr(B.Bvo), _ptr(eps), T, vp(om), vp(s), vp(ds)))
+    return s, ds
+
+
+@dataclasses.dataclass
+class DysonResult:
+    omega: np.ndarray
+    pole: np.ndarray
+    vec: np.ndarray       # (nsel, nsel): row k = eigenvector of root k over the selected orbitals
+    iters: np.ndarray
+    status: np.ndarray
+
+
+def dyson_solve(B: BBlocks, eps: torch.Tensor, *, conv: float = 1e-5, max_iter: int = 50,
+                ctx: Context | None = None) -> DysonResult:
+    """One pole of the Dyson equation over the selected orbitals per orbital (Eq. (DysonSol2))."""
+    _dev(eps, torch.float64, "eps")
+    ctx = ctx or context(eps.device.index or 0)
+    n = B.nsel
+    om, pole = np.zeros(n), np.zeros(n)
+    vec = np.zeros((n, n))
+    iters = np.zeros(n, dtype=np.int32)
+    st = np.zeros(n, dtype=np.int32)
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    ctx.check(ctx.lib.cds_dyson_solve(ctx.h, B.prec, B.nvec, B.ldk, B.nmo, B.nocc, n, vp(B.sel), _ptr(B.Bsel),
+                                      _ptr(B.Bvo), _ptr(eps), float(conv), int(max_iter), vp(om), vp(pole),
+                                      vp(vec), vp(iters), vp(st)))
+    return DysonResult(om, pole, vec, iters, st)
+
+
 @dataclasses.dataclass
 class QPResult:
     omega: np.ndarray

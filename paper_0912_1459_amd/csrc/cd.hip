@@ -10,12 +10,14 @@
 // look-ahead over candidate pivots, which leaves the pivot sequence unchanged:
 //
 //   every `block_steps` steps (default 16; block start at step k0):
-//     cd_cand    the pivot of step k0 plus the argmax rows of the tiles with the
-//                largest residual diagonals (up to CD_NCAND candidates)
+//     cd_cand    the pivot of step k0 plus the rows with the largest residual
+//                diagonals (CD_NCAND candidates in all)
+//     cd_candcol R[c][I] = V[I][cand_c]                               (ERI columns)
 //     cd_gather  P[j][c] = L[j][cand_c]                               j < k0
-//     cd_pass    R[c][I] = V[I][cand_c] - sum_{j<k0} L[j][I] P[j][c]  (one read of L,
+//     cd_pass    R[c][I] -= sum_{j<k0} L[j][I] P[j][c]                (one read of L,
 //                FP64 MFMA)
-//   every step k, ONE launch (cd_step), each 64-row block:
+//   every step k, ONE launch (cd_step), each block of one (or, for many tiles, four)
+//   64-row tiles:
 //     - picks the pivot itself from the previous step's tile records (largest and
 //       smallest residual of each 64-row tile, and its lowest row within the tie window of its
 //       largest): one sweep over all records, or for many tiles 64 super-tile maxima
@@ -194,80 +196,6 @@ __device__ __forceinline__ double block_max(double v, double *sh)
     if (threadIdx.x == 0) sh[0] = v;
     __syncthreads();
     return sh[0];
-}
-
-template <int NT>
-__device__ __forceinline__ double block_min(double v, double *sh)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    v = (threadIdx.x < NT / 64) ? sh[threadIdx.x] : INFINITY;
-    if (w == 0)
-        for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    __syncthreads();
-    if (threadIdx.x == 0) sh[0] = v;
-    __syncthreads();
-    return sh[0];
-}
-
-template <int NT>
-__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *sh)
-{
-    for (int o = 32; o > 0; o >>= 1) {
-        int64_t u = __shfl_xor(v, o, 64);
-        v = u < v ? u : v;
-    }
-    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    v = (threadIdx.x < NT / 64) ? sh[threadIdx.x] : INT64_MAX;
-    if (w == 0)
-        for (int o = 32; o > 0; o >>= 1) {
-            int64_t u = __shfl_xor(v, o, 64);
-            v = u < v ? u : v;
-        }
-    __syncthreads();
-    if (threadIdx.x == 0) sh[0] = v;
-    __syncthreads();
-    return sh[0];
-}
-
-
-// (value, index) argmax: larger value wins, lower index on equal values
-__device__ __forceinline__ void amax_merge(double &v, int64_t &i, double v2, int64_t i2)
-{
-    if (v2 > v || (v2 == v && i2 < i)) {
-        v = v2;
-        i = i2;
-    }
-}
-
-template <int NT>
-__device__ __forceinline__ void block_argmax(double &v, int64_t &idx, double *shv, int64_t *shi)
-{
-    for (int o = 32; o > 0; o >>= 1) {
-        double v2 = __shfl_xor(v, o, 64);
-        int64_t i2 = __shfl_xor(idx, o, 64);
-        amax_merge(v, idx, v2, i2);
-    }
-    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) {
-        shv[w] = v;
-        shi[w] = idx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < NT / 64; ++k) amax_merge(shv[0], shi[0], shv[k], shi[k]);
-    }
-    __syncthreads();
-    v = shv[0];
-    idx = shi[0];
-    __syncthreads();
 }
 
 template <int NT>

@@ -36,6 +36,8 @@ enum CdsSlot {
     WS_AD_TMP2,
     WS_MP_G,        // MP2: integral chunk
     WS_MP_S,        // MP2: per-(a, b) sums
+    WS_DY_G,        // self-energy matrix: integrals of all selected orbitals
+    WS_DY_PART,     // self-energy matrix: partial pair sums
     WS_SLOTS
 };
 
