@@ -40,7 +40,24 @@ def parse():
     p.add_argument("--workload", default="c60", choices=["c60", "large"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-targets", type=int, default=4, help="targets in the oracle Newton sample")
+    p.add_argument("--quick", action="store_true",
+                   help="timed steps and roofline only (no precision, MP2, sweep, aCD or Dyson reports)")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run an elementwise device copy of MIB MiB three times (scales HBM counters)")
     return p.parse_args()
+
+
+def copy_probe(mib: int):
+    """y = 2 x over MIB MiB of float64: reads and writes MIB MiB per launch, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the other kernels to bytes."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
 
 
 def progress(msg: str):
@@ -92,6 +109,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding "
               "of this path is a design note, not part of this build.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
     import paper_0912_1459_amd.core as C
     from paper_0912_1459_amd import inputs as I
@@ -190,6 +210,14 @@ def main():
                     "traffic": traffic.get("cd_step_kernel"), "launches": n_step / args.steps,
                     "avg_launch_us": round(avg * 1e6, 3),
                     "units": "pairs x (8 B per vector subtracted + 34..66 B) per launch"}
+
+    if args.quick:
+        print(json.dumps({"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+                          "higher_is_better": True, "roofline": roofline,
+                          "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M,
+                                 "kernels": cd_kernels}}))
+        return
 
     progress("precision report")
     # per-precision contraction throughput and accuracy against the FP64 GPU path

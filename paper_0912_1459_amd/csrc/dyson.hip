@@ -144,14 +144,17 @@ __global__ __launch_bounds__(DY_NT) void sigma_pairs_kernel(const GT *__restrict
     }
 }
 
-// out[q] = sum_b part[b][q] in block order, q over pairs x DY_TT x 2
+// out[q] = sum_b part[b][q], q over pairs x DY_TT x 2: one wave per output, lane l sums
+// blocks l, l+64, ... in order, then a fixed shuffle tree (deterministic)
 __global__ void pairs_reduce_kernel(const double *__restrict__ part, int nblk, int64_t nq, double *__restrict__ out)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (q >= nq) return;                                   // whole waves leave together
     double a = 0.0;
-    for (int b = 0; b < nblk; ++b) a += part[(int64_t)b * nq + q];
-    out[q] = a;
+    for (int b = l; b < nblk; b += 64) a += part[(int64_t)b * nq + q];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (l == 0) out[q] = a;
 }
 
 // cyclic Jacobi for a symmetric n x n matrix (row-major, destroyed): eigenvalues w,
@@ -266,7 +269,7 @@ int dy_eval(cds_ctx *ctx, const DyState &S, int T, const double *h_w, double *h_
                            (const float *)S.G, S.nsel, S.nmo, S.nocc, S.nvirt, S.nvo, S.eps,
                            (const double *)S.d_omega, T, S.nA, S.nE, S.cpb, S.part);
     CDS_LAUNCHED(ctx);
-    hipLaunchKernelGGL(pairs_reduce_kernel, dim3((unsigned)cds_ceil_div(nq, 256)), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL(pairs_reduce_kernel, dim3((unsigned)cds_ceil_div(nq, 4)), dim3(256), 0, ctx->stream,
                        (const double *)S.part, S.nblk, nq, S.out);
     CDS_LAUNCHED(ctx);
     CDS_HIP(ctx, hipMemcpyAsync(hb, S.out, (size_t)nq * 8, hipMemcpyDeviceToHost, ctx->stream));
