@@ -190,6 +190,9 @@ def main():
                  "gbs": round(st["bytes_cd_pass"] / t_pass / 1e9, 1) if t_pass > 0 else None,
                  "tflops_fp64": round(st["flops_cd_pass"] / t_pass / 1e12, 2) if t_pass > 0 else None},
         "misses_per_cd": st["n_cd_miss"] / args.steps,
+        "speculative": {"blocks_per_cd": st["n_cd_spec_block"] / args.steps,
+                        "steps_per_cd": st["n_cd_spec"] / args.steps,
+                        "ms_per_cd": round(st["t_cd_spec_ms"] / args.steps, 3)},
     }
     traffic = committed_traffic()
     if t_pass >= t_step:

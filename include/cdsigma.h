@@ -104,6 +104,9 @@ typedef struct cds_stats {
     double t_mp2_ms;         /* MP2 energies (contraction + reduction)        */
     double flops_mp2;        /* 2 nvec x rows x columns of the MP2 contractions */
     double t_dyson_ms;       /* self-energy matrices and Dyson pole searches  */
+    double t_cd_spec_ms;     /* speculative blocks (with kernel timing on)    */
+    int64_t n_cd_spec;       /* Cholesky steps committed by speculative blocks */
+    int64_t n_cd_spec_block; /* speculative blocks tried                      */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -123,8 +126,18 @@ int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
  * forms the residual columns of up to 64 candidate pivots (the next pivot and
  * the largest residual diagonals); steps whose pivot is a candidate then only
  * subtract the vectors made since.  0 disables it (each step streams all of L).
- * Default 16; valid range [0, 256]. */
+ * Default 32; valid range [0, 256]. */
 int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
+/* Speculative look-ahead blocks of the Cholesky decomposition: 1 (default)
+ * = after each look-ahead pass, the next (up to 32) steps restricted to the
+ * candidates are decomposed in one small kernel, one launch makes those vectors
+ * for every row and checks that no other row would have been chosen, the steps
+ * before the first failing one are committed, and the next look-ahead block
+ * starts there (a per-step kernel only when nothing could be committed);
+ * 0 = a look-ahead pass every block_steps steps and per-step kernels.  Used
+ * with the one-sweep pivot search (at most 1024 tiles).  The pivots are the
+ * same either way. */
+int cds_set_cd_speculate(cds_ctx *ctx, int32_t on);
 /* Cholesky code path by problem size: 0 (default) = automatic; 1 = the path of
  * large pair counts at any size (pivot search through 64 super-tile maxima,
  * then tiles, then rows, instead of one sweep over all 64-row tile records; four

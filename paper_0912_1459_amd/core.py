@@ -110,6 +110,10 @@ class Context:
         """FP32/bf16x3 transforms computed in FP64 with only the output rounded (True)."""
         self.check(self.lib.cds_set_transform_fp64(self.h, int(bool(on))))
 
+    def set_cd_speculate(self, on: bool):
+        """Speculative look-ahead blocks in the Cholesky decomposition (default on)."""
+        self.check(self.lib.cds_set_cd_speculate(self.h, int(bool(on))))
+
     def set_cd_large_path(self, on: bool):
         """Cholesky code path of large pair counts (hierarchical pivot search, four tiles per
         step block) at any size (True), or chosen by size (False)."""

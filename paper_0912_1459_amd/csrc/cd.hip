@@ -6,18 +6,25 @@
 // Each step k picks the pivot p (lowest index within the tie window of the largest residual
 // diagonal), forms the residual column c = V[:,p] - sum_{j<k} L[j] L[j][p], sets
 // L[k] = c / sqrt(D_p) and updates D.  Done literally, step k streams k*npairs*8
-// bytes of L.  This implementation forms the same residual columns with a
-// look-ahead over candidate pivots, which leaves the pivot sequence unchanged:
-//
-//   every `block_steps` steps (default 16; block start at step k0):
+// bytes of L and needs a grid-wide argmax before the next step.  This implementation
+// makes the same steps (same pivot rule, the vectors equal to rounding) in look-ahead
+// blocks that start at step k0:
 //     cd_cand    the pivot of step k0 plus the rows with the largest residual
 //                diagonals (CD_NCAND candidates in all)
 //     cd_candcol R[c][I] = V[I][cand_c]                               (ERI columns)
 //     cd_gather  P[j][c] = L[j][cand_c]                               j < k0
 //     cd_pass    R[c][I] -= sum_{j<k0} L[j][I] P[j][c]                (one read of L,
 //                FP64 MFMA)
-//   every step k, ONE launch (cd_step), each block of one (or, for many tiles, four)
-//   64-row tiles:
+//   speculative block (default, one-sweep pivot search):
+//     cd_spec    the next steps restricted to the candidates (one wave, their 64 x 64
+//                residual block in LDS): pivots, sqrt(D_p), the pivots' rows
+//     cd_rows    those vectors for every row, with a check per step that no row
+//                outside the candidates would have changed the pivot choice
+//     cd_commit  the steps before the first failing one become real (D, mask, tile
+//                records, pivots); the next block starts there
+//   per-step kernel (block_steps steps per block when speculation is off, or when
+//   nothing could be committed): ONE launch per step (cd_step), each block of one
+//   (or, for many tiles, four) 64-row tiles:
 //     - picks the pivot itself from the previous step's tile records (largest and
 //       smallest residual of each 64-row tile, and its lowest row within the tie window of its
 //       largest): one sweep over all records, or for many tiles 64 super-tile maxima
@@ -52,6 +59,7 @@ constexpr int CD_NCAND = 64;            // candidate residual columns per look-a
 constexpr int CD_PASS_JC = 32;          // candidate-row entries staged per pass chunk
 constexpr int CD_TPT = 4;               // tile records per thread in the flat pivot search
 constexpr int CD_ONE_TILE_MAX = 1280;   // tiles up to which a step block holds one tile
+constexpr int CD_SPEC_MAX = 32;         // steps of one speculative look-ahead block
 constexpr int CD_CAND_MAXTILE = 8192;   // tiles the candidate selection handles (look-ahead
                                         // is off above 8192 * 64 pairs)
 
@@ -68,6 +76,7 @@ struct CdState {
     int32_t pad;
     int64_t nmiss;   // steps whose pivot was not a candidate
     double bytes;    // bytes the step kernels must move (algorithmic, per the formula at the update)
+    int64_t nspec;   // steps committed by speculative blocks
     int64_t kdone;   // step whose launch found a termination rule (INT64_MAX before): later
                      // launches return at once; blocks of that same launch all still see it
                      // as not earlier than their step, so no block splits on it
@@ -255,6 +264,51 @@ __device__ __forceinline__ double wave_min(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
     return v;
 }
+// Wave reductions through DPP row operations (quad swaps, half-row and row mirrors) and
+// four lane reads, instead of six rounds of cross-lane permutes: result in every lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+__device__ __forceinline__ double wave_max_dpp(double v)
+{
+    v = fmax(v, dpp_f64<0xB1>(v));     // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_f64<0x4E>(v));     // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_f64<0x141>(v));    // row_half_mirror
+    v = fmax(v, dpp_f64<0x140>(v));    // row_mirror: every lane holds its 16-lane row maximum
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+__device__ __forceinline__ int64_t i64_min(int64_t a, int64_t b) { return b < a ? b : a; }
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_i64(int64_t v)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)(v & 0xffffffff), (int)(v & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(v >> 32), (int)(v >> 32), CTRL, 0xF, 0xF, false);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t wave_min_i64_dpp(int64_t v)
+{
+    v = i64_min(v, dpp_i64<0xB1>(v));
+    v = i64_min(v, dpp_i64<0x4E>(v));
+    v = i64_min(v, dpp_i64<0x141>(v));
+    v = i64_min(v, dpp_i64<0x140>(v));
+    return i64_min(i64_min(readlane_i64(v, 0), readlane_i64(v, 16)), i64_min(readlane_i64(v, 32), readlane_i64(v, 48)));
+}
+
 __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
 {
     for (int o = 32; o > 0; o >>= 1) {
@@ -700,6 +754,198 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     }
 }
 
+// ---- speculative look-ahead block ---------------------------------------------
+// After a look-ahead pass the candidates' residual columns are known, so the next
+// steps restricted to the candidates form a small pivoted Cholesky problem
+// (cd_spec_kernel, one wave, one candidate per lane; its first pivot is the true one,
+// since the candidates hold the largest residuals and the pivot of step k0).
+// cd_rows_kernel then makes those vectors for every row in one launch and checks every
+// step: step j stands if no
+// eligible row has a residual above the candidates' maximum, nor a residual in its tie
+// window at a lower index than the chosen pivot (candidate rows cannot, since both
+// kernels evaluate them with the same operations), nor any non-pivot row a residual
+// below -psd_tol.  The host commits the steps before the first one that fails
+// (cd_commit_kernel) and starts the next block there.
+struct SpecOut {
+    int32_t nspec;           // speculated steps
+    uint32_t viol;           // bit j: step j does not stand (atomicOr by cd_rows_kernel)
+    int64_t p[CD_SPEC_MAX];  // pivots
+    int32_t slot[CD_SPEC_MAX];
+    double sq[CD_SPEC_MAX], cmax[CD_SPEC_MAX], thr[CD_SPEC_MAX];
+    double lpiv[CD_SPEC_MAX][CD_SPEC_MAX];   // lpiv[i][j] = L[k0+i][p_j], i < j
+};
+
+__global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, int r, int nmax,
+                                                     const double *__restrict__ R, int64_t ldr,
+                                                     const int64_t *__restrict__ cand, const CdState *st,
+                                                     SpecOut *so)
+{
+    // lane c = candidate c; its column of the speculated vectors stays in registers (lc), the
+    // pivot's entries come by lane shuffles, the candidates' residual columns from LDS
+    __shared__ double Rcc[CD_NCAND][CD_NCAND + 1];   // Rcc[s][c] = R[s][cand_c]
+    __shared__ double Lc[CD_SPEC_MAX][64];
+    __shared__ __align__(16) double Lt[64][CD_SPEC_MAX + 2];  // Lt[c][i] = L[k0+i][cand_c]
+    __shared__ int64_t spj[CD_SPEC_MAX];
+    __shared__ int ssj[CD_SPEC_MAX];
+    __shared__ double ssq[CD_SPEC_MAX], scm[CD_SPEC_MAX], sth[CD_SPEC_MAX];
+    const int l = threadIdx.x;
+    const int nc = (st->done || st->ncand == 0) ? 0 : st->ncand;
+    const bool have = l < nc;
+    const int64_t I = have ? cand[l] : -1;
+    double d = have ? b.D[r][I] : 0.0;
+    unsigned char m = have ? b.mask[r][I] : 1;
+    for (int s = 0; s < nc; ++s) Rcc[s][l] = have ? R[(int64_t)s * ldr + I] : 0.0;
+    if (l < CD_SPEC_MAX) {
+        spj[l] = -1;
+        ssj[l] = 0;
+        ssq[l] = scm[l] = sth[l] = 0.0;
+    }
+    __syncthreads();
+    double lc[CD_SPEC_MAX];
+#pragma unroll
+    for (int j = 0; j < CD_SPEC_MAX; ++j) lc[j] = 0.0;
+    int nspec = 0;
+    bool alive = true;                                    // uniform over the wave
+#pragma unroll
+    for (int j = 0; j < CD_SPEC_MAX; ++j) {
+        if (j >= nmax) alive = false;
+        if (!alive) continue;
+        const bool elig = have && m == 0;
+        const double cmax = wave_max_dpp(elig ? d : -INFINITY);
+        if (cmax == -INFINITY || cmax <= cp.delta) alive = false;   // termination: per-step path
+        if (!alive) continue;
+        const double thr = cmax - tie_window(cmax, cp.tau);
+        const int64_t pm = wave_min_i64_dpp((elig && d >= thr) ? I : INT64_MAX);
+        if (pm == INT64_MAX) alive = false;                         // non-finite residuals
+        if (alive) {
+            const unsigned long long bs = __ballot(have && I == pm);
+            const int slot = __ffsll((long long)bs) - 1;
+            const double sq = sqrt(__shfl(d, slot, 64));
+            double c = Rcc[slot][l];
+            const double *lp = &Lt[slot][0];                                        // L[k0+i][p_j]
+#pragma unroll
+            for (int i = 0; i < j; ++i) c = fma(-lc[i], lp[i], c);
+            double lj;
+            if (m == 1) {
+                lj = 0.0;
+            } else if (l == slot) {
+                lj = sq;
+                d = 0.0;
+                m = 1;
+            } else {
+                lj = c / sq;
+                d = fma(-lj, lj, d);
+            }
+            lc[j] = lj;
+            Lt[l][j] = lj;
+            __syncthreads();
+            if (l == 0) {
+                spj[j] = pm;
+                ssj[j] = slot;
+                ssq[j] = sq;
+                scm[j] = cmax;
+                sth[j] = thr;
+            }
+            nspec = j + 1;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < CD_SPEC_MAX; ++i) Lc[i][l] = lc[i];
+    __syncthreads();
+    // lpiv[i][j] = L[k0+i][p_j]
+    for (int q = l; q < CD_SPEC_MAX * CD_SPEC_MAX; q += 64) {
+        const int i = q / CD_SPEC_MAX, j = q % CD_SPEC_MAX;
+        so->lpiv[i][j] = (i < j && j < nspec) ? Lc[i][ssj[j]] : 0.0;
+    }
+    if (l < CD_SPEC_MAX) {
+        so->p[l] = spj[l];
+        so->slot[l] = ssj[l];
+        so->sq[l] = ssq[l];
+        so->cmax[l] = scm[l];
+        so->thr[l] = sth[l];
+    }
+    if (l == 0) {
+        so->nspec = nspec;
+        so->viol = 0u;
+    }
+}
+
+// every row: the speculated vectors L[k0+j] (same operations as cd_spec_kernel), the
+// residual after each (Dbuf[j][I] = D after vector j) and the step checks
+__global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, int r, int64_t k0,
+                                                      const double *__restrict__ R, int64_t ldr, double *__restrict__ L,
+                                                      int64_t ldl, double *__restrict__ Dbuf, SpecOut *so)
+{
+    __shared__ SpecOut ss;
+    for (int q = threadIdx.x; q < (int)(sizeof(SpecOut) / 8); q += 256)
+        ((int64_t *)&ss)[q] = ((const int64_t *)so)[q];
+    __syncthreads();
+    const int ns = ss.nspec;
+    const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool ok = I < cp.npairs;
+    unsigned char m = ok ? b.mask[r][I] : 1;
+    double d = ok ? b.D[r][I] : 0.0;
+    double rv[CD_SPEC_MAX];
+#pragma unroll
+    for (int j = 0; j < CD_SPEC_MAX; ++j) rv[j] = (ok && j < ns) ? R[(int64_t)ss.slot[j] * ldr + I] : 0.0;
+    double lv[CD_SPEC_MAX];
+    unsigned viol = 0u;
+#pragma unroll
+    for (int j = 0; j < CD_SPEC_MAX; ++j) {
+        lv[j] = 0.0;
+        if (j >= ns || !ok) continue;
+        if (m == 0 && (d > ss.cmax[j] || (d >= ss.thr[j] && I < ss.p[j]))) viol |= 1u << j;
+        if (m != 1 && d < -cp.psd_tol) viol |= 1u << j;     // NOT_PSD is the per-step path's call
+        double lj;
+        if (m == 1) {
+            lj = 0.0;
+        } else if (I == ss.p[j]) {
+            lj = ss.sq[j];
+            d = 0.0;
+            m = 1;
+        } else {
+            double c = rv[j];
+#pragma unroll
+            for (int i = 0; i < j; ++i) c = fma(-lv[i], ss.lpiv[i][j], c);
+            lj = c / ss.sq[j];
+            d = fma(-lj, lj, d);
+        }
+        lv[j] = lj;
+        L[(k0 + j) * ldl + I] = lj;
+        Dbuf[(int64_t)j * cp.npairs + I] = d;
+    }
+    // wave OR, one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) viol |= (unsigned)__shfl_xor((int)viol, o, 64);
+    if ((threadIdx.x & 63) == 0 && viol) atomicOr(&so->viol, viol);
+}
+
+// commit the first nc speculated steps: residuals, pivot marks and tile records into the
+// buffers of parity w (the step k0 + nc reads them), pivots and the state
+__global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, int r, int w, int64_t k0, int nc,
+                                                        const double *__restrict__ Dbuf, const SpecOut *so,
+                                                        CdState *st, int64_t *__restrict__ piv)
+{
+    const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool ok = I < cp.npairs;
+    unsigned char m = ok ? b.mask[r][I] : 1;
+    double d = 0.0;
+    if (ok) {
+        d = Dbuf[(int64_t)(nc - 1) * cp.npairs + I];
+        for (int j = 0; j < nc; ++j)
+            if (I == so->p[j]) m = 1;
+        b.D[w][I] = d;
+        b.mask[w][I] = m;
+    }
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile < b.ntile) tile_record(b, w, 0, cp, tile, ok && m == 0, ok && m != 1, d);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int j = 0; j < nc; ++j) piv[k0 + j] = so->p[j];
+        st->k = k0 + nc;
+        st->dmax = so->cmax[nc - 1];
+        st->nspec += nc;
+    }
+}
+
 // Boundary of the top `want` nonzero keys held in registers (KPT per thread, 0 = no key):
 // four 8-bit radix passes over the key bits; returns the top 32 bits of the boundary key.
 // Every thread of the block calls it.
@@ -1065,10 +1311,12 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     // workspace: D copy, ERI diagonal, candidate rows P (max_vec x NCAND), residual columns R
     void *w_part, *w_tile, *w_mask, *w_state;
     const size_t nP = (size_t)max_vec * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
-    CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR) * 8 + 256, &w_part));
+    const bool spec_on = bsteps > 0 && ctx->cd_speculate && ntile <= (int64_t)CD_NT * CD_TPT && !ctx->cd_large_path;
+    const size_t nDb = spec_on ? (size_t)CD_SPEC_MAX * npairs : 0;
+    CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR + nDb) * 8 + 256, &w_part));
     CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
     CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)2 * npairs, &w_mask));
-    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + 64, &w_state));
+    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + sizeof(SpecOut) + 64, &w_state));
     double *D1 = (double *)w_part;
     double *diag = D1 + npairs;
     double *Pc = diag + npairs;
@@ -1091,6 +1339,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     double *dscratch = (double *)(sb + 6 * CD_NSUP);
     CdState *st = (CdState *)w_state;
     int64_t *cand = (int64_t *)(st + 1);
+    SpecOut *so = (SpecOut *)(cand + CD_NCAND);
+    double *Dbuf = Rc + nR;
 
     // largest ERI diagonal (for the default tie window / PSD tolerance)
     if (dense)
@@ -1138,7 +1388,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)ntile), dim3(CD_TILE), 0, ctx->stream, bf, cp);
     CDS_LAUNCHED(ctx);
 
-    int64_t k = nvec_in, k0 = nvec_in;
+    int64_t k = nvec_in, k0 = nvec_in, next_start = nvec_in;
     int batch = 16;                     // batch ends fall on look-ahead block starts (16, 32, 64)
     CdState hs = {};
     const dim3 grid((unsigned)ntile);
@@ -1157,15 +1407,17 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         // steps k <= max_vec: the step at k == max_vec only records the termination (CAP or
         // convergence) and writes no vector
         for (int bi = 0; bi < batch && k <= max_vec; ++bi, ++k) {
-            const int64_t s = k - nvec_in;
-            const int r = (int)(s & 1), sr = (int)(s % 3), sw = (int)((s + 1) % 3), sz = (int)((s + 2) % 3);
-            if (bsteps > 0 && s % bsteps == 0 && k < max_vec) {
+            int64_t s = k - nvec_in;
+            const int r = (int)(s & 1), sr = (int)(s % 3);
+            const bool block_start = bsteps > 0 && k == next_start;
+            if (block_start && k < max_vec) {
                 // look-ahead block start: candidates, their rows, one pass over L
                 if (run_timed) {
                     CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
                     run_timed = false;
                 }
                 k0 = k;
+                if (!spec_on) next_start = k + bsteps;
                 hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
                                    st, cand);
                 CDS_LAUNCHED(ctx);
@@ -1190,7 +1442,54 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
                 ctx->stats.n_cd_pass_launch += 1;
+                if (spec_on) {
+                    // speculative block: the candidates' own decomposition, all rows, the check
+                    const int nmax = (int)std::min<int64_t>(std::min(bsteps, CD_SPEC_MAX), max_vec - k);
+                    CdsTimer tsp;
+                    if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
+                    hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, r, nmax,
+                                       (const double *)Rc, ldr, (const int64_t *)cand, (const CdState *)st, so);
+                    CDS_LAUNCHED(ctx);
+                    hipLaunchKernelGGL(cd_rows_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
+                                       ctx->stream, bf, cp, r, k, (const double *)Rc, ldr, L, ldl, Dbuf, so);
+                    CDS_LAUNCHED(ctx);
+                    if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
+                    unsigned char *hq = (unsigned char *)hp + 128;
+                    CDS_HIP(ctx, hipMemcpyAsync(hq, so, 8, hipMemcpyDeviceToHost, ctx->stream));
+                    CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
+                    CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                    const int nspec = ((const int32_t *)hq)[0];
+                    const uint32_t viol = ((const uint32_t *)hq)[1];
+                    if (((const CdState *)hp)->done) break;   // the state is re-read and ends the loop
+                    ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)k + 8.0 * CD_NCAND * (double)npairs;
+                    ctx->stats.flops_cd_pass += 2.0 * (double)npairs * (double)k * CD_NCAND;
+                    ctx->stats.n_cd_pass += 1;
+                    int nc = 0;
+                    while (nc < nspec && !(viol & (1u << nc))) ++nc;
+                    ctx->stats.n_cd_spec_block += 1;
+                    // the next look-ahead block starts where this one stopped (after one per-step
+                    // kernel if nothing could be committed: a termination or a failed first step);
+                    // a new block at a failure measured faster than per-step kernels to the end
+                    // of a fixed block
+                    next_start = k + std::max(nc, 1);
+                    if (nc > 0) {
+                        const int w = (int)((s + nc) & 1);
+                        CdsTimer tcm;
+                        if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tcm));
+                        hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
+                                           ctx->stream, bf, cp, r, w, k, nc, (const double *)Dbuf,
+                                           (const SpecOut *)so, st, piv);
+                        CDS_LAUNCHED(ctx);
+                        if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tcm, &ctx->stats.t_cd_spec_ms));
+                        ctx->stats.n_cd_spec += nc;
+                        k += nc;
+                        bi += nc;
+                        --k;                  // the loop increment lands on the next block start
+                        continue;
+                    }
+                }
             }
+            const int r2 = (int)(s & 1), sr2 = (int)(s % 3), sw2 = (int)((s + 1) % 3), sz2 = (int)((s + 2) % 3);
             // one event pair around each run of consecutive step launches (a pair around
             // every launch would add its own overhead to each)
             if (ctx->kernel_timing && !run_timed) {
@@ -1198,11 +1497,11 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 run_timed = true;
             }
             if (dense)
-                launch_step_any<true>(ctx, vw, tb, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc, ldr,
-                                      cand, st, piv);
+                launch_step_any<true>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
+                                      ldr, cand, st, piv);
             else
-                launch_step_any<false>(ctx, vw, tb, bf, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, Rc, ldr,
-                                       cand, st, piv);
+                launch_step_any<false>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
+                                       ldr, cand, st, piv);
             CDS_LAUNCHED(ctx);
             ctx->stats.n_cd_step_launch += 1;
         }
@@ -1222,7 +1521,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     ctx->stats.n_cd_steps += hs.k - nvec_in;
     // passes that did work: block starts before the final k (8 npairs B per vector read, one
     // row of R written per candidate; 2 flops per vector, pair and candidate slot)
-    if (bsteps > 0)
+    if (bsteps > 0 && !spec_on)
         for (int64_t j = nvec_in; j < hs.k; j += bsteps) {
             ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)j + 8.0 * CD_NCAND * (double)npairs;
             ctx->stats.flops_cd_pass += 2.0 * (double)npairs * (double)j * CD_NCAND;
@@ -1302,6 +1601,14 @@ int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps)
     if (block_steps < 0 || block_steps > 256)
         return cds_fail(ctx, CDS_EINVAL, "block_steps must be in [0, 256]");
     ctx->cd_lookahead = block_steps;
+    return CDS_OK;
+}
+
+int cds_set_cd_speculate(cds_ctx *ctx, int32_t on)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (on != 0 && on != 1) return cds_fail(ctx, CDS_EINVAL, "on must be 0 or 1");
+    ctx->cd_speculate = on;
     return CDS_OK;
 }
 

@@ -139,6 +139,31 @@ def test_cd_large_path(cds, name, delta, lookahead):
     assert np.all(np.abs(got.L.cpu().numpy().T - ref.L).max(axis=0) <= tol)
 
 
+@pytest.mark.parametrize("name,delta", [("plain", 1e-8), ("c60", 1e-6)])
+def test_cd_speculative_blocks(cds, name, delta):
+    # speculative look-ahead blocks on and off: same pivots, vectors equal to rounding; most
+    # steps come from the speculative blocks
+    w = workload(name)
+    log(f"cd speculative blocks {name} delta={delta}")
+    c, a = _dev(w.centres), _dev(w.alpha)
+    ctx0 = cds.Context(0)
+    ctx0.set_cd_speculate(False)
+    base = cds.cholesky(delta, centres=c, alpha=a, ctx=ctx0)
+    ctx1 = cds.Context(0)
+    ctx1.set_cd_speculate(True)
+    got = cds.cholesky(delta, centres=c, alpha=a, ctx=ctx1)
+    st = ctx1.stats()
+    log(f"  {st['n_cd_spec']} of {got.nvec} steps from {st['n_cd_spec_block']} speculative blocks")
+    assert got.nvec == base.nvec and got.status == base.status
+    assert torch.equal(got.piv[: got.nvec], base.piv[: base.nvec])
+    ref = oracle_cd(name, delta)
+    assert np.array_equal(got.piv[: got.nvec].cpu().numpy(), ref.piv)
+    tol = torch.as_tensor(cd_tolerance(ref, E.eri_diagonal(w.centres, w.alpha).max()), device="cuda")
+    assert torch.all((got.L - base.L).abs().max(dim=1).values <= tol)
+    assert torch.all((got.D - base.D).abs() <= 1e3 * np.finfo(float).eps * E.eri_diagonal(w.centres, w.alpha).max())
+    assert st["n_cd_spec"] >= got.nvec // 2
+
+
 def test_cd_cap_status_and_resume(cds):
     w = workload("plain")
     log("cd cap plain")
