@@ -794,7 +794,15 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, int 
     const int64_t I = have ? cand[l] : -1;
     double d = have ? b.D[r][I] : 0.0;
     unsigned char m = have ? b.mask[r][I] : 1;
-    for (int s = 0; s < nc; ++s) Rcc[s][l] = have ? R[(int64_t)s * ldr + I] : 0.0;
+    // the candidates' 64 x 64 residual block, 16 loads in flight per lane
+#pragma unroll
+    for (int s0 = 0; s0 < CD_NCAND; s0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = (have && s0 + u < nc) ? R[(int64_t)(s0 + u) * ldr + I] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Rcc[s0 + u][l] = v[u];
+    }
     if (l < CD_SPEC_MAX) {
         spj[l] = -1;
         ssj[l] = 0;
