@@ -134,9 +134,8 @@ int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
  * for every row and checks that no other row would have been chosen, the steps
  * before the first failing one are committed, and the next look-ahead block
  * starts there (a per-step kernel only when nothing could be committed);
- * 0 = a look-ahead pass every block_steps steps and per-step kernels.  Used
- * with the one-sweep pivot search (at most 1024 tiles).  The pivots are the
- * same either way. */
+ * 0 = a look-ahead pass every block_steps steps and per-step kernels.  The
+ * pivots are the same either way. */
 int cds_set_cd_speculate(cds_ctx *ctx, int32_t on);
 /* Cholesky code path by problem size: 0 (default) = automatic; 1 = the path of
  * large pair counts at any size (pivot search through 64 super-tile maxima,

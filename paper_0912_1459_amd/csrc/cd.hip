@@ -927,10 +927,22 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, int
     if ((threadIdx.x & 63) == 0 && viol) atomicOr(&so->viol, viol);
 }
 
+// empty two super-tile key buffers (before a commit on the hierarchical search path)
+__global__ void reset_super_kernel(CdBufs b, int b1, int b2)
+{
+    const int t = threadIdx.x;
+    if (t < CD_NSUP) {
+        b.smax[b1][t] = 0ull;
+        b.smin[b1][t] = ~0ull;
+        b.smax[b2][t] = 0ull;
+        b.smin[b2][t] = ~0ull;
+    }
+}
+
 // commit the first nc speculated steps: residuals, pivot marks and tile records into the
 // buffers of parity w (the step k0 + nc reads them), pivots and the state
-__global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, int r, int w, int64_t k0, int nc,
-                                                        const double *__restrict__ Dbuf, const SpecOut *so,
+__global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, int r, int w, int sw, int64_t k0,
+                                                        int nc, const double *__restrict__ Dbuf, const SpecOut *so,
                                                         CdState *st, int64_t *__restrict__ piv)
 {
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -945,7 +957,7 @@ __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, i
         b.mask[w][I] = m;
     }
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile < b.ntile) tile_record(b, w, 0, cp, tile, ok && m == 0, ok && m != 1, d);
+    if (tile < b.ntile) tile_record(b, w, sw, cp, tile, ok && m == 0, ok && m != 1, d);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int j = 0; j < nc; ++j) piv[k0 + j] = so->p[j];
         st->k = k0 + nc;
@@ -1319,7 +1331,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     // workspace: D copy, ERI diagonal, candidate rows P (max_vec x NCAND), residual columns R
     void *w_part, *w_tile, *w_mask, *w_state;
     const size_t nP = (size_t)max_vec * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
-    const bool spec_on = bsteps > 0 && ctx->cd_speculate && ntile <= (int64_t)CD_NT * CD_TPT && !ctx->cd_large_path;
+    const bool spec_on = bsteps > 0 && ctx->cd_speculate;
     const size_t nDb = spec_on ? (size_t)CD_SPEC_MAX * npairs : 0;
     CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR + nDb) * 8 + 256, &w_part));
     CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
@@ -1482,10 +1494,16 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                     next_start = k + std::max(nc, 1);
                     if (nc > 0) {
                         const int w = (int)((s + nc) & 1);
+                        const int sw3 = (int)((s + nc) % 3);    // keys the step after the block reads
                         CdsTimer tcm;
                         if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tcm));
+                        if (!bf.flat) {
+                            hipLaunchKernelGGL(reset_super_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, sw3,
+                                               (int)((s + nc + 1) % 3));
+                            CDS_LAUNCHED(ctx);
+                        }
                         hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
-                                           ctx->stream, bf, cp, r, w, k, nc, (const double *)Dbuf,
+                                           ctx->stream, bf, cp, r, w, sw3, k, nc, (const double *)Dbuf,
                                            (const SpecOut *)so, st, piv);
                         CDS_LAUNCHED(ctx);
                         if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tcm, &ctx->stats.t_cd_spec_ms));
