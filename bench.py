@@ -64,9 +64,9 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def committed_traffic() -> dict:
+def committed_traffic(workload: str) -> dict:
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, per
-    kernel, if the Cholesky source is unchanged since the counters were taken; else {}."""
+    kernel, if it was taken on this workload and the Cholesky source is unchanged since; else {}."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "cd_kernels_c60_traffic.json")
     src = os.path.join(ROOT, "paper_0912_1459_amd", "csrc", "cd.hip")
@@ -77,7 +77,7 @@ def committed_traffic() -> dict:
             sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return {}
-    if rec.get("cd_hip_sha256") != sha:
+    if rec.get("cd_hip_sha256") != sha or rec.get("workload_key") != workload:
         return {}
     return {k: v["hbm_bytes_per_launch"] for k, v in rec.get("kernels", {}).items()}
 
@@ -194,7 +194,7 @@ def main():
                         "steps_per_cd": st["n_cd_spec"] / args.steps,
                         "ms_per_cd": round(st["t_cd_spec_ms"] / args.steps, 3)},
     }
-    traffic = committed_traffic()
+    traffic = committed_traffic(args.workload)
     if t_pass >= t_step:
         # 2 flops per vector, pair row and candidate: 16 flops per byte of L, above the FP64
         # MFMA ridge (78.6 TF / 8 TB/s)
