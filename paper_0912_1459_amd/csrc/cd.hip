@@ -1153,9 +1153,11 @@ __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int6
 // Software-pipelined over chunks of CD_PASS_JC vectors: the L fragments and P rows of
 // chunk c+1 are loaded into registers while the MFMAs of chunk c run; P goes to the other
 // half of a double-buffered LDS tile after them, so one barrier per chunk suffices.
-__global__ __launch_bounds__(256) void cd_pass_kernel(const double *__restrict__ L, int64_t ldl, int64_t npairs,
+// L and P are deliberately not __restrict__: the compiler may then not move their loads
+// across the compiler barriers that hold the prefetch ahead of the MFMAs
+__global__ __launch_bounds__(256) void cd_pass_kernel(const double *L, int64_t ldl, int64_t npairs,
                                                       int64_t k0, const CdState *__restrict__ st,
-                                                      const double *__restrict__ P, double *__restrict__ R,
+                                                      const double *P, double *__restrict__ R,
                                                       int64_t ldr)
 {
     constexpr int NS = CD_PASS_JC / 4;                     // MFMA k-steps per chunk
@@ -1173,28 +1175,31 @@ __global__ __launch_bounds__(256) void cd_pass_kernel(const double *__restrict__
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = doublex4{0.0, 0.0, 0.0, 0.0};
 
+    // Every load is issued unconditionally from a clamped in-range address and nothing masks
+    // a value between its load and its use: a load under a branch, or a select right after
+    // it, makes the compiler wait for the loads in flight and so serialises the prefetch with
+    // the MFMAs.  Vectors j >= k0 meet zero entries of P (set at the LDS store) and add
+    // exactly 0; rows beyond npairs read row npairs - 1 and are never stored.
+    const int64_t rowL = rowok ? rowA : npairs - 1;
     auto load_a = [&](int64_t c, double *a) {
         const int64_t j0 = c * CD_PASS_JC;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int64_t j = j0 + 4 * s + g;
-            a[s] = (rowok && j < k0) ? L[j * ldl + rowA] : 0.0;
-        }
+        for (int s = 0; s < NS; ++s) a[s] = L[min(j0 + 4 * s + g, k0 - 1) * ldl + rowL];
     };
     auto load_p = [&](int64_t c, double *pn) {
         const int64_t j0 = c * CD_PASS_JC;
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int t = threadIdx.x + 256 * i;
-            const int64_t j = j0 + t / CD_NCAND;
-            pn[i] = j < k0 ? P[j * CD_NCAND + t % CD_NCAND] : 0.0;
+            pn[i] = P[min(j0 + t / CD_NCAND, k0 - 1) * CD_NCAND + t % CD_NCAND];
         }
     };
-    auto store_p = [&](int buf, const double *pn) {
+    auto store_p = [&](int buf, int64_t c, const double *pn) {
+        const int64_t j0 = c * CD_PASS_JC;
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int t = threadIdx.x + 256 * i;
-            sp[buf][t / CD_NCAND][t % CD_NCAND] = pn[i];
+            sp[buf][t / CD_NCAND][t % CD_NCAND] = j0 + t / CD_NCAND < k0 ? pn[i] : 0.0;
         }
     };
     auto mfma_chunk = [&](int buf, const double *a) {
@@ -1206,32 +1211,35 @@ __global__ __launch_bounds__(256) void cd_pass_kernel(const double *__restrict__
                                                                0, 0, 0);
     };
 
+    // P of the next chunk is loaded before its L rows (the wait for P before its LDS store
+    // then leaves the L loads in flight), and the prefetch is issued even past the last chunk
+    // (clamped, harmless): a prefetch under a branch would make the first MFMA wait for it
     double a0[NS], a1[NS], pn[NPT];
     if (nchunk > 0) {
-        load_a(0, a0);
         load_p(0, pn);
-        store_p(0, pn);
+        load_a(0, a0);
+        store_p(0, 0, pn);
     }
     for (int64_t c = 0; c < nchunk; c += 2) {
         // chunk c from (a0, sp[0]); prefetch chunk c+1 into (a1, sp[1])
         __syncthreads();
-        const bool n1 = c + 1 < nchunk;
-        if (n1) {
-            load_a(c + 1, a1);
-            load_p(c + 1, pn);
-        }
+        load_p(c + 1, pn);
+        __builtin_amdgcn_sched_barrier(0);      // keep the issue order: P, L, MFMAs
+        load_a(c + 1, a1);
+        asm volatile("" ::: "memory");       // no load sinks to its use
+        __builtin_amdgcn_sched_barrier(0);
         mfma_chunk(0, a0);
-        if (n1) store_p(1, pn);
-        if (!n1) break;
+        store_p(1, c + 1, pn);
+        if (c + 1 >= nchunk) break;
         // chunk c+1 from (a1, sp[1]); prefetch chunk c+2 into (a0, sp[0])
         __syncthreads();
-        const bool n2 = c + 2 < nchunk;
-        if (n2) {
-            load_a(c + 2, a0);
-            load_p(c + 2, pn);
-        }
+        load_p(c + 2, pn);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(c + 2, a0);
+        asm volatile("" ::: "memory");       // no load sinks to its use
+        __builtin_amdgcn_sched_barrier(0);
         mfma_chunk(1, a1);
-        if (n2) store_p(0, pn);
+        store_p(0, c + 2, pn);
     }
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
