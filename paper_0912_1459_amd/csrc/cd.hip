@@ -56,7 +56,8 @@ constexpr int CD_PCHUNK = 1024;         // pivot-row entries staged in LDS per c
 constexpr int CD_AUX_NT = 1024;         // threads of the one-block kernels
 constexpr int CD_NSUP = 64;             // super-tiles of the hierarchical pivot search
 constexpr int CD_NCAND = 64;            // candidate residual columns per look-ahead block
-constexpr int CD_PASS_JC = 32;          // candidate-row entries staged per pass chunk
+constexpr int CD_PASS_D = 2;            // k-steps (4 vectors each) in flight per wave in the pass
+constexpr int CD_PASS_ZROWS = 8;        // zero rows of P after row k0
 constexpr int CD_TPT = 4;               // tile records per thread in the flat pivot search
 constexpr int CD_ONE_TILE_MAX = 1280;   // tiles up to which a step block holds one tile
 constexpr int CD_SPEC_MAX = 32;         // steps of one speculative look-ahead block
@@ -1134,7 +1135,8 @@ __global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, in
     R[(int64_t)c * ldr + I] = v;
 }
 
-// P[j][c] = L[j][cand_c], j < k0, c < ncand (one thread per entry)
+// P[j][c] = L[j][cand_c], j < k0, c < ncand (one thread per entry); rows k0 .. k0 +
+// CD_PASS_ZROWS - 1 are zero (the pass reads them for vectors past k0)
 __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
                                  const int64_t *__restrict__ cand, double *__restrict__ P)
 {
@@ -1142,115 +1144,115 @@ __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int6
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t j = e / CD_NCAND;
     const int c = (int)(e % CD_NCAND);
-    if (j >= k0) return;
-    P[e] = c < st->ncand ? L[j * ldl + cand[c]] : 0.0;
+    if (j >= k0 + CD_PASS_ZROWS) return;
+    P[e] = (j < k0 && c < st->ncand) ? L[j * ldl + cand[c]] : 0.0;
 }
 
 // R[c][I] -= sum_{j<k0} L[j][I] P[j][c] for all candidates (R holds V[I][cand_c]), one
 // read of L.
-// Block = 64 rows x 4 waves; wave w: rows [16w, 16w+16) x 64 candidates = 4 f64 MFMA blocks
-// (v_mfma_f64_16x16x4f64: A = L rows (lane l: row l%16, k l/16), B = P from LDS).
-// Software-pipelined over chunks of CD_PASS_JC vectors: the L fragments and P rows of
-// chunk c+1 are loaded into registers while the MFMAs of chunk c run; P goes to the other
-// half of a double-buffered LDS tile after them, so one barrier per chunk suffices.
-// L and P are deliberately not __restrict__: the compiler may then not move their loads
-// across the compiler barriers that hold the prefetch ahead of the MFMAs
-__global__ __launch_bounds__(256) void cd_pass_kernel(const double *L, int64_t ldl, int64_t npairs,
-                                                      int64_t k0, const CdState *__restrict__ st,
-                                                      const double *P, double *__restrict__ R,
-                                                      int64_t ldr)
+// Block = 64 rows; its 4 waves split the vectors (k-steps of 4) into four contiguous
+// ranges and each forms the whole 64 x 64 block over its range with 16 f64 MFMA tiles
+// (v_mfma_f64_16x16x4f64: A = L, lane l: row l%16 of a 16-row group, vector l/16;
+// B = P, lane l: candidate l%16 of a 16-candidate group, vector l/16).  Both operands go
+// straight from memory to registers (P is small and stays in L2) through a ring of
+// CD_PASS_D k-steps, so the main loop has no LDS traffic and no barrier.  The four
+// partial blocks are then summed through LDS in a fixed order, (w0 + w2) + (w1 + w3).
+// Every load is issued from a clamped in-range address; vectors past a wave's range read a
+// zero row of P and add exactly 0.  L and P are deliberately not __restrict__: the
+// compiler may then not move their loads across the compiler barrier that keeps the ring
+// ahead of the MFMAs.
+__global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_t ldl, int64_t npairs,
+                                                         int64_t k0, const CdState *__restrict__ st,
+                                                         const double *P, double *__restrict__ R,
+                                                         int64_t ldr)
 {
-    constexpr int NS = CD_PASS_JC / 4;                     // MFMA k-steps per chunk
-    constexpr int NPT = CD_PASS_JC * CD_NCAND / 256;       // P entries per thread per chunk
-    __shared__ double sp[2][CD_PASS_JC][CD_NCAND];
+    constexpr int D = CD_PASS_D;
+    __shared__ double red[2][CD_NCAND][CD_TILE];           // red[slot][cand][row ^ cand]
     if (st->done || st->ncand == 0) return;
     const int nc = st->ncand;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
     const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
-    const int64_t rowA = tile0 + 16 * w + r16;
-    const bool rowok = rowA < npairs;
-    const int64_t nchunk = (k0 + CD_PASS_JC - 1) / CD_PASS_JC;
-    doublex4 acc[4];
+    int64_t rowL[4];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) acc[nb] = doublex4{0.0, 0.0, 0.0, 0.0};
-
-    // Every load is issued unconditionally from a clamped in-range address and nothing masks
-    // a value between its load and its use: a load under a branch, or a select right after
-    // it, makes the compiler wait for the loads in flight and so serialises the prefetch with
-    // the MFMAs.  Vectors j >= k0 meet zero entries of P (set at the LDS store) and add
-    // exactly 0; rows beyond npairs read row npairs - 1 and are never stored.
-    const int64_t rowL = rowok ? rowA : npairs - 1;
-    auto load_a = [&](int64_t c, double *a) {
-        const int64_t j0 = c * CD_PASS_JC;
+    for (int m = 0; m < 4; ++m) rowL[m] = min(tile0 + 16 * m + r16, npairs - 1);
+    const int64_t ks = (k0 + 3) / 4;                       // k-steps
+    const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
+    const int64_t jz = 4 * ks;                             // a zero row of P (k0 <= jz < k0 + 4)
+    const int64_t jl_max = k0 > 0 ? k0 - 1 : 0;
+    doublex4 acc[4][4];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = L[min(j0 + 4 * s + g, k0 - 1) * ldl + rowL];
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double a[D][4], b[D][4];
+    auto load = [&](int64_t s, double *as, double *bs) {
+        const int64_t j = 4 * s + g;
+        const int64_t jl = min(j, jl_max);                 // L row: finite
+        const int64_t jp = s < s1 ? j : jz;                // P row: zero past the range
+#pragma unroll
+        for (int m = 0; m < 4; ++m) as[m] = L[jl * ldl + rowL[m]];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bs[n] = P[jp * CD_NCAND + 16 * n + r16];
     };
-    auto load_p = [&](int64_t c, double *pn) {
-        const int64_t j0 = c * CD_PASS_JC;
+    if (k0 > 0) {
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int t = threadIdx.x + 256 * i;
-            pn[i] = P[min(j0 + t / CD_NCAND, k0 - 1) * CD_NCAND + t % CD_NCAND];
+        for (int i = 0; i < D; ++i) {
+            load(s0 + i, a[i], b[i]);                // slot order, as in the loop
+            __builtin_amdgcn_sched_barrier(0);
         }
-    };
-    auto store_p = [&](int buf, int64_t c, const double *pn) {
-        const int64_t j0 = c * CD_PASS_JC;
+        for (int64_t s = s0; s < s1; s += D) {
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int t = threadIdx.x + 256 * i;
-            sp[buf][t / CD_NCAND][t % CD_NCAND] = j0 + t / CD_NCAND < k0 ? pn[i] : 0.0;
+            for (int i = 0; i < D; ++i) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][m], b[i][n], acc[m][n], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                asm volatile("" ::: "memory");       // the refill stays behind the MFMAs of its slot
+                load(s + i + D, a[i], b[i]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
-    };
-    auto mfma_chunk = [&](int buf, const double *a) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sp[buf][4 * s + g][16 * nb + r16], acc[nb],
-                                                               0, 0, 0);
-    };
-
-    // P of the next chunk is loaded before its L rows (the wait for P before its LDS store
-    // then leaves the L loads in flight), and the prefetch is issued even past the last chunk
-    // (clamped, harmless): a prefetch under a branch would make the first MFMA wait for it
-    double a0[NS], a1[NS], pn[NPT];
-    if (nchunk > 0) {
-        load_p(0, pn);
-        load_a(0, a0);
-        store_p(0, 0, pn);
     }
-    for (int64_t c = 0; c < nchunk; c += 2) {
-        // chunk c from (a0, sp[0]); prefetch chunk c+1 into (a1, sp[1])
-        __syncthreads();
-        load_p(c + 1, pn);
-        __builtin_amdgcn_sched_barrier(0);      // keep the issue order: P, L, MFMAs
-        load_a(c + 1, a1);
-        asm volatile("" ::: "memory");       // no load sinks to its use
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_chunk(0, a0);
-        store_p(1, c + 1, pn);
-        if (c + 1 >= nchunk) break;
-        // chunk c+1 from (a1, sp[1]); prefetch chunk c+2 into (a0, sp[0])
-        __syncthreads();
-        load_p(c + 2, pn);
-        __builtin_amdgcn_sched_barrier(0);
-        load_a(c + 2, a0);
-        asm volatile("" ::: "memory");       // no load sinks to its use
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_chunk(1, a1);
-        store_p(0, c + 2, pn);
-    }
+    // fixed-order sum of the four partial blocks, (w0 + w2) + (w1 + w3); the lane holds rows
+    // 16m + g + 4e of candidate 16n + r16; LDS entry (c, row) sits at c * 64 + (row ^ c)
+    auto put = [&](int slot) {
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        const int c = 16 * nb + r16;
-        if (c >= nc) continue;
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t I = tile0 + 16 * w + g + 4 * e;     // f64 MFMA output rows g + 4e
-            if (I >= npairs) continue;
-            R[(int64_t)c * ldr + I] -= acc[nb][e];            // base V[I][cand_c] from cd_candcol
-        }
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 16 * n + r16, row = 16 * m + g + 4 * e;
+                    red[slot][c][row ^ c] = acc[m][n][e];
+                }
+    };
+    auto add = [&](int slot) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 16 * n + r16, row = 16 * m + g + 4 * e;
+                    acc[m][n][e] += red[slot][c][row ^ c];
+                }
+    };
+    if (w >= 2) put(w - 2);
+    __syncthreads();
+    if (w < 2) add(w);
+    __syncthreads();
+    if (w < 2) put(w);
+    __syncthreads();
+    // R[c][I] -= block[I][c], all 256 threads, consecutive threads on consecutive rows
+#pragma unroll
+    for (int q = 0; q < CD_TILE * CD_NCAND / 256; ++q) {
+        const int idx = threadIdx.x + 256 * q, c = idx / CD_TILE, row = idx % CD_TILE;
+        const int64_t I = tile0 + row;
+        if (c < nc && I < npairs)
+            R[(int64_t)c * ldr + I] -= red[0][c][row ^ c] + red[1][c][row ^ c];   // base V[I][cand_c]
     }
 }
 
@@ -1338,7 +1340,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
 
     // workspace: D copy, ERI diagonal, candidate rows P (max_vec x NCAND), residual columns R
     void *w_part, *w_tile, *w_mask, *w_state;
-    const size_t nP = (size_t)max_vec * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
+    const size_t nP = (size_t)(max_vec + CD_PASS_ZROWS) * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
     const bool spec_on = bsteps > 0 && ctx->cd_speculate;
     const size_t nDb = spec_on ? (size_t)CD_SPEC_MAX * npairs : 0;
     CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR + nDb) * 8 + 256, &w_part));
@@ -1450,7 +1452,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                    st, cand);
                 CDS_LAUNCHED(ctx);
                 if (k > 0) {
-                    hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div(k * CD_NCAND, 256)), dim3(256),
+                    hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div((k + CD_PASS_ZROWS) * CD_NCAND, 256)), dim3(256),
                                        0, ctx->stream, (const double *)L, ldl, k, (const CdState *)st,
                                        (const int64_t *)cand, Pc);
                     CDS_LAUNCHED(ctx);
