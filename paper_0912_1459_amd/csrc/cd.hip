@@ -894,14 +894,16 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, int
     const bool ok = I < cp.npairs;
     unsigned char m = ok ? b.mask[r][I] : 1;
     double d = ok ? b.D[r][I] : 0.0;
-    double rv[CD_SPEC_MAX];
+    // right-looking within the row: cv[j] holds R[I][p_j] minus the terms of the vectors made
+    // so far; once L_j[I] is known every later cv[j'] takes its term at once.  Each cv[j]
+    // still receives its terms in the order i = 0, 1, ..., j-1 (the order of cd_spec_kernel),
+    // but only one fused multiply-add per step stays on the serial path.
+    double cv[CD_SPEC_MAX];
 #pragma unroll
-    for (int j = 0; j < CD_SPEC_MAX; ++j) rv[j] = (ok && j < ns) ? R[(int64_t)ss.slot[j] * ldr + I] : 0.0;
-    double lv[CD_SPEC_MAX];
+    for (int j = 0; j < CD_SPEC_MAX; ++j) cv[j] = (ok && j < ns) ? R[(int64_t)ss.slot[j] * ldr + I] : 0.0;
     unsigned viol = 0u;
 #pragma unroll
     for (int j = 0; j < CD_SPEC_MAX; ++j) {
-        lv[j] = 0.0;
         if (j >= ns || !ok) continue;
         if (m == 0 && (d > ss.cmax[j] || (d >= ss.thr[j] && I < ss.p[j]))) viol |= 1u << j;
         if (m != 1 && d < -cp.psd_tol) viol |= 1u << j;     // NOT_PSD is the per-step path's call
@@ -913,15 +915,17 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, int
             d = 0.0;
             m = 1;
         } else {
-            double c = rv[j];
-#pragma unroll
-            for (int i = 0; i < j; ++i) c = fma(-lv[i], ss.lpiv[i][j], c);
-            lj = c / ss.sq[j];
+            lj = cv[j] / ss.sq[j];
             d = fma(-lj, lj, d);
         }
-        lv[j] = lj;
         L[(k0 + j) * ldl + I] = lj;
         Dbuf[(int64_t)j * cp.npairs + I] = d;
+        if (m != 1) {
+            // a pivot row (also the one made now) takes no further values; lpiv[j][j'] =
+            // L_j[p_j'], 0 for j' >= ns
+#pragma unroll
+            for (int jj = j + 1; jj < CD_SPEC_MAX; ++jj) cv[jj] = fma(-lj, ss.lpiv[j][jj], cv[jj]);
+        }
     }
     // wave OR, one atomic per wave
     for (int o = 32; o > 0; o >>= 1) viol |= (unsigned)__shfl_xor((int)viol, o, 64);
