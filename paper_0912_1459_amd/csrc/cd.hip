@@ -74,13 +74,15 @@ struct CdState {
     int32_t done;    // 1 once a termination rule fired
     int32_t status;  // CDS_CD_* once done
     int32_t ncand;   // candidates of the current look-ahead block
-    int32_t pad;
+    int32_t stall;   // 1: the last speculative block kept no step (the host runs one per-step launch)
     int64_t nmiss;   // steps whose pivot was not a candidate
     double bytes;    // bytes the step kernels must move (algorithmic, per the formula at the update)
     int64_t nspec;   // steps committed by speculative blocks
     int64_t kdone;   // step whose launch found a termination rule (INT64_MAX before): later
                      // launches return at once; blocks of that same launch all still see it
                      // as not earlier than their step, so no block splits on it
+    int64_t npass;   // speculative blocks that ran a pass
+    double sumk0;    // sum of their start steps (for the pass work counts)
 };
 
 // Per 64-row tile, over its non-pivot rows: the largest and smallest residual diagonal,
@@ -104,6 +106,9 @@ struct CdBufs {
 struct CdParams {
     int64_t npairs, max_vec;
     double delta, tau, psd_tol;
+    int64_t nvec_in;   // vectors given on entry (buffer parities count steps from there)
+    int32_t spec_len;  // longest speculative block
+    int32_t pad;
 };
 
 // order-preserving map of doubles to unsigned keys; 0 means "no entry" (-inf),
@@ -774,13 +779,33 @@ struct SpecOut {
     int32_t slot[CD_SPEC_MAX];
     double sq[CD_SPEC_MAX], cmax[CD_SPEC_MAX], thr[CD_SPEC_MAX];
     double lpiv[CD_SPEC_MAX][CD_SPEC_MAX];   // lpiv[i][j] = L[k0+i][p_j], i < j
+    int64_t k0;              // start step of the block
 };
 
-__global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, int r, int nmax,
-                                                     const double *__restrict__ R, int64_t ldr,
-                                                     const int64_t *__restrict__ cand, const CdState *st,
-                                                     SpecOut *so)
+// Speculative blocks are chained on the device: each kernel of a block takes the block's
+// start step from the state (the candidate, gather, pass and speculative kernels from
+// st->k, which only the commit changes; the rows and commit kernels from so->k0) and the
+// buffer parities from the steps made since entry, so the host can queue several blocks
+// without reading anything back.  A block that can keep no step raises st->stall; the
+// kernels of later blocks then return at once until the host has run one per-step launch.
+__device__ __forceinline__ bool spec_idle(const CdState *st) { return st->done || st->stall; }
+
+// steps of the block that stand: those before the first failed check
+__device__ __forceinline__ int spec_keep(const SpecOut *so)
 {
+    const uint32_t v = so->viol;
+    const int first = v ? __ffs((int)v) - 1 : 32;
+    return min(so->nspec, first);
+}
+
+__global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, const double *__restrict__ R,
+                                                     int64_t ldr, const int64_t *__restrict__ cand,
+                                                     const CdState *st, SpecOut *so)
+{
+    if (spec_idle(st)) return;
+    const int64_t k0 = st->k;
+    const int r = (int)((k0 - cp.nvec_in) & 1);
+    const int nmax = (int)min((int64_t)cp.spec_len, cp.max_vec - k0);
     // lane c = candidate c; its column of the speculated vectors stays in registers (lc), the
     // pivot's entries come by lane shuffles, the candidates' residual columns from LDS
     __shared__ double Rcc[CD_NCAND][CD_NCAND + 1];   // Rcc[s][c] = R[s][cand_c]
@@ -790,7 +815,7 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, int 
     __shared__ int ssj[CD_SPEC_MAX];
     __shared__ double ssq[CD_SPEC_MAX], scm[CD_SPEC_MAX], sth[CD_SPEC_MAX];
     const int l = threadIdx.x;
-    const int nc = (st->done || st->ncand == 0) ? 0 : st->ncand;
+    const int nc = st->ncand;
     const bool have = l < nc;
     const int64_t I = have ? cand[l] : -1;
     double d = have ? b.D[r][I] : 0.0;
@@ -876,20 +901,24 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, int 
     if (l == 0) {
         so->nspec = nspec;
         so->viol = 0u;
+        so->k0 = k0;
     }
 }
 
 // every row: the speculated vectors L[k0+j] (same operations as cd_spec_kernel), the
 // residual after each (Dbuf[j][I] = D after vector j) and the step checks
-__global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, int r, int64_t k0,
+__global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, const CdState *st,
                                                       const double *__restrict__ R, int64_t ldr, double *__restrict__ L,
                                                       int64_t ldl, double *__restrict__ Dbuf, SpecOut *so)
 {
     __shared__ SpecOut ss;
+    if (spec_idle(st)) return;
     for (int q = threadIdx.x; q < (int)(sizeof(SpecOut) / 8); q += 256)
         ((int64_t *)&ss)[q] = ((const int64_t *)so)[q];
     __syncthreads();
     const int ns = ss.nspec;
+    const int64_t k0 = ss.k0;
+    const int r = (int)((k0 - cp.nvec_in) & 1);
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool ok = I < cp.npairs;
     unsigned char m = ok ? b.mask[r][I] : 1;
@@ -932,9 +961,15 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, int
     if ((threadIdx.x & 63) == 0 && viol) atomicOr(&so->viol, viol);
 }
 
-// empty two super-tile key buffers (before a commit on the hierarchical search path)
-__global__ void reset_super_kernel(CdBufs b, int b1, int b2)
+// empty the two super-tile key buffers that the commit and the step after it fill
+// (hierarchical search path, before the commit)
+__global__ void reset_super_kernel(CdBufs b, CdParams cp, const CdState *st, const SpecOut *so)
 {
+    if (spec_idle(st)) return;
+    const int nc = spec_keep(so);
+    if (nc == 0) return;
+    const int64_t s = so->k0 + nc - cp.nvec_in;
+    const int b1 = (int)(s % 3), b2 = (int)((s + 1) % 3);
     const int t = threadIdx.x;
     if (t < CD_NSUP) {
         b.smax[b1][t] = 0ull;
@@ -946,10 +981,17 @@ __global__ void reset_super_kernel(CdBufs b, int b1, int b2)
 
 // commit the first nc speculated steps: residuals, pivot marks and tile records into the
 // buffers of parity w (the step k0 + nc reads them), pivots and the state
-__global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, int r, int w, int sw, int64_t k0,
-                                                        int nc, const double *__restrict__ Dbuf, const SpecOut *so,
-                                                        CdState *st, int64_t *__restrict__ piv)
+__global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, const double *__restrict__ Dbuf,
+                                                        const SpecOut *so, CdState *st, int64_t *__restrict__ piv)
 {
+    if (spec_idle(st)) return;
+    const int nc = spec_keep(so);
+    if (nc == 0) {                               // nothing stands: one per-step launch next
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->stall = 1;
+        return;
+    }
+    const int64_t k0 = so->k0, s = k0 - cp.nvec_in;
+    const int r = (int)(s & 1), w = (int)((s + nc) & 1), sw = (int)((s + nc) % 3);
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool ok = I < cp.npairs;
     unsigned char m = ok ? b.mask[r][I] : 1;
@@ -1078,6 +1120,14 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     __shared__ int shs[CD_AUX_NT / 64 + 1];
     __shared__ int64_t stile[CD_NCAND];
     if (st->done) return;
+    const bool chained = k < 0;                  // speculative block: position from the state
+    if (chained) {
+        if (st->stall) return;
+        k = st->k;
+        const int64_t s = k - cp.nvec_in;
+        r = (int)(s & 1);
+        sr = (int)(s % 3);
+    }
     const Pick pk = cd_pick<CD_AUX_NT>(b, r, sr, cp, k, psh);
     if (pk.status != PICK_GO) {                  // the step kernel records the termination
         if (threadIdx.x == 0) st->ncand = 0;     // gather and pass have nothing to do
@@ -1115,6 +1165,10 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     if (threadIdx.x == 0) {
         cand[0] = p;
         st->ncand = 1 + nrow;
+        if (chained) {
+            st->npass += 1;
+            st->sumk0 += (double)k;
+        }
     }
 }
 
@@ -1126,7 +1180,7 @@ __global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, in
                                   double *__restrict__ R, int64_t ldr)
 {
     const int c = blockIdx.y;
-    if (st->done || c >= st->ncand) return;
+    if (spec_idle(st) || c >= st->ncand) return;
     const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= npairs) return;
     const int64_t q = cand[c];
@@ -1139,17 +1193,21 @@ __global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, in
     R[(int64_t)c * ldr + I] = v;
 }
 
-// P[j][c] = L[j][cand_c], j < k0, c < ncand (one thread per entry); rows k0 .. k0 +
-// CD_PASS_ZROWS - 1 are zero (the pass reads them for vectors past k0)
+// P[j][c] = L[j][cand_c], j < k0, c < ncand (grid-stride over the entries); rows k0 .. k0 +
+// CD_PASS_ZROWS - 1 are zero (the pass reads them for vectors past k0).  k0 < 0: the start
+// of the current speculative block.
 __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
                                  const int64_t *__restrict__ cand, double *__restrict__ P)
 {
-    if (st->done || st->ncand == 0) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t j = e / CD_NCAND;
-    const int c = (int)(e % CD_NCAND);
-    if (j >= k0 + CD_PASS_ZROWS) return;
-    P[e] = (j < k0 && c < st->ncand) ? L[j * ldl + cand[c]] : 0.0;
+    if (spec_idle(st) || st->ncand == 0) return;
+    if (k0 < 0) k0 = st->k;
+    const int nc = st->ncand;
+    const int64_t ne = (k0 + CD_PASS_ZROWS) * CD_NCAND;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / CD_NCAND;
+        const int c = (int)(e % CD_NCAND);
+        P[e] = (j < k0 && c < nc) ? L[j * ldl + cand[c]] : 0.0;
+    }
 }
 
 // R[c][I] -= sum_{j<k0} L[j][I] P[j][c] for all candidates (R holds V[I][cand_c]), one
@@ -1172,7 +1230,8 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
 {
     constexpr int D = CD_PASS_D;
     __shared__ double red[2][CD_NCAND][CD_TILE];           // red[slot][cand][row ^ cand]
-    if (st->done || st->ncand == 0) return;
+    if (spec_idle(st) || st->ncand == 0) return;
+    if (k0 < 0) k0 = st->k;                                // speculative block: from the state
     const int nc = st->ncand;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
@@ -1395,6 +1454,9 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     cp.delta = delta;
     cp.tau = tau < 0 ? 1e-10 * vmax : tau;
     cp.psd_tol = psd_tol < 0 ? 1e3 * DBL_EPSILON * vmax : psd_tol;
+    cp.nvec_in = nvec_in;
+    cp.spec_len = std::min(bsteps, CD_SPEC_MAX);
+    cp.pad = 0;
 
     CdsTimer tall;
     CDS_CALL(cds_timer_start(ctx, &tall));
@@ -1428,7 +1490,76 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     const dim3 grid((unsigned)ntile);
     CdsTimer tk;
     bool run_timed = false;
-    for (;;) {
+    // speculative blocks, chained on the device: NB blocks are queued per read of the state;
+    // a stall (a block that kept no step: a termination or a failed first check) gets one
+    // per-step launch at the same start, whose candidates and residual columns still hold
+    constexpr int NB = 4;
+    const unsigned ggrid = (unsigned)std::min<int64_t>(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), 256);
+    while (spec_on) {
+        CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        hs = *(CdState *)hp;
+        if (hs.done) break;
+        k = hs.k;
+        if (k > max_vec)
+            return cds_fail(ctx, CDS_EDEVICE, "CD did not terminate at max_vec=%lld", (long long)max_vec);
+        if (hs.stall) {
+            CDS_HIP(ctx, hipMemsetAsync(&st->stall, 0, sizeof(int32_t), ctx->stream));
+            const int64_t s = k - nvec_in;
+            const int r2 = (int)(s & 1), sr2 = (int)(s % 3), sw2 = (int)((s + 1) % 3), sz2 = (int)((s + 2) % 3);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tk));
+            if (dense)
+                launch_step_any<true>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k, bsteps, pt, V, ldv, L, ldl, Rc,
+                                      ldr, cand, st, piv);
+            else
+                launch_step_any<false>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k, bsteps, pt, V, ldv, L, ldl, Rc,
+                                       ldr, cand, st, piv);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
+            ctx->stats.n_cd_step_launch += 1;
+            continue;
+        }
+        for (int bi = 0; bi < NB; ++bi) {
+            hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
+                               st, cand);
+            CDS_LAUNCHED(ctx);
+            hipLaunchKernelGGL(cd_gather_kernel, dim3(ggrid), dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                               (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
+            CDS_LAUNCHED(ctx);
+            const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCAND);
+            if (dense)
+                hipLaunchKernelGGL(cd_candcol_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
+                                   (const CdState *)st, (const int64_t *)cand, Rc, ldr);
+            else
+                hipLaunchKernelGGL(cd_candcol_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
+                                   (const CdState *)st, (const int64_t *)cand, Rc, ldr);
+            CDS_LAUNCHED(ctx);
+            CdsTimer tp;
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
+            hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
+                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
+            CdsTimer tsp;
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
+            hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const double *)Rc, ldr,
+                               (const int64_t *)cand, (const CdState *)st, so);
+            CDS_LAUNCHED(ctx);
+            hipLaunchKernelGGL(cd_rows_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
+                               ctx->stream, bf, cp, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf, so);
+            CDS_LAUNCHED(ctx);
+            if (!bf.flat) {
+                hipLaunchKernelGGL(reset_super_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const CdState *)st,
+                                   (const SpecOut *)so);
+                CDS_LAUNCHED(ctx);
+            }
+            hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
+                               ctx->stream, bf, cp, (const double *)Dbuf, (const SpecOut *)so, st, piv);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
+        }
+    }
+    for (; !spec_on;) {
         CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
         CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
         hs = *(CdState *)hp;
@@ -1451,7 +1582,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                     run_timed = false;
                 }
                 k0 = k;
-                if (!spec_on) next_start = k + bsteps;
+                next_start = k + bsteps;
                 hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
                                    st, cand);
                 CDS_LAUNCHED(ctx);
@@ -1476,58 +1607,6 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
                 ctx->stats.n_cd_pass_launch += 1;
-                if (spec_on) {
-                    // speculative block: the candidates' own decomposition, all rows, the check
-                    const int nmax = (int)std::min<int64_t>(std::min(bsteps, CD_SPEC_MAX), max_vec - k);
-                    CdsTimer tsp;
-                    if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
-                    hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, r, nmax,
-                                       (const double *)Rc, ldr, (const int64_t *)cand, (const CdState *)st, so);
-                    CDS_LAUNCHED(ctx);
-                    hipLaunchKernelGGL(cd_rows_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
-                                       ctx->stream, bf, cp, r, k, (const double *)Rc, ldr, L, ldl, Dbuf, so);
-                    CDS_LAUNCHED(ctx);
-                    if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
-                    unsigned char *hq = (unsigned char *)hp + 128;
-                    CDS_HIP(ctx, hipMemcpyAsync(hq, so, 8, hipMemcpyDeviceToHost, ctx->stream));
-                    CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
-                    CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-                    const int nspec = ((const int32_t *)hq)[0];
-                    const uint32_t viol = ((const uint32_t *)hq)[1];
-                    if (((const CdState *)hp)->done) break;   // the state is re-read and ends the loop
-                    ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)k + 8.0 * CD_NCAND * (double)npairs;
-                    ctx->stats.flops_cd_pass += 2.0 * (double)npairs * (double)k * CD_NCAND;
-                    ctx->stats.n_cd_pass += 1;
-                    int nc = 0;
-                    while (nc < nspec && !(viol & (1u << nc))) ++nc;
-                    ctx->stats.n_cd_spec_block += 1;
-                    // the next look-ahead block starts where this one stopped (after one per-step
-                    // kernel if nothing could be committed: a termination or a failed first step);
-                    // a new block at a failure measured faster than per-step kernels to the end
-                    // of a fixed block
-                    next_start = k + std::max(nc, 1);
-                    if (nc > 0) {
-                        const int w = (int)((s + nc) & 1);
-                        const int sw3 = (int)((s + nc) % 3);    // keys the step after the block reads
-                        CdsTimer tcm;
-                        if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tcm));
-                        if (!bf.flat) {
-                            hipLaunchKernelGGL(reset_super_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, sw3,
-                                               (int)((s + nc + 1) % 3));
-                            CDS_LAUNCHED(ctx);
-                        }
-                        hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
-                                           ctx->stream, bf, cp, r, w, sw3, k, nc, (const double *)Dbuf,
-                                           (const SpecOut *)so, st, piv);
-                        CDS_LAUNCHED(ctx);
-                        if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tcm, &ctx->stats.t_cd_spec_ms));
-                        ctx->stats.n_cd_spec += nc;
-                        k += nc;
-                        bi += nc;
-                        --k;                  // the loop increment lands on the next block start
-                        continue;
-                    }
-                }
             }
             const int r2 = (int)(s & 1), sr2 = (int)(s % 3), sw2 = (int)((s + 1) % 3), sz2 = (int)((s + 2) % 3);
             // one event pair around each run of consecutive step launches (a pair around
@@ -1561,6 +1640,14 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     ctx->stats.n_cd_steps += hs.k - nvec_in;
     // passes that did work: block starts before the final k (8 npairs B per vector read, one
     // row of R written per candidate; 2 flops per vector, pair and candidate slot)
+    if (spec_on) {
+        ctx->stats.n_cd_pass_launch += hs.npass;
+        ctx->stats.n_cd_pass += hs.npass;
+        ctx->stats.n_cd_spec_block += hs.npass;
+        ctx->stats.n_cd_spec += hs.nspec;
+        ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * hs.sumk0 + 8.0 * CD_NCAND * (double)npairs * (double)hs.npass;
+        ctx->stats.flops_cd_pass += 2.0 * (double)npairs * hs.sumk0 * CD_NCAND;
+    }
     if (bsteps > 0 && !spec_on)
         for (int64_t j = nvec_in; j < hs.k; j += bsteps) {
             ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * (double)j + 8.0 * CD_NCAND * (double)npairs;
