@@ -845,16 +845,26 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
         if (j >= nmax) alive = false;
         if (!alive) continue;
         const bool elig = have && m == 0;
+        const double sql = sqrt(d);                                 // off the serial path
         const double cmax = wave_max_dpp(elig ? d : -INFINITY);
         if (cmax == -INFINITY || cmax <= cp.delta) alive = false;   // termination: per-step path
         if (!alive) continue;
         const double thr = cmax - tie_window(cmax, cp.tau);
-        const int64_t pm = wave_min_i64_dpp((elig && d >= thr) ? I : INT64_MAX);
-        if (pm == INT64_MAX) alive = false;                         // non-finite residuals
+        // pivot: the lowest row index within the tie window; usually one lane is in it
+        const unsigned long long win = __ballot(elig && d >= thr);
+        int64_t pm;
+        if (__popcll(win) == 1) {
+            const int wl = __ffsll((long long)win) - 1;
+            pm = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(I >> 32), wl) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)(I & 0xffffffff), wl));
+        } else {
+            pm = wave_min_i64_dpp((elig && d >= thr) ? I : INT64_MAX);
+        }
+        if (win == 0 || pm == INT64_MAX) alive = false;             // non-finite residuals
         if (alive) {
             const unsigned long long bs = __ballot(have && I == pm);
             const int slot = __ffsll((long long)bs) - 1;
-            const double sq = sqrt(__shfl(d, slot, 64));
+            const double sq = readlane_f64(sql, slot);
             double c = Rcc[slot][l];
             const double *lp = &Lt[slot][0];                                        // L[k0+i][p_j]
 #pragma unroll
