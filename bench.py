@@ -219,7 +219,10 @@ def main():
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
                           "higher_is_better": True, "roofline": roofline,
                           "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M,
-                                 "kernels": cd_kernels}}))
+                                 "kernels": cd_kernels},
+                          "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
+                                        ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms",
+                                         "t_newton_ms")}}))
         return
 
     progress("precision report")

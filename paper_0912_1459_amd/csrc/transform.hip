@@ -19,7 +19,9 @@ int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, cons
 
 namespace {
 
-constexpr int KBATCH_MAX = 64;
+constexpr int KBATCH_MIN = 64;          // vectors per transform batch: at least this many,
+constexpr int KBATCH_WG = 2048;         // enough that the smallest GEMM launches this many tiles,
+constexpr size_t KBATCH_BYTES = 1ull << 30;   // and the unpacked batch stays below this size
 
 __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 {
@@ -168,7 +170,12 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     // working precision of the GEMMs; the output is rounded to `prec` in the last pass
     const int wp = ctx->transform_fp64 ? CDS_PREC_FP64 : prec;
     const size_t es = wsize(wp);
-    const int kbatch = (int)std::min<int64_t>(KBATCH_MAX, nvec);
+    // batch: the virtual-occupied GEMM has one 128 x 128 tile group per vector and would
+    // leave most of the chip idle with small batches
+    const int64_t tiles_vo = cds_ceil_div(nvirt, 128) * cds_ceil_div(nocc, 128);
+    int64_t kb_want = std::max<int64_t>(KBATCH_MIN, cds_ceil_div(KBATCH_WG, tiles_vo));
+    kb_want = std::min<int64_t>(kb_want, std::max<int64_t>(1, (int64_t)(KBATCH_BYTES / ((size_t)nbf * np_ * es))));
+    const int kbatch = (int)std::min<int64_t>(kb_want, nvec);
 
     // workspace: Ct + CX (+ sel list), Lu batch, T batch (+ split copy), Bk batch
     void *wcx, *wlu, *wt, *wb;
