@@ -83,6 +83,8 @@ struct CdState {
                      // as not earlier than their step, so no block splits on it
     int64_t npass;   // speculative blocks that ran a pass
     double sumk0;    // sum of their start steps (for the pass work counts)
+    int32_t nmap;    // entries of the row -> candidate slot map that are set (cand[0 .. nmap))
+    int32_t pad2;
 };
 
 // Per 64-row tile, over its non-pivot rows: the largest and smallest residual diagonal,
@@ -101,6 +103,8 @@ struct CdBufs {
     unsigned long long *smin[3];        // super-tile min keys (atomicMin)
     int64_t ntile, tps;                 // tiles; tiles per super-tile
     int flat;                           // 1: pivot search over all tile records (no keys)
+    signed char *slot;                  // row -> candidate slot of the current block, -1 otherwise
+    double *rc;                         // rc[s][c] = R[s][cand_c], the candidates' own block
 };
 
 struct CdParams {
@@ -820,14 +824,14 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
     const int64_t I = have ? cand[l] : -1;
     double d = have ? b.D[r][I] : 0.0;
     unsigned char m = have ? b.mask[r][I] : 1;
-    // the candidates' 64 x 64 residual block, 16 loads in flight per lane
+    // the candidates' 64 x 64 residual block (compact, written by the pass), 32 loads in flight
 #pragma unroll
-    for (int s0 = 0; s0 < CD_NCAND; s0 += 16) {
-        double v[16];
+    for (int s0 = 0; s0 < CD_NCAND; s0 += 32) {
+        double v[32];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = (have && s0 + u < nc) ? R[(int64_t)(s0 + u) * ldr + I] : 0.0;
+        for (int u = 0; u < 32; ++u) v[u] = b.rc[(s0 + u) * CD_NCAND + l];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) Rcc[s0 + u][l] = v[u];
+        for (int u = 0; u < 32; ++u) Rcc[s0 + u][l] = (have && s0 + u < nc) ? v[u] : 0.0;
     }
     if (l < CD_SPEC_MAX) {
         spj[l] = -1;
@@ -1138,9 +1142,16 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
         r = (int)(s & 1);
         sr = (int)(s % 3);
     }
+    // the previous block's rows leave the slot map
+    const int nmap = st->nmap;
+    if ((int)threadIdx.x < nmap) b.slot[cand[threadIdx.x]] = -1;
+    __syncthreads();
     const Pick pk = cd_pick<CD_AUX_NT>(b, r, sr, cp, k, psh);
     if (pk.status != PICK_GO) {                  // the step kernel records the termination
-        if (threadIdx.x == 0) st->ncand = 0;     // gather and pass have nothing to do
+        if (threadIdx.x == 0) {
+            st->ncand = 0;                       // gather and pass have nothing to do
+            st->nmap = 0;
+        }
         return;
     }
     const int64_t p = pk.p;
@@ -1172,9 +1183,12 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     const int nrow = select_top<CD_AUX_NT, RK>(v, CD_NCAND - 1, hist, &s_prefix, &s_need, shs, [&](int pos, int id) {
         cand[1 + pos] = stile[id / CD_TILE] * CD_TILE + id % CD_TILE;
     });
+    if (threadIdx.x == 0) cand[0] = p;
+    __syncthreads();
+    if ((int)threadIdx.x < 1 + nrow) b.slot[cand[threadIdx.x]] = (signed char)threadIdx.x;
     if (threadIdx.x == 0) {
-        cand[0] = p;
         st->ncand = 1 + nrow;
+        st->nmap = 1 + nrow;
         if (chained) {
             st->npass += 1;
             st->sumk0 += (double)k;
@@ -1236,7 +1250,8 @@ __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int6
 __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_t ldl, int64_t npairs,
                                                          int64_t k0, const CdState *__restrict__ st,
                                                          const double *P, double *__restrict__ R,
-                                                         int64_t ldr)
+                                                         int64_t ldr, const signed char *__restrict__ slotmap,
+                                                         double *__restrict__ rc)
 {
     constexpr int D = CD_PASS_D;
     __shared__ double red[2][CD_NCAND][CD_TILE];           // red[slot][cand][row ^ cand]
@@ -1319,13 +1334,19 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
     __syncthreads();
     if (w < 2) put(w);
     __syncthreads();
-    // R[c][I] -= block[I][c], all 256 threads, consecutive threads on consecutive rows
+    // R[c][I] -= block[I][c], all 256 threads, consecutive threads on consecutive rows (each
+    // thread keeps one row); a candidate row also goes to the compact block rc
+    const int row = threadIdx.x % CD_TILE;
+    const int64_t I = tile0 + row;
+    const int sl = I < npairs ? slotmap[I] : -1;
 #pragma unroll
     for (int q = 0; q < CD_TILE * CD_NCAND / 256; ++q) {
-        const int idx = threadIdx.x + 256 * q, c = idx / CD_TILE, row = idx % CD_TILE;
-        const int64_t I = tile0 + row;
-        if (c < nc && I < npairs)
-            R[(int64_t)c * ldr + I] -= red[0][c][row ^ c] + red[1][c][row ^ c];   // base V[I][cand_c]
+        const int c = (threadIdx.x + 256 * q) / CD_TILE;
+        if (c < nc && I < npairs) {
+            const double v = R[(int64_t)c * ldr + I] - (red[0][c][row ^ c] + red[1][c][row ^ c]);  // base V[I][cand_c]
+            R[(int64_t)c * ldr + I] = v;
+            if (sl >= 0) rc[c * CD_NCAND + sl] = v;
+        }
     }
 }
 
@@ -1418,8 +1439,9 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     const size_t nDb = spec_on ? (size_t)CD_SPEC_MAX * npairs : 0;
     CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR + nDb) * 8 + 256, &w_part));
     CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
-    CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)2 * npairs, &w_mask));
-    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + sizeof(SpecOut) + 64, &w_state));
+    CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)3 * npairs, &w_mask));
+    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + sizeof(SpecOut) + 64 +
+                                      (size_t)CD_NCAND * CD_NCAND * 8 + 256, &w_state));
     double *D1 = (double *)w_part;
     double *diag = D1 + npairs;
     double *Pc = diag + npairs;
@@ -1443,6 +1465,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     CdState *st = (CdState *)w_state;
     int64_t *cand = (int64_t *)(st + 1);
     SpecOut *so = (SpecOut *)(cand + CD_NCAND);
+    bf.slot = (signed char *)(bf.mask[1] + npairs);
+    bf.rc = (double *)(((uintptr_t)(so + 1) + 255) & ~(uintptr_t)255);
     double *Dbuf = Rc + nR;
 
     // largest ERI diagonal (for the default tie window / PSD tolerance)
@@ -1476,6 +1500,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     } else {
         CDS_HIP(ctx, hipMemsetAsync(bf.mask[0], 0, (size_t)npairs, ctx->stream));
     }
+    CDS_HIP(ctx, hipMemsetAsync(bf.slot, 0xff, (size_t)npairs, ctx->stream));   // no row is a candidate
     // super-tile buffers 0 and 1 start empty (2 is reset by the first step)
     CDS_HIP(ctx, hipMemsetAsync(bf.smax[0], 0, (size_t)3 * CD_NSUP * 8, ctx->stream));
     CDS_HIP(ctx, hipMemsetAsync(bf.smin[0], 0xff, (size_t)3 * CD_NSUP * 8, ctx->stream));
@@ -1547,7 +1572,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             CdsTimer tp;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
             hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
-                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr);
+                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc);
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
             CdsTimer tsp;
@@ -1613,7 +1639,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 CdsTimer tp;
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
                 hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs, k,
-                                   (const CdState *)st, (const double *)Pc, Rc, ldr);
+                                   (const CdState *)st, (const double *)Pc, Rc, ldr, (const signed char *)bf.slot,
+                                   bf.rc);
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
                 ctx->stats.n_cd_pass_launch += 1;
