@@ -254,6 +254,144 @@ __global__ __launch_bounds__(NT, PREC == CDS_PREC_FP64 ? 1 : 2) void gemm_kernel
         }
 }
 
+// ---- large split-bf16 GEMM -------------------------------------------------------
+// 256 x 256 tile per workgroup of 512 threads (8 waves in 2 x 4, 128 x 64 per wave = 8 x 4
+// blocks of 16 x 16, three v_mfma_f32_16x16x32_bf16 per block and 32-k stage), for the
+// products big enough to fill the chip with such tiles.  Operand tiles (two bf16 planes
+// each) go straight from global memory to LDS (global_load_lds_dwordx4: lane t of a load
+// writes LDS bytes 16t..16t+15 after the wave's base), double-buffered by stage; the
+// 16-byte k-chunks of a row are stored XOR-swizzled by (row >> 1) & 3 (the swizzle is
+// applied to the global address), so the fragment reads of 8 consecutive rows hit distinct
+// banks.  The stage waits are explicit (vmcnt, then s_barrier without a memory fence, which
+// would also wait for the next stage's loads).  Tiles of one XCD are contiguous in a grouped
+// order (4 tile rows x all tile columns), so tiles that share operand rows run on the same
+// L2.
+constexpr int GB_M = 256, GB_N = 256, GB_K = 32, GB_NT = 512, GB_GM = 4;
+constexpr int GB_PLANE = GB_M * GB_K * 2;       // bytes of one operand plane per stage (16 KB)
+constexpr int GB_STAGE = 4 * GB_PLANE;          // A hi, A lo, B hi, B lo (64 KB)
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt with vmcnt = n (expcnt, lgkmcnt left alone)
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// one stage (32 k) of both operands into LDS stage buffer `buf`: 64 wave loads of 1 KB
+// (16 rows x 64 bytes), 8 per wave
+__device__ __forceinline__ void gb_stage(const Args &a, unsigned char *buf, int64_t m0, int64_t n0, int64_t k0,
+                                         int64_t batch, int wave, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int id = wave * 8 + i;           // 0..63: operand plane (4) x row group (16)
+        const int op = id >> 4, rg = id & 15;  // op: 0 A hi, 1 A lo, 2 B hi, 3 B lo
+        const bool isA = op < 2;
+        const int row = rg * 16 + (lane >> 2);
+        const int pos = lane & 3;
+        const int chunk = pos ^ ((row >> 1) & 3);
+        const int64_t nrows = isA ? a.M : a.N;
+        const int64_t grow = min((isA ? m0 : n0) + row, nrows - 1);
+        const unsigned char *base = isA ? (op == 0 ? a.A : a.Alo) : (op == 2 ? a.B : a.Blo);
+        const int64_t srow = isA ? a.sAm : a.sBn, sb = isA ? a.sAb : a.sBb;
+        const __bf16 *src = reinterpret_cast<const __bf16 *>(base) + batch * sb + grow * srow + k0 + chunk * 8;
+        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(buf + op * GB_PLANE + rg * 1024), 16, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(GB_NT, 1) void gemm_bf16x3_big_kernel(Args a, int64_t tiles_m, int64_t tiles_n)
+{
+    __shared__ __align__(16) unsigned char lds0[GB_STAGE];
+    __shared__ __align__(16) unsigned char lds1[GB_STAGE];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+    const int64_t batch = blockIdx.y;
+    // tile of this workgroup: contiguous ranges per XCD (workgroups go round-robin over the 8)
+    const int64_t T = tiles_m * tiles_n, bid = blockIdx.x;
+    const int64_t q8 = T / 8, r8 = T % 8, xcd = bid % 8, j = bid / 8;
+    const int64_t t = xcd * q8 + min(xcd, r8) + j;
+    const int64_t gsz = GB_GM * tiles_n, grp = t / gsz, rem = t % gsz;
+    const int64_t gm = min((int64_t)GB_GM, tiles_m - grp * GB_GM);
+    const int64_t tm = grp * GB_GM + rem % gm, tn = rem / gm;
+    const int64_t m0 = tm * GB_M, n0 = tn * GB_N;
+    const int64_t ns = a.K / GB_K;
+
+    floatx4 acc[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    auto compute = [&](const unsigned char *buf) {
+        bf16x8 bh[4], bl[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int row = wn + 16 * jj + r16;
+            const int off = row * 64 + ((g ^ ((row >> 1) & 3)) * 16);
+            bh[jj] = *reinterpret_cast<const bf16x8 *>(buf + 2 * GB_PLANE + off);
+            bl[jj] = *reinterpret_cast<const bf16x8 *>(buf + 3 * GB_PLANE + off);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 ah[4], al[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = wm + 16 * (4 * h + i) + r16;
+                const int off = row * 64 + ((g ^ ((row >> 1) & 3)) * 16);
+                ah[i] = *reinterpret_cast<const bf16x8 *>(buf + off);
+                al[i] = *reinterpret_cast<const bf16x8 *>(buf + GB_PLANE + off);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    floatx4 &c = acc[4 * h + i][jj];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[jj], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[jj], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[jj], c, 0, 0, 0);
+                }
+        }
+    };
+
+    gb_stage(a, lds0, m0, n0, 0, batch, wave, lane);
+    for (int64_t s = 0; s < ns; ++s) {
+        unsigned char *cur = (s & 1) ? lds1 : lds0;
+        unsigned char *nxt = (s & 1) ? lds0 : lds1;
+        if (s + 1 < ns) {
+            gb_stage(a, nxt, m0, n0, (s + 1) * GB_K, batch, wave, lane);   // nxt was freed by the last barrier
+            wait_vm<8>();                      // this wave's loads of stage s have landed
+        } else {
+            wait_vm<0>();
+        }
+        __builtin_amdgcn_s_barrier();          // ... and every wave's
+        compute(cur);
+        __builtin_amdgcn_s_waitcnt(0xC07F);    // lgkmcnt(0): this wave's reads of cur are done
+        __builtin_amdgcn_s_barrier();          // cur may be refilled
+    }
+
+    float *C = reinterpret_cast<float *>(a.C) + batch * a.sCb;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int64_t n = n0 + wn + 16 * jj + r16;
+            if (n >= a.N) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t m = m0 + wm + 16 * i + 4 * g + e;
+                if (m >= a.M) continue;
+                float *dst = C + m * a.sCm + n * a.sCn;
+                double v = a.alpha * (double)acc[i][jj][e];
+                if (a.beta != 0.0) v += a.beta * (double)(*dst);
+                *dst = (float)v;
+            }
+        }
+}
+
 bool fast_ok(const void *p, int64_t srow, int64_t sk, int64_t K, int kb, size_t esz)
 {
     return sk == 1 && K % kb == 0 && cds_aligned(p, 16) && (srow * (int64_t)esz) % 16 == 0;
@@ -275,6 +413,16 @@ int launch(cds_ctx *ctx, Args &a)
     if (gy > 65535 || a.batch > 65535)
         return cds_fail(ctx, CDS_EINVAL, "GEMM grid too large (%lld x %lld x %lld)", (long long)gx,
                         (long long)gy, (long long)a.batch);
+    if (PREC == CDS_PREC_BF16X3 && a.M >= 512 && a.N >= 512 && a.K % GB_K == 0 &&
+        cds_aligned(a.A, 16) && cds_aligned(a.Alo, 16) && cds_aligned(a.B, 16) && cds_aligned(a.Blo, 16)) {
+        const int64_t tm = cds_ceil_div(a.M, GB_M), tn = cds_ceil_div(a.N, GB_N);
+        if (tm * tn <= 0x7fffffff) {
+            hipLaunchKernelGGL(gemm_bf16x3_big_kernel, dim3((unsigned)(tm * tn), (unsigned)a.batch), dim3(GB_NT), 0,
+                               ctx->stream, a, tm, tn);
+            CDS_LAUNCHED(ctx);
+            return CDS_OK;
+        }
+    }
     size_t lds = (size_t)2 * Tr<PREC>::PLANES * BM * PITCH;
     hipLaunchKernelGGL(gemm_kernel<PREC>, dim3((unsigned)gx, (unsigned)gy, (unsigned)a.batch), dim3(NT),
                        lds, ctx->stream, a);
