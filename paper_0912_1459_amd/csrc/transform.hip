@@ -45,22 +45,59 @@ __device__ __forceinline__ void put(void *base, int prec, int64_t idx, int64_t p
     }
 }
 
-// Lu[kb][mu][nu] = L^{k0+kb}_{mu nu} (0 for nu >= nbf)
-__global__ void unpack_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, int nkb,
-                              int nbf, int np_, void *out, int prec, int64_t plane)
+
+// four consecutive elements idx .. idx+3 (16-byte aligned for FP64 / 8-byte for the others)
+__device__ __forceinline__ void put4(void *base, int prec, int64_t idx, int64_t plane, const double (&v)[4])
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t per = (int64_t)nbf * np_;
-    if (t >= per * nkb) return;
-    int kb = (int)(t / per);
-    int64_t rem = t - (int64_t)kb * per;
-    int mu = (int)(rem / np_), nu = (int)(rem - (int64_t)mu * np_);
-    double v = 0.0;
-    if (nu < nbf) {
-        int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
-        v = L[(k0 + kb) * ldl + (int64_t)b * (b + 1) / 2 + a];
+    if (prec == CDS_PREC_FP64) {
+        double4 x = {v[0], v[1], v[2], v[3]};
+        *reinterpret_cast<double2 *>((double *)base + idx) = double2{x.x, x.y};
+        *reinterpret_cast<double2 *>((double *)base + idx + 2) = double2{x.z, x.w};
+    } else if (prec == CDS_PREC_FP32) {
+        *reinterpret_cast<float4 *>((float *)base + idx) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+        __bf16 hi[4], lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) split_bf16((float)v[e], hi[e], lo[e]);
+        *reinterpret_cast<uint2 *>((__bf16 *)base + idx) = *reinterpret_cast<const uint2 *>(hi);
+        *reinterpret_cast<uint2 *>((__bf16 *)base + plane + idx) = *reinterpret_cast<const uint2 *>(lo);
     }
-    put(out, prec, t, plane, v);
+}
+
+// Lu[kb][mu][nu] = L^{k0+kb}_{mu nu} (0 for nu >= nbf), by 32 x 32 blocks: workgroup
+// (kb, block pair bm >= bn) reads the block rows mu in bm, nu in bn of the lower triangle
+// (contiguous in nu), writes it in place and, off the diagonal, transposed through LDS
+__global__ __launch_bounds__(256) void unpack_blocks_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0,
+                                                            int nbf, int np_, void *out, int prec, int64_t plane)
+{
+    __shared__ double tile[32][33];
+    const int kb = blockIdx.y;
+    int bp = blockIdx.x, bm = 0;                  // block pair index -> (bm, bn), bn <= bm
+    while (bp > bm) bp -= ++bm;
+    const int bn = bp;
+    const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
+    const double *Lk = L + (k0 + kb) * ldl;
+    const int64_t base = (int64_t)kb * nbf * np_;
+    const int mu = bm * 32 + r;
+    double v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int nu = bn * 32 + c0 + e;
+        v[e] = 0.0;
+        if (mu < nbf && nu < nbf) {
+            const int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
+            v[e] = Lk[(int64_t)b * (b + 1) / 2 + a];
+        }
+        tile[r][c0 + e] = v[e];
+    }
+    if (mu < nbf) put4(out, prec, base + (int64_t)mu * np_ + bn * 32 + c0, plane, v);
+    if (bm == bn) return;                         // the diagonal block holds both triangles
+    __syncthreads();
+    const int nu_row = bn * 32 + r;               // transposed: row nu of block bn, columns mu of bm
+    if (nu_row >= nbf) return;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = tile[c0 + e][r];
+    put4(out, prec, base + (int64_t)nu_row * np_ + bm * 32 + c0, plane, v);
 }
 
 // Ct[p][mu] = C[mu][p]; CX rows: occupied 0..nocc-1 then sel[s]; k padded to np_
@@ -221,9 +258,9 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     for (int64_t k0 = 0; k0 < nvec; k0 += kbatch) {
         const int nkb = (int)std::min<int64_t>(kbatch, nvec - k0);
         {
-            int64_t n = (int64_t)nkb * nbf * np_;
-            hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
-                               ctx->stream, L, ldl, k0, nkb, nbf, np_, wlu, wp, (int64_t)nkb * nbf * np_);
+            const int nb = np_ / 32;
+            hipLaunchKernelGGL(unpack_blocks_kernel, dim3((unsigned)(nb * (nb + 1) / 2), (unsigned)nkb), dim3(256), 0,
+                               ctx->stream, L, ldl, k0, nbf, np_, wlu, wp, (int64_t)nkb * nbf * np_);
             CDS_LAUNCHED(ctx);
         }
         const int64_t planeLu = (int64_t)nkb * nbf * np_;
