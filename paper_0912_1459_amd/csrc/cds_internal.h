@@ -132,6 +132,8 @@ struct GemmDesc {
     void *C;
     int64_t sCm, sCn, sCb;
     double alpha, beta;      // beta: 0 overwrite, 1 accumulate
+    void *Clo;               // BF16X3 only, beta 0: C and Clo receive the hi and lo bf16 planes
+                             // of the result (same element offsets) instead of floats
 };
 // prec of A/B/C: FP64 -> double, FP32/BF16X3 -> float storage
 int cds_gemm(cds_ctx *ctx, int prec, const GemmDesc &d);

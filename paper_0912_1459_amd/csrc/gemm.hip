@@ -39,7 +39,7 @@ struct Args {
     int64_t sAm, sAk, sAb;
     const unsigned char *B, *Blo;
     int64_t sBk, sBn, sBb;
-    unsigned char *C;
+    unsigned char *C, *Clo;        // Clo: split output (BF16X3, see GemmDesc)
     int64_t sCm, sCn, sCb;
     double alpha, beta;
     int fastA, fastB;              // K-contiguous, 16-byte aligned rows, K % KB == 0
@@ -134,6 +134,14 @@ __device__ __forceinline__ void store_tile(unsigned char *lds, const uint4 (&reg
             *reinterpret_cast<uint4 *>(lds + pl * (BM * PITCH) + r * PITCH + q * 16) = reg[pl][i];
         }
     (void)rows_fast;
+}
+
+// result element idx as a hi/lo pair of bf16 planes (x ~ hi + lo)
+__device__ __forceinline__ void split_store(const Args &a, int64_t idx, float x)
+{
+    const __bf16 hi = (__bf16)x;
+    reinterpret_cast<__bf16 *>(a.C)[idx] = hi;
+    reinterpret_cast<__bf16 *>(a.Clo)[idx] = (__bf16)(x - (float)hi);
 }
 
 template <int PREC>
@@ -233,7 +241,7 @@ __global__ __launch_bounds__(NT, PREC == CDS_PREC_FP64 ? 1 : 2) void gemm_kernel
         }
     }
 
-    // epilogue: C = alpha * acc + beta * C
+    // epilogue: C = alpha * acc + beta * C (or the split planes of alpha * acc)
     O *C = reinterpret_cast<O *>(a.C) + batch * a.sCb;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -246,6 +254,12 @@ __global__ __launch_bounds__(NT, PREC == CDS_PREC_FP64 ? 1 : 2) void gemm_kernel
                 // f32/bf16 MFMA: lane group g holds rows 4g..4g+3; f64: rows g, g+4, g+8, g+12
                 const int64_t m = m0 + wm + 16 * i + (PREC == CDS_PREC_FP64 ? g + 4 * e : 4 * g + e);
                 if (m >= a.M) continue;
+                if constexpr (PREC == CDS_PREC_BF16X3) {
+                    if (a.Clo) {
+                        split_store(a, batch * a.sCb + m * a.sCm + n * a.sCn, (float)(a.alpha * (double)acc[i][j][e]));
+                        continue;
+                    }
+                }
                 O *dst = C + m * a.sCm + n * a.sCn;
                 double v = a.alpha * (double)acc[i][j][e];
                 if (a.beta != 0.0) v += a.beta * (double)(*dst);
@@ -384,6 +398,10 @@ __global__ __launch_bounds__(GB_NT, 1) void gemm_bf16x3_big_kernel(Args a, int64
             for (int e = 0; e < 4; ++e) {
                 const int64_t m = m0 + wm + 16 * i + 4 * g + e;
                 if (m >= a.M) continue;
+                if (a.Clo) {
+                    split_store(a, batch * a.sCb + m * a.sCm + n * a.sCn, (float)(a.alpha * (double)acc[i][jj][e]));
+                    continue;
+                }
                 float *dst = C + m * a.sCm + n * a.sCn;
                 double v = a.alpha * (double)acc[i][jj][e];
                 if (a.beta != 0.0) v += a.beta * (double)(*dst);
@@ -450,6 +468,9 @@ int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, cons
     a.sBn = d.sBn;
     a.sBb = d.sBb;
     a.C = (unsigned char *)d.C;
+    a.Clo = (unsigned char *)d.Clo;
+    if (a.Clo && (prec != CDS_PREC_BF16X3 || d.beta != 0.0))
+        return cds_fail(ctx, CDS_EINVAL, "split GEMM output needs BF16X3 and beta 0");
     a.sCm = d.sCm;
     a.sCn = d.sCn;
     a.sCb = d.sCb;

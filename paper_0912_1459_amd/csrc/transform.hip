@@ -128,16 +128,16 @@ __global__ void coef_kernel(const double *__restrict__ C, int nbf, int nmo, int 
     put(dst, prec, idx, plane, v);
 }
 
-// float T -> bf16 planes (for the second GEMM of the BF16X3 transform)
-__global__ void split_kernel(const float *__restrict__ x, int64_t n, __bf16 *__restrict__ out, int64_t plane)
+// zero the byte columns [c0, c1) of nrows rows of pitch `pitch` bytes (2-byte units)
+__global__ void zero_cols_kernel(unsigned char *base, int64_t nrows, int64_t pitch, int c0, int c1)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    __bf16 hi, lo;
-    split_bf16(x[t], hi, lo);
-    out[t] = hi;
-    out[plane + t] = lo;
+    const int per = (c1 - c0) / 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * per) return;
+    const int64_t r = t / per;
+    *reinterpret_cast<uint16_t *>(base + r * pitch + c0 + 2 * (t - r * per)) = 0;
 }
+
 
 // Bk[kb][row] (working type W) -> out[row*ldk + k0 + kb] in the output format.
 // rows [0, nvo) go to Bvo, rows [nvo, nvo + nselr) to Bsel.
@@ -242,7 +242,16 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     // T: working float output, and (bf16) a split copy after it
     float *Tf = (float *)wt;
     __bf16 *Ts = (__bf16 *)((unsigned char *)wt + (size_t)nT * 4);
-    CDS_HIP(ctx, hipMemsetAsync(wt, 0, (size_t)nT * es * (wp == CDS_PREC_BF16X3 ? 2 : 1), ctx->stream));
+    // the first GEMM writes columns < nbf of T; the K padding [nbf, np_) must read as 0
+    if (np_ > nbf) {
+        const size_t tes0 = (wp == CDS_PREC_FP64) ? 8 : (wp == CDS_PREC_FP32 ? 4 : 2);
+        unsigned char *tb = (wp == CDS_PREC_BF16X3) ? (unsigned char *)Ts : (unsigned char *)wt;
+        const int64_t trows = (int64_t)kbatch * nx * (wp == CDS_PREC_BF16X3 ? 2 : 1);   // both planes
+        const int64_t nz = trows * (int64_t)((np_ - nbf) * tes0 / 2);
+        hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)cds_ceil_div(nz, 256)), dim3(256), 0, ctx->stream, tb,
+                           trows, (int64_t)np_ * (int64_t)tes0, (int)(nbf * tes0), (int)(np_ * tes0));
+        CDS_LAUNCHED(ctx);
+    }
 
     // zero padding of B beyond nvec
     if (ldk > nvec) {
@@ -273,11 +282,10 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
         g1.C = Tout; g1.sCm = np_; g1.sCn = 1; g1.sCb = (int64_t)nx * np_;
         g1.alpha = 1.0; g1.beta = 0.0;
         if (wp == CDS_PREC_BF16X3) {
+            // T straight into its two bf16 planes (the split of the FP32 result)
+            g1.C = Ts;
+            g1.Clo = Ts + (int64_t)nkb * nx * np_;
             CDS_CALL(cds_gemm_ex(ctx, gprec, g1, (const __bf16 *)CX + planeCX, (const __bf16 *)wlu + planeLu));
-            int64_t n = (int64_t)nkb * nx * np_;
-            hipLaunchKernelGGL(split_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
-                               ctx->stream, Tf, n, Ts, n);
-            CDS_LAUNCHED(ctx);
         } else {
             CDS_CALL(cds_gemm_ex(ctx, gprec, g1, nullptr, nullptr));
         }
