@@ -134,10 +134,13 @@ __device__ __forceinline__ double okey_min(unsigned long long u)
     return okey_max(u);
 }
 
+// F0(T) = (1/2) sqrt(pi / T) erf(sqrt T) = (sqrt(pi) / 2) erf(t) / t with t = sqrt T (one
+// square root, one division); the series near T = 0
 __device__ __forceinline__ double boys_f0(double T)
 {
     if (T < 1e-12) return 1.0 - T / 3.0 + T * T / 10.0;
-    return 0.5 * sqrt(M_PI / T) * erf(sqrt(T));
+    const double t = sqrt(T);
+    return 0.88622692545275801365 * erf(t) / t;           // sqrt(pi) / 2
 }
 
 // (rho_I | V | rho_J) for two s-Gaussian product densities
@@ -145,11 +148,12 @@ __device__ __forceinline__ double eri_pp(double p, double Px, double Py, double 
                                          double q, double Qx, double Qy, double Qz, double Kq)
 {
     const double two_pi_52 = 2.0 * 17.493418327624862;   // 2 pi^(5/2)
-    double dx = Px - Qx, dy = Py - Qy, dz = Pz - Qz;
-    double r2 = dx * dx + dy * dy + dz * dz;
-    double s = p + q;
-    double T = p * q / s * r2;
-    return Kp * Kq * two_pi_52 / (p * q * sqrt(s)) * boys_f0(T);
+    const double dx = Px - Qx, dy = Py - Qy, dz = Pz - Qz;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double s = p + q, pq = p * q;
+    const double e = 1.0 / (pq * s);                        // one division for both factors
+    const double T = pq * pq * e * r2;                      // p q / (p + q) * r2
+    return Kp * Kq * two_pi_52 * sqrt(s) * e * boys_f0(T);  // ... / (p q sqrt(p + q))
 }
 
 __global__ void pair_setup_kernel(int32_t nbf, const double *__restrict__ centres,
@@ -295,6 +299,25 @@ __device__ __forceinline__ double wave_max_dpp(double v)
     v = fmax(v, dpp_f64<0x141>(v));    // row_half_mirror
     v = fmax(v, dpp_f64<0x140>(v));    // row_mirror: every lane holds its 16-lane row maximum
     return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+// maximum over the wave (DPP row_shr 1, 2, 4, 8, then row_bcast 15, 31; lane 63 holds it)
+__device__ __forceinline__ unsigned wave_max_u32_dpp(unsigned v)
+{
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+// largest order-preserving key (okey) over the wave: high words, then the low words of the
+// lanes that hold the largest high word
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long k)
+{
+    const unsigned hi = wave_max_u32_dpp((unsigned)(k >> 32));
+    const unsigned lo = wave_max_u32_dpp((unsigned)(k >> 32) == hi ? (unsigned)k : 0u);
+    return ((unsigned long long)hi << 32) | lo;
 }
 __device__ __forceinline__ int64_t i64_min(int64_t a, int64_t b) { return b < a ? b : a; }
 template <int CTRL>
@@ -850,7 +873,7 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
         if (!alive) continue;
         const bool elig = have && m == 0;
         const double sql = sqrt(d);                                 // off the serial path
-        const double cmax = wave_max_dpp(elig ? d : -INFINITY);
+        const double cmax = okey_max(wave_max_key(elig ? okey(d) : 0ull));   // as fmax, on integer keys
         if (cmax == -INFINITY || cmax <= cp.delta) alive = false;   // termination: per-step path
         if (!alive) continue;
         const double thr = cmax - tie_window(cmax, cp.tau);
