@@ -60,7 +60,9 @@ constexpr int CD_PASS_D = 2;            // k-steps (4 vectors each) in flight pe
 constexpr int CD_PASS_ZROWS = 8;        // zero rows of P after row k0
 constexpr int CD_TPT = 4;               // tile records per thread in the flat pivot search
 constexpr int CD_ONE_TILE_MAX = 1280;   // tiles up to which a step block holds one tile
-constexpr int CD_SPEC_MAX = 32;         // steps of one speculative look-ahead block
+constexpr int CD_SPEC_MAX = 48;         // steps of one speculative look-ahead block (multiple of 8, <= 64)
+constexpr int CD_SPEC_CHUNK = 8;        // steps between the rows kernel's looks at the published checks
+constexpr int CD_SPEC_MARGIN = 8;       // speculated steps past the last one that is sure to stand
 constexpr int CD_CAND_MAXTILE = 8192;   // tiles the candidate selection handles (look-ahead
                                         // is off above 8192 * 64 pairs)
 
@@ -85,6 +87,7 @@ struct CdState {
     double sumk0;    // sum of their start steps (for the pass work counts)
     int32_t nmap;    // entries of the row -> candidate slot map that are set (cand[0 .. nmap))
     int32_t pad2;
+    double dnc;      // bound on the residual diagonals of the eligible rows that are not candidates
 };
 
 // Per 64-row tile, over its non-pivot rows: the largest and smallest residual diagonal,
@@ -801,7 +804,8 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
 // (cd_commit_kernel) and starts the next block there.
 struct SpecOut {
     int32_t nspec;           // speculated steps
-    uint32_t viol;           // bit j: step j does not stand (atomicOr by cd_rows_kernel)
+    int32_t pad;
+    uint64_t viol;           // bit j: step j does not stand (atomicOr by cd_rows_kernel)
     int64_t p[CD_SPEC_MAX];  // pivots
     int32_t slot[CD_SPEC_MAX];
     double sq[CD_SPEC_MAX], cmax[CD_SPEC_MAX], thr[CD_SPEC_MAX];
@@ -820,8 +824,8 @@ __device__ __forceinline__ bool spec_idle(const CdState *st) { return st->done |
 // steps of the block that stand: those before the first failed check
 __device__ __forceinline__ int spec_keep(const SpecOut *so)
 {
-    const uint32_t v = so->viol;
-    const int first = v ? __ffs((int)v) - 1 : 32;
+    const uint64_t v = so->viol;
+    const int first = v ? __ffsll((long long)v) - 1 : 64;
     return min(so->nspec, first);
 }
 
@@ -867,6 +871,10 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
     for (int j = 0; j < CD_SPEC_MAX; ++j) lc[j] = 0.0;
     int nspec = 0;
     bool alive = true;                                    // uniform over the wave
+    // steps whose tie threshold stays above every non-candidate residual stand for sure
+    // (those residuals only decrease); speculation goes CD_SPEC_MARGIN steps past them
+    const double dnc = st->dnc;
+    int stop_at = nmax;
 #pragma unroll
     for (int j = 0; j < CD_SPEC_MAX; ++j) {
         if (j >= nmax) alive = false;
@@ -877,6 +885,9 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
         if (cmax == -INFINITY || cmax <= cp.delta) alive = false;   // termination: per-step path
         if (!alive) continue;
         const double thr = cmax - tie_window(cmax, cp.tau);
+        if (!(thr > dnc) && j + CD_SPEC_MARGIN < stop_at) stop_at = j + CD_SPEC_MARGIN;
+        if (j >= stop_at) alive = false;
+        if (!alive) continue;
         // pivot: the lowest row index within the tie window; usually one lane is in it
         const unsigned long long win = __ballot(elig && d >= thr);
         int64_t pm;
@@ -937,7 +948,7 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
     }
     if (l == 0) {
         so->nspec = nspec;
-        so->viol = 0u;
+        so->viol = 0ull;
         so->k0 = k0;
     }
 }
@@ -967,35 +978,52 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, con
     double cv[CD_SPEC_MAX];
 #pragma unroll
     for (int j = 0; j < CD_SPEC_MAX; ++j) cv[j] = (ok && j < ns) ? R[(int64_t)ss.slot[j] * ldr + I] : 0.0;
-    unsigned viol = 0u;
-#pragma unroll
-    for (int j = 0; j < CD_SPEC_MAX; ++j) {
-        if (j >= ns || !ok) continue;
-        if (m == 0 && (d > ss.cmax[j] || (d >= ss.thr[j] && I < ss.p[j]))) viol |= 1u << j;
-        if (m != 1 && d < -cp.psd_tol) viol |= 1u << j;     // NOT_PSD is the per-step path's call
-        double lj;
-        if (m == 1) {
-            lj = 0.0;
-        } else if (I == ss.p[j]) {
-            lj = ss.sq[j];
-            d = 0.0;
-            m = 1;
-        } else {
-            lj = cv[j] / ss.sq[j];
-            d = fma(-lj, lj, d);
+    // Steps in chunks of CD_SPEC_CHUNK.  After each chunk a wave publishes the checks it saw
+    // fail, and it stops once any step before the next chunk has failed anywhere (that read
+    // is issued at the chunk's start and may be late, which only delays the stop): the
+    // commit keeps the steps before the first failure, all of which every row has made.
+    unsigned long long viol = 0ull, pub = 0ull;
+    bool live = ok;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < CD_SPEC_MAX / CD_SPEC_CHUNK; ++c) {
+        const unsigned long long seen =
+            c > 0 ? __hip_atomic_load(&so->viol, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+#pragma clang loop unroll(full)
+        for (int u = 0; u < CD_SPEC_CHUNK; ++u) {
+            const int j = c * CD_SPEC_CHUNK + u;
+            if (j >= ns || !live) continue;
+            if (m == 0 && (d > ss.cmax[j] || (d >= ss.thr[j] && I < ss.p[j]))) viol |= 1ull << j;
+            if (m != 1 && d < -cp.psd_tol) viol |= 1ull << j;     // NOT_PSD is the per-step path's call
+            double lj;
+            if (m == 1) {
+                lj = 0.0;
+            } else if (I == ss.p[j]) {
+                lj = ss.sq[j];
+                d = 0.0;
+                m = 1;
+            } else {
+                lj = cv[j] / ss.sq[j];
+                d = fma(-lj, lj, d);
+            }
+            L[(k0 + j) * ldl + I] = lj;
+            Dbuf[(int64_t)j * cp.npairs + I] = d;
+            if (m != 1) {
+                // a pivot row (also the one made now) takes no further values; lpiv[j][j'] =
+                // L_j[p_j'], 0 for j' >= ns
+#pragma clang loop unroll(full)
+                for (int jj = j + 1; jj < CD_SPEC_MAX; ++jj) cv[jj] = fma(-lj, ss.lpiv[j][jj], cv[jj]);
+            }
         }
-        L[(k0 + j) * ldl + I] = lj;
-        Dbuf[(int64_t)j * cp.npairs + I] = d;
-        if (m != 1) {
-            // a pivot row (also the one made now) takes no further values; lpiv[j][j'] =
-            // L_j[p_j'], 0 for j' >= ns
-#pragma unroll
-            for (int jj = j + 1; jj < CD_SPEC_MAX; ++jj) cv[jj] = fma(-lj, ss.lpiv[j][jj], cv[jj]);
+        // wave OR of the failed checks; new ones are published at once
+        unsigned long long w = viol;
+        for (int o = 32; o > 0; o >>= 1) w |= (unsigned long long)__shfl_xor((long long)w, o, 64);
+        if (w & ~pub) {
+            if ((threadIdx.x & 63) == 0) atomicOr((unsigned long long *)&so->viol, w);
+            pub |= w;
         }
+        const int next = (c + 1) * CD_SPEC_CHUNK;
+        if ((seen | w) & (next >= 64 ? ~0ull : ((1ull << next) - 1))) live = false;
     }
-    // wave OR, one atomic per wave
-    for (int o = 32; o > 0; o >>= 1) viol |= (unsigned)__shfl_xor((int)viol, o, 64);
-    if ((threadIdx.x & 63) == 0 && viol) atomicOr(&so->viol, viol);
 }
 
 // empty the two super-tile key buffers that the commit and the step after it fill
@@ -1111,7 +1139,8 @@ __device__ unsigned long long radix_boundary(const unsigned long long (&u)[KPT],
 // how many were written.
 template <int NT, int KPT, typename F>
 __device__ int select_top(const unsigned long long (&u)[KPT], int want, unsigned int *hist,
-                          unsigned long long *s_prefix, int *s_need, int *shs, F &&emit)
+                          unsigned long long *s_prefix, int *s_need, int *shs, F &&emit,
+                          unsigned long long *s_rest)
 {
     const unsigned long long thr = radix_boundary<NT, KPT>(u, want, hist, s_prefix, s_need);
     int na = 0, nbd = 0;
@@ -1125,18 +1154,29 @@ __device__ int select_top(const unsigned long long (&u)[KPT], int want, unsigned
     int ia = block_excl_scan<NT>(na, shs, &tot_a);
     int ib = block_excl_scan<NT>(nbd, shs, &tot_b);
     const int nabove = min(tot_a, want);
+    unsigned long long rest = 0ull;             // largest key not selected
 #pragma unroll
     for (int e = 0; e < KPT; ++e) {
         if (u[e] == 0ull) continue;
         const int id = threadIdx.x * KPT + e;
         if ((u[e] >> 32) > thr) {
             if (ia < want) emit(ia, id);
+            else rest = max(rest, u[e]);
             ++ia;
         } else if ((u[e] >> 32) == thr) {
             if (nabove + ib < want) emit(nabove + ib, id);
+            else rest = max(rest, u[e]);
             ++ib;
+        } else {
+            rest = max(rest, u[e]);
         }
     }
+    // block maximum of rest (wave, then the waves through LDS)
+    for (int o = 32; o > 0; o >>= 1) rest = max(rest, (unsigned long long)__shfl_xor((long long)rest, o, 64));
+    if (threadIdx.x == 0) *s_rest = 0ull;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && rest) atomicMax(s_rest, rest);
+    __syncthreads();
     return min(nabove + tot_b, want);
 }
 
@@ -1156,6 +1196,7 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     __shared__ int s_need;
     __shared__ int shs[CD_AUX_NT / 64 + 1];
     __shared__ int64_t stile[CD_NCAND];
+    __shared__ unsigned long long s_rest;
     if (st->done) return;
     const bool chained = k < 0;                  // speculative block: position from the state
     if (chained) {
@@ -1187,7 +1228,8 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
         u[e] = v > 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
     }
     const int ntsel = select_top<CD_AUX_NT, TK>(u, CD_NCAND, hist, &s_prefix, &s_need, shs,
-                                                 [&](int pos, int id) { stile[pos] = id; });
+                                                 [&](int pos, int id) { stile[pos] = id; }, &s_rest);
+    const unsigned long long rest_tile = s_rest;  // largest maximum of a tile not selected
     __syncthreads();
     unsigned long long v[RK];
 #pragma unroll
@@ -1205,13 +1247,17 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     }
     const int nrow = select_top<CD_AUX_NT, RK>(v, CD_NCAND - 1, hist, &s_prefix, &s_need, shs, [&](int pos, int id) {
         cand[1 + pos] = stile[id / CD_TILE] * CD_TILE + id % CD_TILE;
-    });
+    }, &s_rest);
+    // every eligible row outside the candidates is at most the larger of the two rests (keys
+    // are the bits of positive doubles; 0 = none)
+    const unsigned long long rest = max(rest_tile, s_rest);
     if (threadIdx.x == 0) cand[0] = p;
     __syncthreads();
     if ((int)threadIdx.x < 1 + nrow) b.slot[cand[threadIdx.x]] = (signed char)threadIdx.x;
     if (threadIdx.x == 0) {
         st->ncand = 1 + nrow;
         st->nmap = 1 + nrow;
+        st->dnc = rest ? __longlong_as_double((long long)rest) : 0.0;
         if (chained) {
             st->npass += 1;
             st->sumk0 += (double)k;

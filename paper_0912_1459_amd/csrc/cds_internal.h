@@ -59,7 +59,7 @@ struct cds_ctx {
     std::vector<hipEvent_t> free_events;
     bool broken = false;
     bool kernel_timing = false;      // time every CD step / pass launch with events
-    int cd_lookahead = 32;           // Cholesky look-ahead block length (0: plain steps)
+    int cd_lookahead = 48;           // Cholesky look-ahead block length (0: plain steps)
     int cd_large_path = 0;           // 1: Cholesky code path of large pair counts at any size
     int cd_speculate = 1;            // 1: speculative look-ahead blocks
     int transform_fp64 = 0;          // 1: transform GEMMs in FP64, output rounded to its precision
