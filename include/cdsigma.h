@@ -126,10 +126,11 @@ int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
  * forms the residual columns of up to 64 candidate pivots (the next pivot and
  * the largest residual diagonals); steps whose pivot is a candidate then only
  * subtract the vectors made since.  0 disables it (each step streams all of L).
- * Default 32; valid range [0, 256]. */
+ * With speculative blocks on, it also caps their length (at most 48).
+ * Default 48; valid range [0, 256]. */
 int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
 /* Speculative look-ahead blocks of the Cholesky decomposition: 1 (default)
- * = after each look-ahead pass, the next (up to 32) steps restricted to the
+ * = after each look-ahead pass, the next (up to 48) steps restricted to the
  * candidates are decomposed in one small kernel, one launch makes those vectors
  * for every row and checks that no other row would have been chosen, the steps
  * before the first failing one are committed, and the next look-ahead block
