@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     p.add_argument("--workload", default="c60", choices=["c60", "large"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-overlap", action="store_true",
+                   help="decomposition, then transform (instead of the transform beside the decomposition)")
     p.add_argument("--cpu-targets", type=int, default=4, help="targets in the oracle Newton sample")
     p.add_argument("--quick", action="store_true",
                    help="timed steps and roofline only (no precision, MP2, sweep, aCD or Dyson reports)")
@@ -133,11 +135,16 @@ def main():
         # the blocks are rounded for the contraction
         ctx.set_transform_fp64(True)
     nsel = len(w.targets)
-    max_vec = (12 if args.workload == "c60" else 6) * w.nbf     # grows by resuming if short
+    max_vec = (12 if args.workload == "c60" else 6) * w.nbf     # enough for both workloads at their delta
 
     def step(prec):
-        cd = C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, grow=True, ctx=ctx)
-        B = C.transform(cd.Lbuf, cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
+        if args.no_overlap:
+            cd = C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, grow=True, ctx=ctx)
+            B = C.transform(cd.Lbuf, cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
+        else:
+            # the transform of the vectors made so far runs beside the decomposition
+            cd, B = C.cholesky_transform(delta, centres=centres, alpha=alpha, C=Cm, nocc=w.nocc, sel=w.targets,
+                                         prec=prec, max_vec=max_vec, ctx=ctx)
         qp = C.qp_solve(B, eps, conv=conv, mode="residues", ctx=ctx)
         return cd, B, qp
 
@@ -219,7 +226,7 @@ def main():
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
                           "higher_is_better": True, "roofline": roofline,
                           "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M,
-                                 "kernels": cd_kernels},
+                                 "kernels": cd_kernels, "transform_overlapped": not args.no_overlap},
                           "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
                                         ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms",
                                          "t_newton_ms")}}))
@@ -363,6 +370,7 @@ def main():
                    "nvec": M, "prec": args.prec},
         "roofline": roofline,
         "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M, "kernels": cd_kernels,
+               "transform_overlapped": not args.no_overlap,
                # bytes the plain one-vector-per-step algorithm streams, over the whole decomposition
                "plain_algorithm_equivalent_gbs": round(st_run["bytes_cd"] / (st_run["t_cd_ms"] / 1e3) / 1e9, 1)},
         "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in

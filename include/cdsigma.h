@@ -229,14 +229,43 @@ int cds_cholesky_sgauss_subset(cds_ctx *ctx, int32_t nbf, const double *centres,
  *   Bvo [(a*nocc + i)*ldk + K] = B^K[nocc + a, i]          a < nmo-nocc, i < nocc
  * Entries K in [nvec, ldk) are written as 0 (ldk >= nvec; ldk a multiple of 64
  * is fastest).  C: nbf x nmo row-major (C[mu*nmo + p]), columns are MOs.
- * prec: CDS_PREC_FP64 writes double; CDS_PREC_FP32 and CDS_PREC_BF16X3 write
- * float (the bf16 split happens inside the contraction).  The transform
- * itself runs in FP64 for FP64 output and in the requested precision
- * otherwise.  h_sel: host int32[nsel], each in [0, nmo).
+ * prec: CDS_PREC_FP64 writes double; CDS_PREC_FP32 writes float;
+ * CDS_PREC_BF16X3 writes each block as two bf16 planes, the hi plane (rows x
+ * ldk) followed by the lo plane, with hi = x rounded to bf16 and lo = the FP32
+ * remainder x - hi rounded to bf16.  The transform itself runs in FP64 for FP64
+ * output and in the requested precision otherwise (see
+ * cds_set_transform_fp64).  h_sel: host int32[nsel], each in [0, nmo).
  */
 int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const double *L,
                   int64_t ldl, const double *C, int32_t nmo, int32_t nocc, int32_t nsel,
                   const int32_t *h_sel, int64_t ldk, void *Bsel, void *Bvo);
+
+/*
+ * The decomposition of cds_cholesky_sgauss from a fresh start (nvec_in = 0)
+ * and the transform of cds_transform of its vectors (Eq. (transformation)) in
+ * one call, the transform overlapped with the decomposition: vectors become
+ * final when the decomposition's host loop reads its device state, and after
+ * each look-ahead block's pass a piece of them (up to 96) is transformed on a
+ * second stream of the library (default priority), which fills the device
+ * while the block's single-workgroup kernels run; the remaining vectors
+ * follow the last one.  The results are those of
+ * cds_cholesky_sgauss(..., nvec_in = 0, ...) followed by cds_transform(...,
+ * nvec = *h_nvec, ...) with the same arguments, bit for bit (each vector's
+ * blocks do not depend on how the vectors are batched).
+ * ldk >= max_vec (the number of vectors is known only at the end); entries K
+ * in [*h_nvec, ldk) are written as 0.  On CDS_ECAP and CDS_ENOTPSD the vectors
+ * made are transformed as well.  Before returning, the call makes the caller's
+ * stream wait for the side stream, so work queued there afterwards sees Bsel
+ * and Bvo.  Arguments, layouts and other errors as the two calls.  The
+ * statistics record the decomposition as cds_cholesky_sgauss does and, as the
+ * transform time, only the part left after the decomposition ends.
+ */
+int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const double *centres,
+                                  const double *alpha, double delta, double tau, double psd_tol,
+                                  int64_t max_vec, double *L, int64_t ldl, int64_t *piv, double *D,
+                                  int32_t prec, const double *C, int32_t nmo, int32_t nocc,
+                                  int32_t nsel, const int32_t *h_sel, int64_t ldk, void *Bsel,
+                                  void *Bvo, int64_t *h_nvec, double *h_dmax, int32_t *h_status);
 
 /*
  * Second-order self-energy, Eq. (SE), and its energy derivative at T trial

@@ -318,6 +318,47 @@ def transform(L: torch.Tensor, nvec: int, C: torch.Tensor, nocc: int, sel, prec=
     return BBlocks(prec, Bsel, Bvo, nvec, ldk, nmo, nocc, sel)
 
 
+def cholesky_transform(delta: float, *, centres: torch.Tensor, alpha: torch.Tensor, C: torch.Tensor, nocc: int,
+                       sel, prec="fp64", tau: float = -1.0, psd_tol: float = -1.0, max_vec: int | None = None,
+                       ctx: Context | None = None) -> tuple[CDResult, BBlocks]:
+    """cholesky() from a fresh start and transform() of its vectors in one library call.
+
+    The transform of the vectors made so far runs on a second stream while the decomposition
+    goes on; the results equal the two calls with ldk = round_up(max_vec, 64).  max_vec must
+    be large enough (there is no growth): CDS_ECAP raises.
+    """
+    prec = _prec(prec)
+    _dev(centres, torch.float64, "centres")
+    _dev(alpha, torch.float64, "alpha")
+    _dev(C, torch.float64, "C")
+    nbf = alpha.shape[0]
+    np_ = npairs(nbf)
+    dev = alpha.device
+    ctx = ctx or context(dev.index or 0)
+    if max_vec is None:
+        max_vec = max(64, 12 * nbf)
+    max_vec = int(min(max_vec, np_))
+    ldl = round_up(np_, 64)
+    Lbuf = torch.empty((max_vec, ldl), dtype=torch.float64, device=dev)
+    piv = torch.zeros(max_vec, dtype=torch.int64, device=dev)
+    D = torch.empty(np_, dtype=torch.float64, device=dev)
+    nmo = C.shape[1]
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+    ldk = round_up(max_vec, 64)
+    Bsel = _alloc_B(prec, sel.shape[0] * nmo, ldk, dev)
+    Bvo = _alloc_B(prec, (nmo - nocc) * nocc, ldk, dev)
+    nvec = ctypes.c_int64()
+    dmax = ctypes.c_double()
+    status = ctypes.c_int32()
+    rc = ctx.lib.cds_cholesky_transform_sgauss(
+        ctx.h, nbf, _ptr(centres), _ptr(alpha), float(delta), float(tau), float(psd_tol), max_vec, _ptr(Lbuf), ldl,
+        _ptr(piv), _ptr(D), prec, _ptr(C), nmo, nocc, sel.shape[0], sel.ctypes.data_as(ctypes.c_void_p), ldk,
+        _ptr(Bsel), _ptr(Bvo), ctypes.byref(nvec), ctypes.byref(dmax), ctypes.byref(status))
+    ctx.check(rc, ok=(A.CDS_OK, A.CDS_ENOTPSD))
+    cd = CDResult(Lbuf, piv, D, int(nvec.value), float(dmax.value), int(status.value), np_)
+    return cd, BBlocks(prec, Bsel, Bvo, cd.nvec, ldk, nmo, nocc, sel)
+
+
 def blocks_from_numpy(Bsel: np.ndarray, Bvo: np.ndarray, nocc: int, sel, prec="fp64", *, ldk=None,
                       device="cuda") -> BBlocks:
     """Upload oracle-layout blocks Bsel (M, nsel, nmo), Bvo (M, nvirt, nocc) into the kernel layout."""

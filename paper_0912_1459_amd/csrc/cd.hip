@@ -1478,7 +1478,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                   const double *alpha, int64_t npairs, const double *V, int64_t ldv, double delta,
                   double tau, double psd_tol, int64_t max_vec, double *L, int64_t ldl,
                   int64_t *piv, double *D, int64_t nvec_in, int64_t *h_nvec, double *h_dmax,
-                  int32_t *h_status, const unsigned char *allowed = nullptr)
+                  int32_t *h_status, const unsigned char *allowed = nullptr, const CdHook *hook = nullptr)
 {
     CDS_CALL(cds_enter(ctx));
     CDS_REQUIRE(ctx, npairs >= 1, "npairs must be >= 1");
@@ -1607,6 +1607,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         k = hs.k;
         if (k > max_vec)
             return cds_fail(ctx, CDS_EDEVICE, "CD did not terminate at max_vec=%lld", (long long)max_vec);
+        if (hook) CDS_CALL(hook->committed(hook->user, k));
         if (hs.stall) {
             CDS_HIP(ctx, hipMemsetAsync(&st->stall, 0, sizeof(int32_t), ctx->stream));
             const int64_t s = k - nvec_in;
@@ -1645,6 +1646,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                (const signed char *)bf.slot, bf.rc);
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
+            if (hook && hook->block) CDS_CALL(hook->block(hook->user));
             CdsTimer tsp;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
             hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const double *)Rc, ldr,
@@ -1674,6 +1676,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                             (long long)hs.k, (long long)k);
         if (k > max_vec)
             return cds_fail(ctx, CDS_EDEVICE, "CD did not terminate at max_vec=%lld", (long long)max_vec);
+        if (hook) CDS_CALL(hook->committed(hook->user, k));
         // steps k <= max_vec: the step at k == max_vec only records the termination (CAP or
         // convergence) and writes no vector
         for (int bi = 0; bi < batch && k <= max_vec; ++bi, ++k) {
@@ -1775,6 +1778,16 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
 }
 
 }  // namespace
+
+int cds_cholesky_hooked(cds_ctx *ctx, int32_t nbf, const double *centres, const double *alpha, double delta,
+                        double tau, double psd_tol, int64_t max_vec, double *L, int64_t ldl, int64_t *piv,
+                        double *D, int64_t *h_nvec, double *h_dmax, int32_t *h_status, const CdHook *hook)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (nbf < 1 || !centres || !alpha) return cds_fail(ctx, CDS_EINVAL, "nbf < 1 or NULL basis");
+    return cholesky_impl(ctx, false, nbf, centres, alpha, cds_npairs(nbf), nullptr, 0, delta, tau, psd_tol,
+                         max_vec, L, ldl, piv, D, 0, h_nvec, h_dmax, h_status, nullptr, hook);
+}
 
 extern "C" {
 

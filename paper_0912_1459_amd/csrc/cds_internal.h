@@ -63,6 +63,9 @@ struct cds_ctx {
     int cd_large_path = 0;           // 1: Cholesky code path of large pair counts at any size
     int cd_speculate = 1;            // 1: speculative look-ahead blocks
     int transform_fp64 = 0;          // 1: transform GEMMs in FP64, output rounded to its precision
+    hipStream_t stream2 = nullptr;   // side stream (default priority) of the overlapped transform
+    hipEvent_t join = nullptr;       // orders stream2 after / before the caller's stream
+    hipEvent_t gate = nullptr;       // orders a stream2 batch after a point of the caller's stream
 };
 
 // error helpers -------------------------------------------------------------
@@ -122,6 +125,22 @@ __device__ __forceinline__ void cds_pair_decode(int64_t I, int64_t &mu, int64_t 
 static inline size_t cds_prec_bytes(int prec) { return prec == CDS_PREC_FP64 ? 8 : 4; }
 
 // internal entry points shared between translation units ----------------------
+// Progress of a decomposition: after each read of its device state the host loop calls
+// committed(user, k) with the number of vectors that are final (no later kernel of the
+// decomposition writes L[0..k) again, and the caller's stream has completed their writes).
+// A non-zero return ends the decomposition with that status.
+// block(user) is called after each look-ahead block's pass has been queued on the caller's
+// stream (may be NULL).
+struct CdHook {
+    int (*committed)(void *user, int64_t k);
+    int (*block)(void *user);
+    void *user;
+};
+// cds_cholesky_sgauss from a fresh start (nvec_in = 0) with a progress hook
+int cds_cholesky_hooked(cds_ctx *ctx, int32_t nbf, const double *centres, const double *alpha, double delta,
+                        double tau, double psd_tol, int64_t max_vec, double *L, int64_t ldl, int64_t *piv,
+                        double *D, int64_t *h_nvec, double *h_dmax, int32_t *h_status, const CdHook *hook);
+
 // GEMM engine (gemm.hip): C[b][m][n] = alpha * sum_k A(m,k) B(k,n) (+ beta C)
 struct GemmDesc {
     int64_t M, N, K, batch;

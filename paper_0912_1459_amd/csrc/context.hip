@@ -34,6 +34,7 @@ int cds_ws(cds_ctx *ctx, int slot, size_t bytes, void **out)
     if (ctx->ws_bytes[slot] < bytes) {
         if (ctx->ws[slot]) {
             CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->stream2) CDS_HIP(ctx, hipStreamSynchronize(ctx->stream2));
             CDS_HIP(ctx, hipFree(ctx->ws[slot]));
             ctx->ws[slot] = nullptr;
             ctx->ws_bytes[slot] = 0;
@@ -134,6 +135,12 @@ void cds_destroy(cds_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->stream2) {
+        (void)hipStreamSynchronize(ctx->stream2);
+        (void)hipStreamDestroy(ctx->stream2);
+    }
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->gate) (void)hipEventDestroy(ctx->gate);
     for (auto &t : ctx->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);

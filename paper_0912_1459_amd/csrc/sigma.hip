@@ -409,7 +409,8 @@ int contract_chunk(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const v
     GemmDesc d = {};
     d.M = (int64_t)nsc * sh.nmo;
     d.N = sh.nvo;
-    d.K = sh.ldk;
+    // entries K in [nvec, ldk) are zero: the sum stops at the first multiple of 64 past nvec
+    d.K = std::min<int64_t>(sh.ldk, cds_ceil_div(sh.nvec, 64) * 64);
     d.batch = 1;
     d.A = (const unsigned char *)Bsel + (size_t)s0 * sh.nmo * sh.ldk * es;
     d.sAm = sh.ldk;

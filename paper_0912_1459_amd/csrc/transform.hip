@@ -179,13 +179,25 @@ __global__ void zero_pad_kernel(int64_t nrows, int64_t ldk, int64_t nvec, void *
 
 size_t wsize(int prec) { return prec == CDS_PREC_FP64 ? 8 : (prec == CDS_PREC_FP32 ? 4 : 4); }
 
-}  // namespace
+// One transform: sizes, working precision, workspace and the launches of each stage.
+struct TrPlan {
+    int prec, wp, nbf, nmo, nocc, nsel, nvirt, nx, np_, kbatch;
+    int64_t nvo, nselr, nrows, ldl, ldk;
+    const double *L, *C;
+    void *Bsel, *Bvo;
+    const int32_t *h_sel;
+    unsigned char *Ct, *CX;
+    int32_t *dsel;
+    void *wlu, *wt, *wb;
+    float *Tf;
+    __bf16 *Ts;
+    int64_t planeCt, planeCX;
+};
 
-extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const double *L,
-                             int64_t ldl, const double *C, int32_t nmo, int32_t nocc, int32_t nsel,
-                             const int32_t *h_sel, int64_t ldk, void *Bsel, void *Bvo)
+int tr_check(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const double *L, int64_t ldl,
+             const double *C, int32_t nmo, int32_t nocc, int32_t nsel, const int32_t *h_sel, int64_t ldk,
+             void *Bsel, void *Bvo)
 {
-    CDS_CALL(cds_enter(ctx));
     CDS_REQUIRE(ctx, prec == CDS_PREC_FP64 || prec == CDS_PREC_FP32 || prec == CDS_PREC_BF16X3,
                 "unknown precision %d", prec);
     CDS_REQUIRE(ctx, nbf >= 1 && nmo >= 1 && nmo <= nbf, "need 1 <= nmo <= nbf");
@@ -196,141 +208,306 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     CDS_REQUIRE(ctx, L && C && Bsel && Bvo, "NULL pointer");
     for (int s = 0; s < nsel; ++s)
         CDS_REQUIRE(ctx, h_sel[s] >= 0 && h_sel[s] < nmo, "h_sel[%d]=%d out of range", s, h_sel[s]);
+    return CDS_OK;
+}
 
-    CdsTimer tm;
-    CDS_CALL(cds_timer_start(ctx, &tm));
-    const int nvirt = nmo - nocc;
-    const int nx = nocc + nsel;
-    const int np_ = (int)(cds_ceil_div(nbf, 64) * 64);
-    const int64_t nvo = (int64_t)nvirt * nocc, nselr = (int64_t)nsel * nmo;
-    const int64_t nrows = nvo + nselr;
+// sizes and workspace for batches of at most max(1, min(kb_cap, adaptive size)) vectors
+int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L, int64_t ldl, const double *C,
+             int32_t nmo, int32_t nocc, int32_t nsel, const int32_t *h_sel, int64_t ldk, void *Bsel, void *Bvo,
+             int64_t kb_cap)
+{
+    p.prec = prec;
+    p.nbf = nbf;
+    p.nmo = nmo;
+    p.nocc = nocc;
+    p.nsel = nsel;
+    p.nvirt = nmo - nocc;
+    p.nx = nocc + nsel;
+    p.np_ = (int)(cds_ceil_div(nbf, 64) * 64);
+    p.nvo = (int64_t)p.nvirt * nocc;
+    p.nselr = (int64_t)nsel * nmo;
+    p.nrows = p.nvo + p.nselr;
+    p.L = L;
+    p.ldl = ldl;
+    p.C = C;
+    p.h_sel = h_sel;
+    p.ldk = ldk;
+    p.Bsel = Bsel;
+    p.Bvo = Bvo;
     // working precision of the GEMMs; the output is rounded to `prec` in the last pass
-    const int wp = ctx->transform_fp64 ? CDS_PREC_FP64 : prec;
-    const size_t es = wsize(wp);
+    p.wp = ctx->transform_fp64 ? CDS_PREC_FP64 : prec;
+    const size_t es = wsize(p.wp);
     // batch: the virtual-occupied GEMM has one 128 x 128 tile group per vector and would
     // leave most of the chip idle with small batches
-    const int64_t tiles_vo = cds_ceil_div(nvirt, 128) * cds_ceil_div(nocc, 128);
+    const int64_t tiles_vo = cds_ceil_div(p.nvirt, 128) * cds_ceil_div(nocc, 128);
     int64_t kb_want = std::max<int64_t>(KBATCH_MIN, cds_ceil_div(KBATCH_WG, tiles_vo));
-    kb_want = std::min<int64_t>(kb_want, std::max<int64_t>(1, (int64_t)(KBATCH_BYTES / ((size_t)nbf * np_ * es))));
-    const int kbatch = (int)std::min<int64_t>(kb_want, nvec);
+    kb_want = std::min<int64_t>(kb_want, std::max<int64_t>(1, (int64_t)(KBATCH_BYTES / ((size_t)nbf * p.np_ * es))));
+    p.kbatch = (int)std::max<int64_t>(1, std::min<int64_t>(kb_want, kb_cap));
 
     // workspace: Ct + CX (+ sel list), Lu batch, T batch (+ split copy), Bk batch
-    void *wcx, *wlu, *wt, *wb;
-    const int64_t nCt = (int64_t)nmo * np_, nCX = (int64_t)nx * np_;
+    void *wcx;
+    const int64_t nCt = (int64_t)nmo * p.np_, nCX = (int64_t)p.nx * p.np_;
     CDS_CALL(cds_ws(ctx, WS_TR_CX, (size_t)(nCt + nCX) * es + 256 + nsel * 4, &wcx));
-    const int64_t nLu = (int64_t)kbatch * nbf * np_;
-    CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)nLu * es, &wlu));
-    const int64_t nT = (int64_t)kbatch * nx * np_;
-    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)nT * es * (wp == CDS_PREC_BF16X3 ? 2 : 1), &wt));
-    CDS_CALL(cds_ws(ctx, WS_TR_B, (size_t)kbatch * nrows * (wp == CDS_PREC_FP64 ? 8 : 4), &wb));
+    const int64_t nLu = (int64_t)p.kbatch * nbf * p.np_;
+    CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)nLu * es, &p.wlu));
+    const int64_t nT = (int64_t)p.kbatch * p.nx * p.np_;
+    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)nT * es * (p.wp == CDS_PREC_BF16X3 ? 2 : 1), &p.wt));
+    CDS_CALL(cds_ws(ctx, WS_TR_B, (size_t)p.kbatch * p.nrows * (p.wp == CDS_PREC_FP64 ? 8 : 4), &p.wb));
+    p.Ct = (unsigned char *)wcx;
+    p.CX = p.Ct + nCt * es;
+    p.dsel = (int32_t *)(p.CX + ((nCX * es + 255) / 256) * 256);
+    // for bf16 the hi and lo planes of Ct / CX take 2 x 2 bytes = es per element: each lo
+    // plane follows its hi plane inside the same byte range
+    p.planeCt = nCt;
+    p.planeCX = nCX;
+    // T: working float output, and (bf16) its two planes after it
+    p.Tf = (float *)p.wt;
+    p.Ts = (__bf16 *)((unsigned char *)p.wt + (size_t)nT * 4);
+    return CDS_OK;
+}
 
-    unsigned char *Ct = (unsigned char *)wcx;
-    unsigned char *CX = Ct + nCt * es;
-    int32_t *dsel = (int32_t *)(CX + ((nCX * es + 255) / 256) * 256);
-    CDS_HIP(ctx, hipMemcpyAsync(dsel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
-    // planes for bf16: lo plane follows the hi plane of the same buffer region
-    const int64_t planeCt = nCt, planeCX = nCX;
+// coefficient copies and the zero K padding of T (once per transform)
+int tr_setup(cds_ctx *ctx, const TrPlan &p)
+{
+    CDS_HIP(ctx, hipMemcpyAsync(p.dsel, p.h_sel, (size_t)p.nsel * 4, hipMemcpyHostToDevice, ctx->stream));
     {
-        int64_t n = (int64_t)(nmo + nx) * np_;
+        int64_t n = (int64_t)(p.nmo + p.nx) * p.np_;
         hipLaunchKernelGGL(coef_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0, ctx->stream,
-                           C, nbf, nmo, nocc, nsel, dsel, np_, (void *)Ct, (void *)CX, wp, planeCt,
-                           planeCX);
+                           p.C, p.nbf, p.nmo, p.nocc, p.nsel, p.dsel, p.np_, (void *)p.Ct, (void *)p.CX, p.wp,
+                           p.planeCt, p.planeCX);
         CDS_LAUNCHED(ctx);
     }
-    // for bf16, hi+lo planes of Ct/CX take 2 x 2 bytes = es (4) per element: place lo planes
-    // right after each hi plane inside the same byte range (hi plane uses nC*2 bytes).
-    // T: working float output, and (bf16) a split copy after it
-    float *Tf = (float *)wt;
-    __bf16 *Ts = (__bf16 *)((unsigned char *)wt + (size_t)nT * 4);
     // the first GEMM writes columns < nbf of T; the K padding [nbf, np_) must read as 0
-    if (np_ > nbf) {
-        const size_t tes0 = (wp == CDS_PREC_FP64) ? 8 : (wp == CDS_PREC_FP32 ? 4 : 2);
-        unsigned char *tb = (wp == CDS_PREC_BF16X3) ? (unsigned char *)Ts : (unsigned char *)wt;
-        const int64_t trows = (int64_t)kbatch * nx * (wp == CDS_PREC_BF16X3 ? 2 : 1);   // both planes
-        const int64_t nz = trows * (int64_t)((np_ - nbf) * tes0 / 2);
+    if (p.np_ > p.nbf) {
+        const size_t tes0 = (p.wp == CDS_PREC_FP64) ? 8 : (p.wp == CDS_PREC_FP32 ? 4 : 2);
+        unsigned char *tb = (p.wp == CDS_PREC_BF16X3) ? (unsigned char *)p.Ts : (unsigned char *)p.wt;
+        const int64_t trows = (int64_t)p.kbatch * p.nx * (p.wp == CDS_PREC_BF16X3 ? 2 : 1);   // both planes
+        const int64_t nz = trows * (int64_t)((p.np_ - p.nbf) * tes0 / 2);
         hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)cds_ceil_div(nz, 256)), dim3(256), 0, ctx->stream, tb,
-                           trows, (int64_t)np_ * (int64_t)tes0, (int)(nbf * tes0), (int)(np_ * tes0));
+                           trows, (int64_t)p.np_ * (int64_t)tes0, (int)(p.nbf * tes0), (int)(p.np_ * tes0));
         CDS_LAUNCHED(ctx);
     }
+    return CDS_OK;
+}
 
-    // zero padding of B beyond nvec
-    if (ldk > nvec) {
-        int64_t n1 = nvo * (ldk - nvec), n2 = nselr * (ldk - nvec);
-        hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)cds_ceil_div(n1, 256)), dim3(256), 0,
-                           ctx->stream, nvo, ldk, nvec, Bvo, prec, nvo * ldk);
-        hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)cds_ceil_div(n2, 256)), dim3(256), 0,
-                           ctx->stream, nselr, ldk, nvec, Bsel, prec, nselr * ldk);
+// zero entries K in [nvec, ldk) of both output blocks
+int tr_pad(cds_ctx *ctx, const TrPlan &p, int64_t nvec)
+{
+    if (p.ldk > nvec) {
+        int64_t n1 = p.nvo * (p.ldk - nvec), n2 = p.nselr * (p.ldk - nvec);
+        hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)cds_ceil_div(n1, 256)), dim3(256), 0, ctx->stream, p.nvo,
+                           p.ldk, nvec, p.Bvo, p.prec, p.nvo * p.ldk);
+        hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)cds_ceil_div(n2, 256)), dim3(256), 0, ctx->stream,
+                           p.nselr, p.ldk, nvec, p.Bsel, p.prec, p.nselr * p.ldk);
         CDS_LAUNCHED(ctx);
     }
+    return CDS_OK;
+}
 
-    const int gprec = wp;     // GEMM precision
-    for (int64_t k0 = 0; k0 < nvec; k0 += kbatch) {
-        const int nkb = (int)std::min<int64_t>(kbatch, nvec - k0);
-        {
-            const int nb = np_ / 32;
-            hipLaunchKernelGGL(unpack_blocks_kernel, dim3((unsigned)(nb * (nb + 1) / 2), (unsigned)nkb), dim3(256), 0,
-                               ctx->stream, L, ldl, k0, nbf, np_, wlu, wp, (int64_t)nkb * nbf * np_);
-            CDS_LAUNCHED(ctx);
-        }
-        const int64_t planeLu = (int64_t)nkb * nbf * np_;
-        // T[kb][x][mu] = sum_nu CX[x][nu] Lu[kb][mu][nu]
-        GemmDesc g1 = {};
-        g1.M = nx; g1.N = nbf; g1.K = np_; g1.batch = nkb;
-        g1.A = CX; g1.sAm = np_; g1.sAk = 1; g1.sAb = 0;
-        g1.B = wlu; g1.sBn = np_; g1.sBk = 1; g1.sBb = (int64_t)nbf * np_;
-        void *Tout = (wp == CDS_PREC_FP64) ? wt : (void *)Tf;
-        g1.C = Tout; g1.sCm = np_; g1.sCn = 1; g1.sCb = (int64_t)nx * np_;
-        g1.alpha = 1.0; g1.beta = 0.0;
-        if (wp == CDS_PREC_BF16X3) {
-            // T straight into its two bf16 planes (the split of the FP32 result)
-            g1.C = Ts;
-            g1.Clo = Ts + (int64_t)nkb * nx * np_;
-            CDS_CALL(cds_gemm_ex(ctx, gprec, g1, (const __bf16 *)CX + planeCX, (const __bf16 *)wlu + planeLu));
-        } else {
-            CDS_CALL(cds_gemm_ex(ctx, gprec, g1, nullptr, nullptr));
-        }
-        const void *Tin = (wp == CDS_PREC_BF16X3) ? (const void *)Ts : (const void *)Tout;
-        const int64_t planeT = (int64_t)nkb * nx * np_;
-        const size_t tes = (wp == CDS_PREC_FP64) ? 8 : (wp == CDS_PREC_FP32 ? 4 : 2);
-        const size_t ces = tes;
-        // Bk[kb][a][i] = sum_mu Ct[nocc+a][mu] T[kb][i][mu]
-        GemmDesc g2 = {};
-        g2.M = nvirt; g2.N = nocc; g2.K = np_; g2.batch = nkb;
-        g2.A = (const unsigned char *)Ct + (size_t)nocc * np_ * ces; g2.sAm = np_; g2.sAk = 1; g2.sAb = 0;
-        g2.B = Tin; g2.sBn = np_; g2.sBk = 1; g2.sBb = (int64_t)nx * np_;
-        g2.C = wb; g2.sCm = nocc; g2.sCn = 1; g2.sCb = nrows;
-        g2.alpha = 1.0; g2.beta = 0.0;
-        // Bk[kb][nvo + s*nmo + r] = sum_mu T[kb][nocc+s][mu] Ct[r][mu]
-        GemmDesc g3 = {};
-        g3.M = nsel; g3.N = nmo; g3.K = np_; g3.batch = nkb;
-        g3.A = (const unsigned char *)Tin + (size_t)nocc * np_ * tes; g3.sAm = np_; g3.sAk = 1;
-        g3.sAb = (int64_t)nx * np_;
-        g3.B = Ct; g3.sBn = np_; g3.sBk = 1; g3.sBb = 0;
-        g3.C = (unsigned char *)wb + (size_t)nvo * (wp == CDS_PREC_FP64 ? 8 : 4);
-        g3.sCm = nmo; g3.sCn = 1; g3.sCb = nrows;
-        g3.alpha = 1.0; g3.beta = 0.0;
-        if (wp == CDS_PREC_BF16X3) {
-            CDS_CALL(cds_gemm_ex(ctx, gprec, g2, (const __bf16 *)Ct + planeCt + (int64_t)nocc * np_,
-                                 Ts + planeT));
-            CDS_CALL(cds_gemm_ex(ctx, gprec, g3, Ts + planeT + (int64_t)nocc * np_,
-                                 (const __bf16 *)Ct + planeCt));
-        } else {
-            CDS_CALL(cds_gemm_ex(ctx, gprec, g2, nullptr, nullptr));
-            CDS_CALL(cds_gemm_ex(ctx, gprec, g3, nullptr, nullptr));
-        }
-        dim3 tg((unsigned)cds_ceil_div(nrows, 32), (unsigned)cds_ceil_div(nkb, 32));
-        if (wp == CDS_PREC_FP64)
-            hipLaunchKernelGGL(transpose_out_kernel<double>, tg, dim3(256), 0, ctx->stream,
-                               (const double *)wb, nrows, nkb, k0, nvo, Bvo, Bsel, ldk, prec, nvo * ldk,
-                               nselr * ldk);
-        else
-            hipLaunchKernelGGL(transpose_out_kernel<float>, tg, dim3(256), 0, ctx->stream,
-                               (const float *)wb, nrows, nkb, k0, nvo, Bvo, Bsel, ldk, prec, nvo * ldk,
-                               nselr * ldk);
+// vectors [k0, k0 + nkb), nkb <= kbatch: unpack, three GEMMs, transposed output
+int tr_batch(cds_ctx *ctx, const TrPlan &p, int64_t k0, int nkb)
+{
+    const int np_ = p.np_, nx = p.nx, nocc = p.nocc, nmo = p.nmo, nsel = p.nsel, nbf = p.nbf;
+    {
+        const int nb = np_ / 32;
+        hipLaunchKernelGGL(unpack_blocks_kernel, dim3((unsigned)(nb * (nb + 1) / 2), (unsigned)nkb), dim3(256), 0,
+                           ctx->stream, p.L, p.ldl, k0, nbf, np_, p.wlu, p.wp, (int64_t)nkb * nbf * np_);
         CDS_LAUNCHED(ctx);
     }
+    const int64_t planeLu = (int64_t)nkb * nbf * np_;
+    const int gprec = p.wp;
+    // T[kb][x][mu] = sum_nu CX[x][nu] Lu[kb][mu][nu]
+    GemmDesc g1 = {};
+    g1.M = nx; g1.N = nbf; g1.K = np_; g1.batch = nkb;
+    g1.A = p.CX; g1.sAm = np_; g1.sAk = 1; g1.sAb = 0;
+    g1.B = p.wlu; g1.sBn = np_; g1.sBk = 1; g1.sBb = (int64_t)nbf * np_;
+    void *Tout = (p.wp == CDS_PREC_FP64) ? p.wt : (void *)p.Tf;
+    g1.C = Tout; g1.sCm = np_; g1.sCn = 1; g1.sCb = (int64_t)nx * np_;
+    g1.alpha = 1.0; g1.beta = 0.0;
+    if (p.wp == CDS_PREC_BF16X3) {
+        // T straight into its two bf16 planes (the split of the FP32 result)
+        g1.C = p.Ts;
+        g1.Clo = p.Ts + (int64_t)nkb * nx * np_;
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g1, (const __bf16 *)p.CX + p.planeCX, (const __bf16 *)p.wlu + planeLu));
+    } else {
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g1, nullptr, nullptr));
+    }
+    const void *Tin = (p.wp == CDS_PREC_BF16X3) ? (const void *)p.Ts : (const void *)Tout;
+    const int64_t planeT = (int64_t)nkb * nx * np_;
+    const size_t tes = (p.wp == CDS_PREC_FP64) ? 8 : (p.wp == CDS_PREC_FP32 ? 4 : 2);
+    const size_t ces = tes;
+    // Bk[kb][a][i] = sum_mu Ct[nocc+a][mu] T[kb][i][mu]
+    GemmDesc g2 = {};
+    g2.M = p.nvirt; g2.N = nocc; g2.K = np_; g2.batch = nkb;
+    g2.A = p.Ct + (size_t)nocc * np_ * ces; g2.sAm = np_; g2.sAk = 1; g2.sAb = 0;
+    g2.B = Tin; g2.sBn = np_; g2.sBk = 1; g2.sBb = (int64_t)nx * np_;
+    g2.C = p.wb; g2.sCm = nocc; g2.sCn = 1; g2.sCb = p.nrows;
+    g2.alpha = 1.0; g2.beta = 0.0;
+    // Bk[kb][nvo + s*nmo + r] = sum_mu T[kb][nocc+s][mu] Ct[r][mu]
+    GemmDesc g3 = {};
+    g3.M = nsel; g3.N = nmo; g3.K = np_; g3.batch = nkb;
+    g3.A = (const unsigned char *)Tin + (size_t)nocc * np_ * tes; g3.sAm = np_; g3.sAk = 1;
+    g3.sAb = (int64_t)nx * np_;
+    g3.B = p.Ct; g3.sBn = np_; g3.sBk = 1; g3.sBb = 0;
+    g3.C = (unsigned char *)p.wb + (size_t)p.nvo * (p.wp == CDS_PREC_FP64 ? 8 : 4);
+    g3.sCm = nmo; g3.sCn = 1; g3.sCb = p.nrows;
+    g3.alpha = 1.0; g3.beta = 0.0;
+    if (p.wp == CDS_PREC_BF16X3) {
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g2, (const __bf16 *)p.Ct + p.planeCt + (int64_t)nocc * np_, p.Ts + planeT));
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g3, p.Ts + planeT + (int64_t)nocc * np_, (const __bf16 *)p.Ct + p.planeCt));
+    } else {
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g2, nullptr, nullptr));
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g3, nullptr, nullptr));
+    }
+    dim3 tg((unsigned)cds_ceil_div(p.nrows, 32), (unsigned)cds_ceil_div(nkb, 32));
+    if (p.wp == CDS_PREC_FP64)
+        hipLaunchKernelGGL(transpose_out_kernel<double>, tg, dim3(256), 0, ctx->stream, (const double *)p.wb, p.nrows,
+                           nkb, k0, p.nvo, p.Bvo, p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
+    else
+        hipLaunchKernelGGL(transpose_out_kernel<float>, tg, dim3(256), 0, ctx->stream, (const float *)p.wb, p.nrows,
+                           nkb, k0, p.nvo, p.Bvo, p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
+    CDS_LAUNCHED(ctx);
+    return CDS_OK;
+}
+
+// vectors [k0, k1) in batches of at most kbatch
+int tr_range(cds_ctx *ctx, const TrPlan &p, int64_t k0, int64_t k1)
+{
+    for (; k0 < k1; k0 += p.kbatch) CDS_CALL(tr_batch(ctx, p, k0, (int)std::min<int64_t>(p.kbatch, k1 - k0)));
+    return CDS_OK;
+}
+
+// launches of the calling thread go to stream s until the scope ends
+struct StreamScope {
+    cds_ctx *c;
+    hipStream_t old;
+    StreamScope(cds_ctx *c_, hipStream_t s) : c(c_), old(c_->stream) { c->stream = s; }
+    ~StreamScope() { c->stream = old; }
+};
+
+// Transform of the decomposition's vectors while it runs, on the side stream.  With look-ahead
+// blocks, each block's pass is followed (through an event) by a piece of at most OVL_PIECE of
+// the vectors known to be final, so the piece runs in the block's single-workgroup and
+// row-update kernels, where most of the device is idle, rather than beside the passes (pieces
+// of 96 measured better than 32, 48, 128, 192 or 256, and than batches queued at each read of
+// the state, which slowed the decomposition by 0.65 ms on c60).  Without blocks (per-step
+// launches), the vectors made since the last batch go at each read of the state, at least
+// OVL_MIN of them.
+constexpr int64_t OVL_MIN = 128;
+constexpr int64_t OVL_PIECE = 96;
+constexpr int64_t OVL_CAP = 512;    // batch size the workspace holds
+
+struct Overlap {
+    cds_ctx *ctx;
+    TrPlan *p;
+    int64_t kdone = 0;    // vectors queued on the side stream
+    int64_t kfinal = 0;   // vectors known to be final
+    bool started = false;
+    bool gated = false;   // pieces follow the blocks (the decomposition runs look-ahead blocks)
+};
+
+int overlap_queue(Overlap &o, int64_t k1)
+{
+    StreamScope sc(o.ctx, o.ctx->stream2);
+    if (!o.started) {
+        CDS_CALL(tr_setup(o.ctx, *o.p));
+        o.started = true;
+    }
+    CDS_CALL(tr_range(o.ctx, *o.p, o.kdone, k1));
+    o.kdone = k1;
+    return CDS_OK;
+}
+
+int overlap_committed(void *user, int64_t k)
+{
+    Overlap &o = *(Overlap *)user;
+    o.kfinal = k;
+    if (o.gated || k - o.kdone < OVL_MIN) return CDS_OK;
+    return overlap_queue(o, k);
+}
+
+// a piece of the final vectors, started on the side stream once the block's pass is done
+int overlap_block(void *user)
+{
+    Overlap &o = *(Overlap *)user;
+    o.gated = true;
+    if (o.kfinal - o.kdone < OVL_PIECE / 2) return CDS_OK;
+    CDS_HIP(o.ctx, hipEventRecord(o.ctx->gate, o.ctx->stream));
+    CDS_HIP(o.ctx, hipStreamWaitEvent(o.ctx->stream2, o.ctx->gate, 0));
+    return overlap_queue(o, std::min<int64_t>(o.kfinal, o.kdone + OVL_PIECE));
+}
+
+}  // namespace
+
+extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const double *L,
+                             int64_t ldl, const double *C, int32_t nmo, int32_t nocc, int32_t nsel,
+                             const int32_t *h_sel, int64_t ldk, void *Bsel, void *Bvo)
+{
+    CDS_CALL(cds_enter(ctx));
+    CDS_CALL(tr_check(ctx, prec, nbf, nvec, L, ldl, C, nmo, nocc, nsel, h_sel, ldk, Bsel, Bvo));
+    CdsTimer tm;
+    CDS_CALL(cds_timer_start(ctx, &tm));
+    TrPlan p;
+    CDS_CALL(tr_alloc(ctx, p, prec, nbf, L, ldl, C, nmo, nocc, nsel, h_sel, ldk, Bsel, Bvo, nvec));
+    CDS_CALL(tr_setup(ctx, p));
+    CDS_CALL(tr_pad(ctx, p, nvec));
+    CDS_CALL(tr_range(ctx, p, 0, nvec));
     CDS_CALL(cds_timer_stop(ctx, &tm, &ctx->stats.t_transform_ms));
     return CDS_OK;
+}
+
+extern "C" int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const double *centres, const double *alpha,
+                                             double delta, double tau, double psd_tol, int64_t max_vec, double *L,
+                                             int64_t ldl, int64_t *piv, double *D, int32_t prec, const double *C,
+                                             int32_t nmo, int32_t nocc, int32_t nsel, const int32_t *h_sel,
+                                             int64_t ldk, void *Bsel, void *Bvo, int64_t *h_nvec, double *h_dmax,
+                                             int32_t *h_status)
+{
+    CDS_CALL(cds_enter(ctx));
+    CDS_REQUIRE(ctx, nbf >= 1 && centres && alpha, "need nbf >= 1, centres and alpha");
+    CDS_REQUIRE(ctx, max_vec >= 1, "max_vec must be >= 1");
+    CDS_CALL(tr_check(ctx, prec, nbf, max_vec, L, ldl, C, nmo, nocc, nsel, h_sel, ldk, Bsel, Bvo));
+    if (!ctx->stream2) {
+        CDS_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking));
+        CDS_HIP(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+        CDS_HIP(ctx, hipEventCreateWithFlags(&ctx->gate, hipEventDisableTiming));
+    }
+    // everything the side stream uses is allocated before any work is queued
+    TrPlan p;
+    CDS_CALL(tr_alloc(ctx, p, prec, nbf, L, ldl, C, nmo, nocc, nsel, h_sel, ldk, Bsel, Bvo,
+                      std::min<int64_t>(OVL_CAP, max_vec)));
+    // the side stream starts after everything queued before this call
+    CDS_HIP(ctx, hipEventRecord(ctx->join, ctx->stream));
+    CDS_HIP(ctx, hipStreamWaitEvent(ctx->stream2, ctx->join, 0));
+    Overlap ov;
+    ov.ctx = ctx;
+    ov.p = &p;
+    CdHook hook = {overlap_committed, overlap_block, &ov};
+    const int rc = cds_cholesky_hooked(ctx, nbf, centres, alpha, delta, tau, psd_tol, max_vec, L, ldl, piv, D,
+                                       h_nvec, h_dmax, h_status, &hook);
+    int rt = CDS_OK;
+    // transform time exposed after the decomposition: from its end to the join
+    CdsTimer tm;
+    const bool timed = rc == CDS_OK || rc == CDS_ECAP || rc == CDS_ENOTPSD;
+    if (timed) rt = cds_timer_start(ctx, &tm);
+    if (rt == CDS_OK && timed) {
+        // the rest of the vectors, on the side stream after the earlier batches
+        StreamScope sc(ctx, ctx->stream2);
+        const std::string err = ctx->err;
+        if (!ov.started) rt = tr_setup(ctx, p);
+        if (rt == CDS_OK && *h_nvec > ov.kdone) rt = tr_range(ctx, p, ov.kdone, *h_nvec);
+        if (rt == CDS_OK) rt = tr_pad(ctx, p, *h_nvec);
+        if (rt == CDS_OK) ctx->err = err;
+    }
+    // the caller's stream waits for the side stream
+    CDS_HIP(ctx, hipEventRecord(ctx->join, ctx->stream2));
+    CDS_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join, 0));
+    if (rt == CDS_OK && timed) {
+        const std::string err = ctx->err;
+        rt = cds_timer_stop(ctx, &tm, &ctx->stats.t_transform_ms);
+        if (rt == CDS_OK) ctx->err = err;
+    }
+    return rt != CDS_OK ? rt : rc;
 }
 
 extern "C" int cds_set_transform_fp64(cds_ctx *ctx, int32_t on)
