@@ -63,6 +63,7 @@ constexpr int CD_ONE_TILE_MAX = 1280;   // tiles up to which a step block holds 
 constexpr int CD_SPEC_MAX = 48;         // steps of one speculative look-ahead block (multiple of 8, <= 64)
 constexpr int CD_SPEC_CHUNK = 8;        // steps between the rows kernel's looks at the published checks
 constexpr int CD_SPEC_MARGIN = 8;       // speculated steps past the last one that is sure to stand
+constexpr int CD_FUSE_MAXBLK = 256;     // row workgroups up to which every one forms the speculative block
 constexpr int CD_CAND_MAXTILE = 8192;   // tiles the candidate selection handles (look-ahead
                                         // is off above 8192 * 64 pairs)
 
@@ -283,25 +284,10 @@ __device__ __forceinline__ double wave_min(double v)
 }
 // Wave reductions through DPP row operations (quad swaps, half-row and row mirrors) and
 // four lane reads, instead of six rounds of cross-lane permutes: result in every lane.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
                             __builtin_amdgcn_readlane(__double2loint(v), lane));
-}
-__device__ __forceinline__ double wave_max_dpp(double v)
-{
-    v = fmax(v, dpp_f64<0xB1>(v));     // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_f64<0x4E>(v));     // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_f64<0x141>(v));    // row_half_mirror
-    v = fmax(v, dpp_f64<0x140>(v));    // row_mirror: every lane holds its 16-lane row maximum
-    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 // maximum over the wave (DPP row_shr 1, 2, 4, 8, then row_bcast 15, 31; lane 63 holds it)
 __device__ __forceinline__ unsigned wave_max_u32_dpp(unsigned v)
@@ -829,22 +815,35 @@ __device__ __forceinline__ int spec_keep(const SpecOut *so)
     return min(so->nspec, first);
 }
 
-__global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, const double *__restrict__ R,
-                                                     int64_t ldr, const int64_t *__restrict__ cand,
-                                                     const CdState *st, SpecOut *so)
+// LDS of the speculative block: the candidates' residual block, their entries of the speculated
+// vectors and the per-step records
+struct SpecLds {
+    double Rcc[CD_NCAND][CD_NCAND + 1];           // Rcc[s][c] = R[s][cand_c]
+    __align__(16) double Lt[64][CD_SPEC_MAX + 2]; // Lt[c][i] = L[k0+i][cand_c]
+    int64_t spj[CD_SPEC_MAX];
+    int ssj[CD_SPEC_MAX];
+    double ssq[CD_SPEC_MAX], scm[CD_SPEC_MAX], sth[CD_SPEC_MAX];
+};
+
+// orders one wave's LDS accesses across lanes without a workgroup barrier: the wave's LDS
+// operations so far have completed (lgkmcnt(0)) and the compiler moves no access across
+__device__ __forceinline__ void wave_lds_sync()
 {
-    if (spec_idle(st)) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The speculative block, run by one wave (threads 0..63 of the workgroup; no workgroup
+// barrier inside): lane c = candidate c, its column of the speculated vectors in registers
+// (lc), the pivot's entries through LDS.  Writes every field of `out` (LDS) but viol.
+__device__ __forceinline__ void spec_body(const CdBufs &b, const CdParams &cp, const int64_t *__restrict__ cand,
+                                          const CdState *st, SpecLds &sm, SpecOut &out)
+{
     const int64_t k0 = st->k;
     const int r = (int)((k0 - cp.nvec_in) & 1);
     const int nmax = (int)min((int64_t)cp.spec_len, cp.max_vec - k0);
-    // lane c = candidate c; its column of the speculated vectors stays in registers (lc), the
-    // pivot's entries come by lane shuffles, the candidates' residual columns from LDS
-    __shared__ double Rcc[CD_NCAND][CD_NCAND + 1];   // Rcc[s][c] = R[s][cand_c]
-    __shared__ double Lc[CD_SPEC_MAX][64];
-    __shared__ __align__(16) double Lt[64][CD_SPEC_MAX + 2];  // Lt[c][i] = L[k0+i][cand_c]
-    __shared__ int64_t spj[CD_SPEC_MAX];
-    __shared__ int ssj[CD_SPEC_MAX];
-    __shared__ double ssq[CD_SPEC_MAX], scm[CD_SPEC_MAX], sth[CD_SPEC_MAX];
     const int l = threadIdx.x;
     const int nc = st->ncand;
     const bool have = l < nc;
@@ -858,14 +857,14 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
 #pragma unroll
         for (int u = 0; u < 32; ++u) v[u] = b.rc[(s0 + u) * CD_NCAND + l];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) Rcc[s0 + u][l] = (have && s0 + u < nc) ? v[u] : 0.0;
+        for (int u = 0; u < 32; ++u) sm.Rcc[s0 + u][l] = (have && s0 + u < nc) ? v[u] : 0.0;
     }
     if (l < CD_SPEC_MAX) {
-        spj[l] = -1;
-        ssj[l] = 0;
-        ssq[l] = scm[l] = sth[l] = 0.0;
+        sm.spj[l] = -1;
+        sm.ssj[l] = 0;
+        sm.ssq[l] = sm.scm[l] = sm.sth[l] = 0.0;
     }
-    __syncthreads();
+    wave_lds_sync();
     double lc[CD_SPEC_MAX];
 #pragma unroll
     for (int j = 0; j < CD_SPEC_MAX; ++j) lc[j] = 0.0;
@@ -903,8 +902,8 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
             const unsigned long long bs = __ballot(have && I == pm);
             const int slot = __ffsll((long long)bs) - 1;
             const double sq = readlane_f64(sql, slot);
-            double c = Rcc[slot][l];
-            const double *lp = &Lt[slot][0];                                        // L[k0+i][p_j]
+            double c = sm.Rcc[slot][l];
+            const double *lp = &sm.Lt[slot][0];                                     // L[k0+i][p_j]
 #pragma unroll
             for (int i = 0; i < j; ++i) c = fma(-lc[i], lp[i], c);
             double lj;
@@ -919,51 +918,65 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
                 d = fma(-lj, lj, d);
             }
             lc[j] = lj;
-            Lt[l][j] = lj;
-            __syncthreads();
+            sm.Lt[l][j] = lj;
+            wave_lds_sync();
             if (l == 0) {
-                spj[j] = pm;
-                ssj[j] = slot;
-                ssq[j] = sq;
-                scm[j] = cmax;
-                sth[j] = thr;
+                sm.spj[j] = pm;
+                sm.ssj[j] = slot;
+                sm.ssq[j] = sq;
+                sm.scm[j] = cmax;
+                sm.sth[j] = thr;
             }
             nspec = j + 1;
         }
     }
-#pragma unroll
-    for (int i = 0; i < CD_SPEC_MAX; ++i) Lc[i][l] = lc[i];
-    __syncthreads();
-    // lpiv[i][j] = L[k0+i][p_j]
+    wave_lds_sync();
+    // lpiv[i][j] = L[k0+i][p_j] = Lt[slot of p_j][i]
     for (int q = l; q < CD_SPEC_MAX * CD_SPEC_MAX; q += 64) {
         const int i = q / CD_SPEC_MAX, j = q % CD_SPEC_MAX;
-        so->lpiv[i][j] = (i < j && j < nspec) ? Lc[i][ssj[j]] : 0.0;
+        out.lpiv[i][j] = (i < j && j < nspec) ? sm.Lt[sm.ssj[j]][i] : 0.0;
     }
     if (l < CD_SPEC_MAX) {
-        so->p[l] = spj[l];
-        so->slot[l] = ssj[l];
-        so->sq[l] = ssq[l];
-        so->cmax[l] = scm[l];
-        so->thr[l] = sth[l];
+        out.p[l] = sm.spj[l];
+        out.slot[l] = sm.ssj[l];
+        out.sq[l] = sm.ssq[l];
+        out.cmax[l] = sm.scm[l];
+        out.thr[l] = sm.sth[l];
     }
     if (l == 0) {
-        so->nspec = nspec;
-        so->viol = 0ull;
-        so->k0 = k0;
+        out.nspec = nspec;
+        out.pad = 0;
+        out.k0 = k0;
     }
 }
 
-// every row: the speculated vectors L[k0+j] (same operations as cd_spec_kernel), the
-// residual after each (Dbuf[j][I] = D after vector j) and the step checks
-__global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, const CdState *st,
-                                                      const double *__restrict__ R, int64_t ldr, double *__restrict__ L,
-                                                      int64_t ldl, double *__restrict__ Dbuf, SpecOut *so)
+// copy of the record without viol (which the rows update while the copy may still run)
+__device__ __forceinline__ void spec_publish(const SpecOut &ss, SpecOut *so)
 {
+    constexpr int n = (int)(sizeof(SpecOut) / 8);
+    constexpr int iv = (int)(offsetof(SpecOut, viol) / 8);
+    for (int q = threadIdx.x; q < n; q += blockDim.x)
+        if (q != iv) ((int64_t *)so)[q] = ((const int64_t *)&ss)[q];
+}
+
+__global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, const int64_t *__restrict__ cand,
+                                                     const CdState *st, SpecOut *so)
+{
+    __shared__ SpecLds sm;
     __shared__ SpecOut ss;
     if (spec_idle(st)) return;
-    for (int q = threadIdx.x; q < (int)(sizeof(SpecOut) / 8); q += 256)
-        ((int64_t *)&ss)[q] = ((const int64_t *)so)[q];
-    __syncthreads();
+    spec_body(b, cp, cand, st, sm, ss);
+    wave_lds_sync();
+    spec_publish(ss, so);
+    if (threadIdx.x == 0) so->viol = 0ull;
+}
+
+// every row of the workgroup: the speculated vectors L[k0+j] (same operations as
+// spec_body), the residual after each (Dbuf[j][I] = D after vector j) and the step checks
+__device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, const double *__restrict__ R,
+                                          int64_t ldr, double *__restrict__ L, int64_t ldl,
+                                          double *__restrict__ Dbuf, SpecOut *so, const SpecOut &ss)
+{
     const int ns = ss.nspec;
     const int64_t k0 = ss.k0;
     const int r = (int)((k0 - cp.nvec_in) & 1);
@@ -973,7 +986,7 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, con
     double d = ok ? b.D[r][I] : 0.0;
     // right-looking within the row: cv[j] holds R[I][p_j] minus the terms of the vectors made
     // so far; once L_j[I] is known every later cv[j'] takes its term at once.  Each cv[j]
-    // still receives its terms in the order i = 0, 1, ..., j-1 (the order of cd_spec_kernel),
+    // still receives its terms in the order i = 0, 1, ..., j-1 (the order of spec_body),
     // but only one fused multiply-add per step stays on the serial path.
     double cv[CD_SPEC_MAX];
 #pragma unroll
@@ -1024,6 +1037,37 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, con
         const int next = (c + 1) * CD_SPEC_CHUNK;
         if ((seen | w) & (next >= 64 ? ~0ull : ((1ull << next) - 1))) live = false;
     }
+}
+
+__global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, const CdState *st,
+                                                      const double *__restrict__ R, int64_t ldr, double *__restrict__ L,
+                                                      int64_t ldl, double *__restrict__ Dbuf, SpecOut *so)
+{
+    __shared__ SpecOut ss;
+    if (spec_idle(st)) return;
+    for (int q = threadIdx.x; q < (int)(sizeof(SpecOut) / 8); q += 256)
+        ((int64_t *)&ss)[q] = ((const int64_t *)so)[q];
+    __syncthreads();
+    rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss);
+}
+
+// Both in one launch (grids of at most CD_FUSE_MAXBLK workgroups): wave 0 of every workgroup
+// forms the speculative block itself (the same operations on the same data, so every
+// workgroup holds the same record), workgroup 0 publishes it for the commit, and all rows
+// follow.  This saves a launch and the record's round trip through memory.  The record's
+// viol was cleared by the candidate kernel, before any workgroup can publish a failure.
+__global__ __launch_bounds__(256) void cd_specrows_kernel(CdBufs b, CdParams cp, const int64_t *__restrict__ cand,
+                                                          const CdState *st, const double *__restrict__ R,
+                                                          int64_t ldr, double *__restrict__ L, int64_t ldl,
+                                                          double *__restrict__ Dbuf, SpecOut *so)
+{
+    __shared__ SpecLds sm;
+    __shared__ SpecOut ss;
+    if (spec_idle(st)) return;
+    if (threadIdx.x < 64) spec_body(b, cp, cand, st, sm, ss);
+    __syncthreads();
+    if (blockIdx.x == 0) spec_publish(ss, so);
+    rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss);
 }
 
 // empty the two super-tile key buffers that the commit and the step after it fill
@@ -1186,7 +1230,7 @@ __device__ int select_top(const unsigned long long (&u)[KPT], int want, unsigned
 // records), then the rows of those tiles; both selections are exact top-k on the IEEE
 // bits (ties at the boundary by lowest position), deterministic.
 __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams cp, int r, int sr, int64_t k,
-                                                            CdState *st, int64_t *__restrict__ cand)
+                                                            CdState *st, int64_t *__restrict__ cand, SpecOut *so)
 {
     constexpr int TK = CD_CAND_MAXTILE / CD_AUX_NT;           // tile keys per thread
     constexpr int RK = CD_NCAND * CD_TILE / CD_AUX_NT;        // row keys per thread
@@ -1201,6 +1245,7 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     const bool chained = k < 0;                  // speculative block: position from the state
     if (chained) {
         if (st->stall) return;
+        if (threadIdx.x == 0) so->viol = 0ull;   // no check of this block has failed yet
         k = st->k;
         const int64_t s = k - cp.nvec_in;
         r = (int)(s & 1);
@@ -1265,16 +1310,14 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     }
 }
 
-// Base of the candidate residual columns: R[c][I] = V[I][cand_c] (grid: row blocks x
-// candidates); the pass then subtracts the projection on the earlier vectors.
+// Base of the candidate residual columns: R[c][I] = V[I][cand_c] for candidate c, rows I of
+// x-block bx; the pass then subtracts the projection on the earlier vectors.
 template <bool DENSE>
-__global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, int64_t ldv, int64_t npairs,
-                                  const CdState *__restrict__ st, const int64_t *__restrict__ cand,
-                                  double *__restrict__ R, int64_t ldr)
+__device__ __forceinline__ void candcol_body(const PairTable &pt, const double *__restrict__ V, int64_t ldv,
+                                             int64_t npairs, const int64_t *__restrict__ cand, int c, int64_t bx,
+                                             double *__restrict__ R, int64_t ldr)
 {
-    const int c = blockIdx.y;
-    if (spec_idle(st) || c >= st->ncand) return;
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t I = bx * blockDim.x + threadIdx.x;
     if (I >= npairs) return;
     const int64_t q = cand[c];
     double v;
@@ -1286,21 +1329,54 @@ __global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, in
     R[(int64_t)c * ldr + I] = v;
 }
 
-// P[j][c] = L[j][cand_c], j < k0, c < ncand (grid-stride over the entries); rows k0 .. k0 +
-// CD_PASS_ZROWS - 1 are zero (the pass reads them for vectors past k0).  k0 < 0: the start
-// of the current speculative block.
-__global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
-                                 const int64_t *__restrict__ cand, double *__restrict__ P)
+// P[j][c] = L[j][cand_c], j < k0, c < nc (stride over the entries from block b of nb);
+// rows k0 .. k0 + CD_PASS_ZROWS - 1 are zero (the pass reads them for vectors past k0)
+__device__ __forceinline__ void gather_body(const double *__restrict__ L, int64_t ldl, int64_t k0, int nc,
+                                            const int64_t *__restrict__ cand, double *__restrict__ P, int64_t b,
+                                            int64_t nb)
 {
-    if (spec_idle(st) || st->ncand == 0) return;
-    if (k0 < 0) k0 = st->k;
-    const int nc = st->ncand;
     const int64_t ne = (k0 + CD_PASS_ZROWS) * CD_NCAND;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = b * blockDim.x + threadIdx.x; e < ne; e += nb * blockDim.x) {
         const int64_t j = e / CD_NCAND;
         const int c = (int)(e % CD_NCAND);
         P[e] = (j < k0 && c < nc) ? L[j * ldl + cand[c]] : 0.0;
     }
+}
+
+template <bool DENSE>
+__global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, int64_t ldv, int64_t npairs,
+                                  const CdState *__restrict__ st, const int64_t *__restrict__ cand,
+                                  double *__restrict__ R, int64_t ldr)
+{
+    const int c = blockIdx.y;
+    if (spec_idle(st) || c >= st->ncand) return;
+    candcol_body<DENSE>(pt, V, ldv, npairs, cand, c, blockIdx.x, R, ldr);
+}
+
+// the gather alone; k0 < 0: the start of the current speculative block
+__global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
+                                 const int64_t *__restrict__ cand, double *__restrict__ P)
+{
+    if (spec_idle(st) || st->ncand == 0) return;
+    gather_body(L, ldl, k0 < 0 ? st->k : k0, st->ncand, cand, P, blockIdx.x, gridDim.x);
+}
+
+// one launch for both, at the start of the current speculative block (they need only the
+// candidate list): block rows y < CD_NCAND evaluate candidate y's column, the last row gathers
+template <bool DENSE>
+__global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict__ V, int64_t ldv, int64_t npairs,
+                                         const CdState *__restrict__ st, const int64_t *__restrict__ cand,
+                                         double *__restrict__ R, int64_t ldr, const double *__restrict__ L,
+                                         int64_t ldl, double *__restrict__ P)
+{
+    if (spec_idle(st)) return;
+    const int nc = st->ncand;
+    if (blockIdx.y == CD_NCAND) {
+        if (nc > 0) gather_body(L, ldl, st->k, nc, cand, P, blockIdx.x, gridDim.x);
+        return;
+    }
+    if ((int)blockIdx.y >= nc) return;
+    candcol_body<DENSE>(pt, V, ldv, npairs, cand, blockIdx.y, blockIdx.x, R, ldr);
 }
 
 // R[c][I] -= sum_{j<k0} L[j][I] P[j][c] for all candidates (R holds V[I][cand_c]), one
@@ -1598,7 +1674,6 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     // a stall (a block that kept no step: a termination or a failed first check) gets one
     // per-step launch at the same start, whose candidates and residual columns still hold
     constexpr int NB = 4;
-    const unsigned ggrid = (unsigned)std::min<int64_t>(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), 256);
     while (spec_on) {
         CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
         CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1626,18 +1701,17 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         }
         for (int bi = 0; bi < NB; ++bi) {
             hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
-                               st, cand);
+                               st, cand, so);
             CDS_LAUNCHED(ctx);
-            hipLaunchKernelGGL(cd_gather_kernel, dim3(ggrid), dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                               (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
-            CDS_LAUNCHED(ctx);
-            const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCAND);
+            const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCAND + 1);
             if (dense)
-                hipLaunchKernelGGL(cd_candcol_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
-                                   (const CdState *)st, (const int64_t *)cand, Rc, ldr);
+                hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                                   npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
+                                   ldl, Pc);
             else
-                hipLaunchKernelGGL(cd_candcol_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
-                                   (const CdState *)st, (const int64_t *)cand, Rc, ldr);
+                hipLaunchKernelGGL(cd_candcol_gather_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                                   npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
+                                   ldl, Pc);
             CDS_LAUNCHED(ctx);
             CdsTimer tp;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
@@ -1649,12 +1723,20 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             if (hook && hook->block) CDS_CALL(hook->block(hook->user));
             CdsTimer tsp;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
-            hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const double *)Rc, ldr,
-                               (const int64_t *)cand, (const CdState *)st, so);
-            CDS_LAUNCHED(ctx);
-            hipLaunchKernelGGL(cd_rows_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
-                               ctx->stream, bf, cp, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf, so);
-            CDS_LAUNCHED(ctx);
+            const unsigned nrb = (unsigned)cds_ceil_div(npairs, 256);
+            if (nrb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path) {
+                hipLaunchKernelGGL(cd_specrows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp,
+                                   (const int64_t *)cand, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf,
+                                   so);
+                CDS_LAUNCHED(ctx);
+            } else {
+                hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
+                                   (const CdState *)st, so);
+                CDS_LAUNCHED(ctx);
+                hipLaunchKernelGGL(cd_rows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp, (const CdState *)st,
+                                   (const double *)Rc, ldr, L, ldl, Dbuf, so);
+                CDS_LAUNCHED(ctx);
+            }
             if (!bf.flat) {
                 hipLaunchKernelGGL(reset_super_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const CdState *)st,
                                    (const SpecOut *)so);
@@ -1692,7 +1774,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 k0 = k;
                 next_start = k + bsteps;
                 hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
-                                   st, cand);
+                                   st, cand, so);
                 CDS_LAUNCHED(ctx);
                 if (k > 0) {
                     hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div((k + CD_PASS_ZROWS) * CD_NCAND, 256)), dim3(256),
