@@ -837,56 +837,67 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // The speculative block, run by one wave (threads 0..63 of the workgroup; no workgroup
 // barrier inside): lane c = candidate c, its column of the speculated vectors in registers
-// (lc), the pivot's entries through LDS.  Writes every field of `out` (LDS) but viol.
-__device__ __forceinline__ void spec_body(const CdBufs &b, const CdParams &cp, const int64_t *__restrict__ cand,
-                                          const CdState *st, SpecLds &sm, SpecOut &out)
-{
-    const int64_t k0 = st->k;
-    const int r = (int)((k0 - cp.nvec_in) & 1);
-    const int nmax = (int)min((int64_t)cp.spec_len, cp.max_vec - k0);
-    const int l = threadIdx.x;
-    const int nc = st->ncand;
-    const bool have = l < nc;
-    const int64_t I = have ? cand[l] : -1;
-    double d = have ? b.D[r][I] : 0.0;
-    unsigned char m = have ? b.mask[r][I] : 1;
-    // the candidates' 64 x 64 residual block (compact, written by the pass), 32 loads in flight
-#pragma unroll
-    for (int s0 = 0; s0 < CD_NCAND; s0 += 32) {
-        double v[32];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) v[u] = b.rc[(s0 + u) * CD_NCAND + l];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) sm.Rcc[s0 + u][l] = (have && s0 + u < nc) ? v[u] : 0.0;
-    }
-    if (l < CD_SPEC_MAX) {
-        sm.spj[l] = -1;
-        sm.ssj[l] = 0;
-        sm.ssq[l] = sm.scm[l] = sm.sth[l] = 0.0;
-    }
-    wave_lds_sync();
+// (lc), the pivot's entries through LDS.  init() loads the block; step(j) forms step j (a
+// no-op once the block has ended), with j a compile-time constant (unrolled callers);
+// finish() writes every field of `out` but viol.
+struct SpecWave {
+    int64_t k0, I;
+    int nmax, nspec, stop_at;
+    bool have, alive;
+    double d, dnc;
+    unsigned char m;
     double lc[CD_SPEC_MAX];
+
+    __device__ __forceinline__ void init(const CdBufs &b, const CdParams &cp, const int64_t *__restrict__ cand,
+                                         const CdState *st, SpecLds &sm)
+    {
+        k0 = st->k;
+        const int r = (int)((k0 - cp.nvec_in) & 1);
+        nmax = (int)min((int64_t)cp.spec_len, cp.max_vec - k0);
+        const int l = threadIdx.x;
+        const int nc = st->ncand;
+        have = l < nc;
+        I = have ? cand[l] : -1;
+        d = have ? b.D[r][I] : 0.0;
+        m = have ? b.mask[r][I] : 1;
+        // the candidates' 64 x 64 residual block (compact, written by the pass), 32 loads in flight
 #pragma unroll
-    for (int j = 0; j < CD_SPEC_MAX; ++j) lc[j] = 0.0;
-    int nspec = 0;
-    bool alive = true;                                    // uniform over the wave
-    // steps whose tie threshold stays above every non-candidate residual stand for sure
-    // (those residuals only decrease); speculation goes CD_SPEC_MARGIN steps past them
-    const double dnc = st->dnc;
-    int stop_at = nmax;
+        for (int s0 = 0; s0 < CD_NCAND; s0 += 32) {
+            double v[32];
 #pragma unroll
-    for (int j = 0; j < CD_SPEC_MAX; ++j) {
+            for (int u = 0; u < 32; ++u) v[u] = b.rc[(s0 + u) * CD_NCAND + l];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) sm.Rcc[s0 + u][l] = (have && s0 + u < nc) ? v[u] : 0.0;
+        }
+        if (l < CD_SPEC_MAX) {
+            sm.spj[l] = -1;
+            sm.ssj[l] = 0;
+            sm.ssq[l] = sm.scm[l] = sm.sth[l] = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < CD_SPEC_MAX; ++j) lc[j] = 0.0;
+        nspec = 0;
+        alive = true;                                     // uniform over the wave
+        // steps whose tie threshold stays above every non-candidate residual stand for sure
+        // (those residuals only decrease); speculation goes CD_SPEC_MARGIN steps past them
+        dnc = st->dnc;
+        stop_at = nmax;
+    }
+
+    __device__ __forceinline__ void step(int j, const CdParams &cp, SpecLds &sm)
+    {
+        const int l = threadIdx.x;
         if (j >= nmax) alive = false;
-        if (!alive) continue;
+        if (!alive) return;
         const bool elig = have && m == 0;
         const double sql = sqrt(d);                                 // off the serial path
         const double cmax = okey_max(wave_max_key(elig ? okey(d) : 0ull));   // as fmax, on integer keys
         if (cmax == -INFINITY || cmax <= cp.delta) alive = false;   // termination: per-step path
-        if (!alive) continue;
+        if (!alive) return;
         const double thr = cmax - tie_window(cmax, cp.tau);
         if (!(thr > dnc) && j + CD_SPEC_MARGIN < stop_at) stop_at = j + CD_SPEC_MARGIN;
         if (j >= stop_at) alive = false;
-        if (!alive) continue;
+        if (!alive) return;
         // pivot: the lowest row index within the tie window; usually one lane is in it
         const unsigned long long win = __ballot(elig && d >= thr);
         int64_t pm;
@@ -898,56 +909,78 @@ __device__ __forceinline__ void spec_body(const CdBufs &b, const CdParams &cp, c
             pm = wave_min_i64_dpp((elig && d >= thr) ? I : INT64_MAX);
         }
         if (win == 0 || pm == INT64_MAX) alive = false;             // non-finite residuals
-        if (alive) {
-            const unsigned long long bs = __ballot(have && I == pm);
-            const int slot = __ffsll((long long)bs) - 1;
-            const double sq = readlane_f64(sql, slot);
-            double c = sm.Rcc[slot][l];
-            const double *lp = &sm.Lt[slot][0];                                     // L[k0+i][p_j]
+        if (!alive) return;
+        const unsigned long long bs = __ballot(have && I == pm);
+        const int slot = __ffsll((long long)bs) - 1;
+        const double sq = readlane_f64(sql, slot);
+        double c = sm.Rcc[slot][l];
+        const double *lp = &sm.Lt[slot][0];                                         // L[k0+i][p_j]
 #pragma unroll
-            for (int i = 0; i < j; ++i) c = fma(-lc[i], lp[i], c);
-            double lj;
-            if (m == 1) {
-                lj = 0.0;
-            } else if (l == slot) {
-                lj = sq;
-                d = 0.0;
-                m = 1;
-            } else {
-                lj = c / sq;
-                d = fma(-lj, lj, d);
-            }
-            lc[j] = lj;
-            sm.Lt[l][j] = lj;
-            wave_lds_sync();
-            if (l == 0) {
-                sm.spj[j] = pm;
-                sm.ssj[j] = slot;
-                sm.ssq[j] = sq;
-                sm.scm[j] = cmax;
-                sm.sth[j] = thr;
-            }
-            nspec = j + 1;
+        for (int i = 0; i < j; ++i) c = fma(-lc[i], lp[i], c);
+        double lj;
+        if (m == 1) {
+            lj = 0.0;
+        } else if (l == slot) {
+            lj = sq;
+            d = 0.0;
+            m = 1;
+        } else {
+            lj = c / sq;
+            d = fma(-lj, lj, d);
+        }
+        lc[j] = lj;
+        sm.Lt[l][j] = lj;
+        wave_lds_sync();
+        if (l == 0) {
+            sm.ssj[j] = slot;
+            sm.ssq[j] = sq;
+            sm.scm[j] = cmax;
+            sm.sth[j] = thr;
+            sm.spj[j] = pm;                   // step j is formed
+        }
+        nspec = j + 1;
+    }
+
+    // the per-step records (for the commit)
+    __device__ __forceinline__ void records(const SpecLds &sm, SpecOut &out) const
+    {
+        const int l = threadIdx.x;
+        if (l < CD_SPEC_MAX) {
+            out.p[l] = sm.spj[l];
+            out.slot[l] = sm.ssj[l];
+            out.sq[l] = sm.ssq[l];
+            out.cmax[l] = sm.scm[l];
+            out.thr[l] = sm.sth[l];
+        }
+        if (l == 0) {
+            out.nspec = nspec;
+            out.pad = 0;
+            out.k0 = k0;
         }
     }
+
+    // the records and lpiv[i][j] = L[k0+i][p_j] = Lt[slot of p_j][i] (for the row updates)
+    __device__ __forceinline__ void finish(const SpecLds &sm, SpecOut &out) const
+    {
+        const int l = threadIdx.x;
+        for (int q = l; q < CD_SPEC_MAX * CD_SPEC_MAX; q += 64) {
+            const int i = q / CD_SPEC_MAX, j = q % CD_SPEC_MAX;
+            out.lpiv[i][j] = (i < j && j < nspec) ? sm.Lt[sm.ssj[j]][i] : 0.0;
+        }
+        records(sm, out);
+    }
+};
+
+__device__ __forceinline__ void spec_body(const CdBufs &b, const CdParams &cp, const int64_t *__restrict__ cand,
+                                          const CdState *st, SpecLds &sm, SpecOut &out)
+{
+    SpecWave sw;
+    sw.init(b, cp, cand, st, sm);
     wave_lds_sync();
-    // lpiv[i][j] = L[k0+i][p_j] = Lt[slot of p_j][i]
-    for (int q = l; q < CD_SPEC_MAX * CD_SPEC_MAX; q += 64) {
-        const int i = q / CD_SPEC_MAX, j = q % CD_SPEC_MAX;
-        out.lpiv[i][j] = (i < j && j < nspec) ? sm.Lt[sm.ssj[j]][i] : 0.0;
-    }
-    if (l < CD_SPEC_MAX) {
-        out.p[l] = sm.spj[l];
-        out.slot[l] = sm.ssj[l];
-        out.sq[l] = sm.ssq[l];
-        out.cmax[l] = sm.scm[l];
-        out.thr[l] = sm.sth[l];
-    }
-    if (l == 0) {
-        out.nspec = nspec;
-        out.pad = 0;
-        out.k0 = k0;
-    }
+#pragma unroll
+    for (int j = 0; j < CD_SPEC_MAX; ++j) sw.step(j, cp, sm);
+    wave_lds_sync();
+    sw.finish(sm, out);
 }
 
 // copy of the record without viol (which the rows update while the copy may still run)
@@ -1051,23 +1084,114 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, con
     rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss);
 }
 
-// Both in one launch (grids of at most CD_FUSE_MAXBLK workgroups): wave 0 of every workgroup
-// forms the speculative block itself (the same operations on the same data, so every
-// workgroup holds the same record), workgroup 0 publishes it for the commit, and all rows
-// follow.  This saves a launch and the record's round trip through memory.  The record's
-// viol was cleared by the candidate kernel, before any workgroup can publish a failure.
-__global__ __launch_bounds__(256) void cd_specrows_kernel(CdBufs b, CdParams cp, const int64_t *__restrict__ cand,
-                                                          const CdState *st, const double *__restrict__ R,
-                                                          int64_t ldr, double *__restrict__ L, int64_t ldl,
-                                                          double *__restrict__ Dbuf, SpecOut *so)
+// One row of the lockstep kernel, left-looking: step j forms L_j[I] = (R[I][p_j] - sum_{i<j}
+// L_i[I] L_i[p_j]) / sqrt(D_j), the terms in the order i = 0, 1, ... with the same fused
+// multiply-adds as SpecWave::step, so the candidates' rows agree with the speculative wave bit
+// for bit; D_j[I] and the checks of step j as the right-looking row update.
+struct RowWave {
+    int64_t I;
+    bool ok;
+    unsigned char m;
+    double d;
+    unsigned long long viol;
+    double lr[CD_SPEC_MAX];   // L_i[I], i < j
+
+    __device__ __forceinline__ void step(int j, const CdParams &cp, const SpecLds &sm, double rpj, double *__restrict__ L,
+                                         int64_t ldl, int64_t k0, double *__restrict__ Dbuf)
+    {
+        const int64_t pj = sm.spj[j];
+        const int slot = sm.ssj[j];
+        const double sq = sm.ssq[j];
+        if (m == 0 && (d > sm.scm[j] || (d >= sm.sth[j] && I < pj))) viol |= 1ull << j;
+        if (m != 1 && d < -cp.psd_tol) viol |= 1ull << j;         // NOT_PSD is the per-step path's call
+        double lj;
+        if (m == 1) {
+            lj = 0.0;
+        } else if (I == pj) {
+            lj = sq;
+            d = 0.0;
+            m = 1;
+        } else {
+            double c = rpj;
+            const double *lp = &sm.Lt[slot][0];
+#pragma unroll
+            for (int i = 0; i < j; ++i) c = fma(-lr[i], lp[i], c);
+            lj = c / sq;
+            d = fma(-lj, lj, d);
+        }
+        lr[j] = lj;
+        if (ok) {
+            L[(k0 + j) * ldl + I] = lj;
+            Dbuf[(int64_t)j * cp.npairs + I] = d;
+        }
+    }
+};
+
+// The speculative block and the row updates in lockstep (grids of at most CD_FUSE_MAXBLK
+// workgroups of CD_LS_ROWS rows): wave 0 of every workgroup forms the speculative block (the
+// same operations on the same data, so every workgroup holds the same record), and the other
+// waves update the workgroup's rows one step behind it, left-looking, so their work runs while
+// wave 0 forms the next step; a workgroup barrier per step hands each step over.  The rows'
+// candidate columns are staged in LDS first (R[I][p_j] is known only when p_j is).  Workgroup 0
+// publishes the records for the commit; the candidate kernel has cleared the failure mask.
+constexpr int CD_LS_ROWS = 128;
+
+struct LockLds {
+    SpecLds sp;
+    double Rs[CD_NCAND][CD_LS_ROWS];   // Rs[c][t] = R[c][row t of the workgroup]
+};
+
+__global__ __launch_bounds__(64 + CD_LS_ROWS, 1) void cd_lockstep_kernel(CdBufs b, CdParams cp,
+                                                                       const int64_t *__restrict__ cand,
+                                                                       const CdState *st, const double *__restrict__ R,
+                                                                       int64_t ldr, double *__restrict__ L, int64_t ldl,
+                                                                       double *__restrict__ Dbuf, SpecOut *so)
 {
-    __shared__ SpecLds sm;
-    __shared__ SpecOut ss;
+    __shared__ LockLds sh;
     if (spec_idle(st)) return;
-    if (threadIdx.x < 64) spec_body(b, cp, cand, st, sm, ss);
+    const bool spec = threadIdx.x < 64;
+    const int t = (int)threadIdx.x - 64;                 // row of the workgroup (row waves)
+    SpecWave sw;
+    RowWave rw;
+    int64_t k0 = 0;
+    if (spec) {
+        sw.init(b, cp, cand, st, sh.sp);
+    } else {
+        k0 = st->k;
+        const int r = (int)((k0 - cp.nvec_in) & 1);
+        const int nc = st->ncand;
+        rw.I = (int64_t)blockIdx.x * CD_LS_ROWS + t;
+        rw.ok = rw.I < cp.npairs;
+        rw.m = rw.ok ? b.mask[r][rw.I] : 1;
+        rw.d = rw.ok ? b.D[r][rw.I] : 0.0;
+        rw.viol = 0ull;
+#pragma unroll
+        for (int j = 0; j < CD_SPEC_MAX; ++j) rw.lr[j] = 0.0;
+#pragma unroll 16
+        for (int c = 0; c < CD_NCAND; ++c) sh.Rs[c][t] = (rw.ok && c < nc) ? R[(int64_t)c * ldr + rw.I] : 0.0;
+    }
     __syncthreads();
-    if (blockIdx.x == 0) spec_publish(ss, so);
-    rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss);
+    // iteration j: wave 0 forms step j, the row waves make step j - 1; once a step is missing
+    // (read after the barrier, so the same in every wave) the rest is skipped
+    bool ended = false;
+#pragma clang loop unroll(full)
+    for (int j = 0; j <= CD_SPEC_MAX; ++j) {
+        if (ended) continue;
+        if (spec) {
+            if (j < CD_SPEC_MAX) sw.step(j, cp, sh.sp);
+        } else if (j > 0) {
+            rw.step(j - 1, cp, sh.sp, sh.Rs[sh.sp.ssj[j - 1]][t], L, ldl, k0, Dbuf);
+        }
+        __syncthreads();
+        ended = j == CD_SPEC_MAX || sh.sp.spj[j] < 0;
+    }
+    if (!spec) {
+        unsigned long long w = rw.viol;
+        for (int o = 32; o > 0; o >>= 1) w |= (unsigned long long)__shfl_xor((long long)w, o, 64);
+        if (w && (threadIdx.x & 63) == 0) atomicOr((unsigned long long *)&so->viol, w);
+    } else if (blockIdx.x == 0) {
+        sw.records(sh.sp, *so);
+    }
 }
 
 // empty the two super-tile key buffers that the commit and the step after it fill
@@ -1724,8 +1848,9 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             CdsTimer tsp;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
             const unsigned nrb = (unsigned)cds_ceil_div(npairs, 256);
-            if (nrb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path) {
-                hipLaunchKernelGGL(cd_specrows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp,
+            const unsigned nlb = (unsigned)cds_ceil_div(npairs, CD_LS_ROWS);
+            if (nlb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path) {
+                hipLaunchKernelGGL(cd_lockstep_kernel, dim3(nlb), dim3(64 + CD_LS_ROWS), 0, ctx->stream, bf, cp,
                                    (const int64_t *)cand, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf,
                                    so);
                 CDS_LAUNCHED(ctx);
