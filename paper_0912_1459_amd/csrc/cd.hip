@@ -861,13 +861,12 @@ struct SpecWave {
         d = have ? b.D[r][I] : 0.0;
         m = have ? b.mask[r][I] : 1;
         // the candidates' 64 x 64 residual block (compact, written by the pass), 32 loads in flight
+        {
+            double v[CD_NCAND];
 #pragma unroll
-        for (int s0 = 0; s0 < CD_NCAND; s0 += 32) {
-            double v[32];
+            for (int u = 0; u < CD_NCAND; ++u) v[u] = b.rc[u * CD_NCAND + l];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) v[u] = b.rc[(s0 + u) * CD_NCAND + l];
-#pragma unroll
-            for (int u = 0; u < 32; ++u) sm.Rcc[s0 + u][l] = (have && s0 + u < nc) ? v[u] : 0.0;
+            for (int u = 0; u < CD_NCAND; ++u) sm.Rcc[u][l] = (have && u < nc) ? v[u] : 0.0;
         }
         if (l < CD_SPEC_MAX) {
             sm.spj[l] = -1;
@@ -1167,8 +1166,12 @@ __global__ __launch_bounds__(64 + CD_LS_ROWS, 1) void cd_lockstep_kernel(CdBufs 
         rw.viol = 0ull;
 #pragma unroll
         for (int j = 0; j < CD_SPEC_MAX; ++j) rw.lr[j] = 0.0;
-#pragma unroll 16
-        for (int c = 0; c < CD_NCAND; ++c) sh.Rs[c][t] = (rw.ok && c < nc) ? R[(int64_t)c * ldr + rw.I] : 0.0;
+        // all 64 loads in flight, then the LDS stores
+        double v[CD_NCAND];
+#pragma unroll
+        for (int c = 0; c < CD_NCAND; ++c) v[c] = R[(int64_t)c * ldr + (rw.ok ? rw.I : 0)];
+#pragma unroll
+        for (int c = 0; c < CD_NCAND; ++c) sh.Rs[c][t] = (rw.ok && c < nc) ? v[c] : 0.0;
     }
     __syncthreads();
     // iteration j: wave 0 forms step j, the row waves make step j - 1; once a step is missing
