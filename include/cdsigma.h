@@ -142,10 +142,10 @@ int cds_set_cd_speculate(cds_ctx *ctx, int32_t on);
  * large pair counts at any size (pivot search through 64 super-tile maxima,
  * then tiles, then rows, instead of one sweep over all 64-row tile records; four
  * tiles per step block instead of one; the speculative block formed once and
- * then read by the row updates, instead of by every row workgroup).  Automatic:
- * the sweep up to 1024 tiles, one tile per block up to 1280 tiles, the
- * speculative block in every row workgroup up to 256 of them.  Results are the
- * same either way. */
+ * then read by the row updates, instead of by every workgroup of 128 rows with
+ * the rows one step behind it).  Automatic: the sweep up to 1024 tiles, one
+ * tile per block up to 1280 tiles, the speculative block in every row
+ * workgroup up to 256 of them.  Results are the same either way. */
 int cds_set_cd_large_path(cds_ctx *ctx, int32_t on);
 /* Working precision of cds_transform for FP32 and BF16X3 outputs: 0 (default)
  * runs its GEMMs in the output precision; 1 runs them in FP64 and rounds only
