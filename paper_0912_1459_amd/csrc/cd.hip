@@ -1077,8 +1077,19 @@ __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, con
 {
     __shared__ SpecOut ss;
     if (spec_idle(st)) return;
-    for (int q = threadIdx.x; q < (int)(sizeof(SpecOut) / 8); q += 256)
-        ((int64_t *)&ss)[q] = ((const int64_t *)so)[q];
+    // the record into LDS, every load in flight before the first store
+    constexpr int NW = (int)(sizeof(SpecOut) / 8), NQ = (NW + 255) / 256;
+    int64_t v[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = (int)threadIdx.x + 256 * i;
+        v[i] = q < NW ? ((const int64_t *)so)[q] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = (int)threadIdx.x + 256 * i;
+        if (q < NW) ((int64_t *)&ss)[q] = v[i];
+    }
     __syncthreads();
     rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss);
 }
@@ -1226,16 +1237,19 @@ __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, c
         if (blockIdx.x == 0 && threadIdx.x == 0) st->stall = 1;
         return;
     }
+    __shared__ int64_t sp[CD_SPEC_MAX];
     const int64_t k0 = so->k0, s = k0 - cp.nvec_in;
     const int r = (int)(s & 1), w = (int)((s + nc) & 1), sw = (int)((s + nc) % 3);
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool ok = I < cp.npairs;
     unsigned char m = ok ? b.mask[r][I] : 1;
-    double d = 0.0;
+    double d = ok ? Dbuf[(int64_t)(nc - 1) * cp.npairs + I] : 0.0;
+    // the block's pivots, loaded once (a loop of loads would wait on each)
+    if ((int)threadIdx.x < CD_SPEC_MAX) sp[threadIdx.x] = (int)threadIdx.x < nc ? so->p[threadIdx.x] : -1;
+    __syncthreads();
     if (ok) {
-        d = Dbuf[(int64_t)(nc - 1) * cp.npairs + I];
         for (int j = 0; j < nc; ++j)
-            if (I == so->p[j]) m = 1;
+            if (I == sp[j]) m = 1;
         b.D[w][I] = d;
         b.mask[w][I] = m;
     }
@@ -1489,7 +1503,9 @@ __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int6
 }
 
 // one launch for both, at the start of the current speculative block (they need only the
-// candidate list): block rows y < CD_NCAND evaluate candidate y's column, the last row gathers
+// candidate list): block rows y < CD_NCAND evaluate candidate y's column, the rows after them
+// gather (enough of them that each thread gathers at most one entry: a strided loop waits on
+// each of its loads)
 template <bool DENSE>
 __global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict__ V, int64_t ldv, int64_t npairs,
                                          const CdState *__restrict__ st, const int64_t *__restrict__ cand,
@@ -1498,8 +1514,10 @@ __global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict_
 {
     if (spec_idle(st)) return;
     const int nc = st->ncand;
-    if (blockIdx.y == CD_NCAND) {
-        if (nc > 0) gather_body(L, ldl, st->k, nc, cand, P, blockIdx.x, gridDim.x);
+    if ((int)blockIdx.y >= CD_NCAND) {          // gather: rows CD_NCAND.. of the grid, one entry per thread
+        const int64_t gb = (int64_t)(blockIdx.y - CD_NCAND) * gridDim.x + blockIdx.x;
+        const int64_t nb = (int64_t)(gridDim.y - CD_NCAND) * gridDim.x;
+        if (nc > 0) gather_body(L, ldl, st->k, nc, cand, P, gb, nb);
         return;
     }
     if ((int)blockIdx.y >= nc) return;
@@ -1830,7 +1848,9 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
                                st, cand, so);
             CDS_LAUNCHED(ctx);
-            const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCAND + 1);
+            const int64_t cgx = cds_ceil_div(npairs, 256);
+            const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
+            const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCAND + gy));
             if (dense)
                 hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
                                    npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
