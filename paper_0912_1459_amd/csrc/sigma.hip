@@ -110,20 +110,34 @@ __global__ __launch_bounds__(EP_NT) void pair_a_kernel(EpArgs e)
     const int nb = (nocc + 31) / 32;
     for (int IB = 0; IB < nb; ++IB)
         for (int JB = IB; JB < nb; ++JB) {
-            __syncthreads();
-            for (int q = threadIdx.x; q < 1024; q += EP_NT) {
+            // both tiles: every load in flight before the LDS stores (a loop of loads would
+            // wait on each)
+            constexpr int QN = 1024 / EP_NT;
+            double v1[QN], v2[QN];
+#pragma unroll
+            for (int u = 0; u < QN; ++u) {
+                const int q = threadIdx.x + EP_NT * u;
                 const int r = q >> 5, c = q & 31;
                 const int i1 = IB * 32 + r, j1 = JB * 32 + c;   // t1[r][c] = X[i1][j1]
                 const int i2 = JB * 32 + r, j2 = IB * 32 + c;   // t2[r][c] = X[i2][j2]
-                t1[r][c] = (i1 < nocc && j1 < nocc) ? ld<GT>(e.G, gbase + (int64_t)i1 * e.nvo + j1) : 0.0;
-                t2[r][c] = (i2 < nocc && j2 < nocc) ? ld<GT>(e.G, gbase + (int64_t)i2 * e.nvo + j2) : 0.0;
+                v1[u] = (i1 < nocc && j1 < nocc) ? ld<GT>(e.G, gbase + (int64_t)i1 * e.nvo + j1) : 0.0;
+                v2[u] = (i2 < nocc && j2 < nocc) ? ld<GT>(e.G, gbase + (int64_t)i2 * e.nvo + j2) : 0.0;
             }
             __syncthreads();
+#pragma unroll
+            for (int u = 0; u < QN; ++u) {
+                const int q = threadIdx.x + EP_NT * u;
+                t1[q >> 5][q & 31] = v1[u];
+                t2[q >> 5][q & 31] = v2[u];
+            }
+            __syncthreads();
+            // element (i, j) = (IB*32 + ci, JB*32 + cj), ci fastest over the threads: the
+            // residues of consecutive i are consecutive in the packed layout
             for (int q = threadIdx.x; q < 1024; q += EP_NT) {
-                const int r = q >> 5, c = q & 31;
-                const int i = IB * 32 + r, j = JB * 32 + c;
-                if (i >= nocc || j >= nocc || (IB == JB && r > c)) continue;
-                const double x = t1[r][c], xt = t2[c][r];
+                const int cj = q >> 5, ci = q & 31;
+                const int i = IB * 32 + ci, j = JB * 32 + cj;
+                if (i >= nocc || j >= nocc || (IB == JB && ci > cj)) continue;
+                const double x = t1[ci][cj], xt = t2[cj][ci];
                 const double R = (i == j) ? x * x : 2.0 * (x * x + xt * xt - x * xt);
                 if constexpr (MODE == EP_SIGMA) {
                     const double dd = ea - eo[i] - eo[j];
@@ -180,23 +194,39 @@ __global__ __launch_bounds__(EP_NT) void pair_b_kernel(EpArgs e)
         const int64_t nitem = (int64_t)(nvirt - a) * nocc;
         const int64_t roff = (int64_t)s * e.nres + e.offB +
                              (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
-        for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
-            const int bo = (int)(q / nocc), i = (int)(q - (int64_t)bo * nocc);
-            const int b = a + bo;
-            const double y = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
-            const double yt = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
-            const double R = (bo == 0) ? y * y : 2.0 * (y * y + yt * yt - y * yt);
-            if constexpr (MODE == EP_SIGMA) {
-                const double dd = eo[i] - ea - ev[b];
+        // four items per thread and round: their loads are all in flight before the first use
+        constexpr int UB = 4;
+        for (int64_t q0 = threadIdx.x; q0 < nitem; q0 += (int64_t)UB * EP_NT) {
+            double yv[UB], ytv[UB];
 #pragma unroll
-                for (int t = 0; t < TT; ++t) {
-                    const double id = 1.0 / (w[t] + dd);
-                    const double ri = R * id;
-                    acc[t][0] += ri;
-                    acc[t][1] -= ri * id;
+            for (int u = 0; u < UB; ++u) {
+                const int64_t q = q0 + (int64_t)u * EP_NT;
+                const int64_t qc = q < nitem ? q : nitem - 1;
+                const int bo = (int)(qc / nocc), i = (int)(qc - (int64_t)bo * nocc);
+                const int b = a + bo;
+                yv[u] = ld<GT>(e.G, base_a + (int64_t)b * nocc + i);
+                ytv[u] = ld<GT>(e.G, gs0 + (int64_t)(nocc + b) * e.nvo + (int64_t)a * nocc + i);
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int64_t q = q0 + (int64_t)u * EP_NT;
+                if (q >= nitem) break;
+                const int bo = (int)(q / nocc), i = (int)(q - (int64_t)bo * nocc);
+                const int b = a + bo;
+                const double y = yv[u], yt = ytv[u];
+                const double R = (bo == 0) ? y * y : 2.0 * (y * y + yt * yt - y * yt);
+                if constexpr (MODE == EP_SIGMA) {
+                    const double dd = eo[i] - ea - ev[b];
+#pragma unroll
+                    for (int t = 0; t < TT; ++t) {
+                        const double id = 1.0 / (w[t] + dd);
+                        const double ri = R * id;
+                        acc[t][0] += ri;
+                        acc[t][1] -= ri * id;
+                    }
+                } else {
+                    ((GT *)e.R)[roff + q] = (GT)R;
                 }
-            } else {
-                ((GT *)e.R)[roff + q] = (GT)R;
             }
         }
     }
@@ -312,6 +342,7 @@ __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__res
     const double *ev = e.eps + nocc;
     const double w = e.omega[s];
     const RT *R = (const RT *)e.R + (int64_t)s * e.nres;
+    constexpr int SU = 4;
     double s0 = 0.0, s1 = 0.0;
     const int blk = blockIdx.x;
     if (blk < nvirt) {
@@ -319,16 +350,28 @@ __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__res
         const int npair = nocc * (nocc + 1) / 2;
         const RT *Ra = R + (int64_t)a * npair;
         const double ea = ev[a];
-        for (int p = threadIdx.x; p < npair; p += EP_NT) {
-            // p = j(j+1)/2 + i, i <= j (float square root, then exact integer correction)
-            int j = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
-            if (j * (j + 1) / 2 > p) --j;
-            if ((j + 1) * (j + 2) / 2 <= p) ++j;
-            const int i = p - j * (j + 1) / 2;
-            const double id = 1.0 / (w + ea - eo[i] - eo[j]);
-            const double ri = (double)Ra[p] * id;
-            s0 += ri;
-            s1 -= ri * id;
+        // SU residues per thread and round, loaded before the first use (same order of terms)
+        for (int p0 = threadIdx.x; p0 < npair; p0 += SU * EP_NT) {
+            double rv[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int p = p0 + u * EP_NT;
+                rv[u] = (double)Ra[p < npair ? p : npair - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int p = p0 + u * EP_NT;
+                if (p >= npair) break;
+                // p = j(j+1)/2 + i, i <= j (float square root, then exact integer correction)
+                int j = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+                if (j * (j + 1) / 2 > p) --j;
+                if ((j + 1) * (j + 2) / 2 <= p) ++j;
+                const int i = p - j * (j + 1) / 2;
+                const double id = 1.0 / (w + ea - eo[i] - eo[j]);
+                const double ri = rv[u] * id;
+                s0 += ri;
+                s1 -= ri * id;
+            }
         }
     } else {
         const int pb = blk - nvirt;
@@ -338,12 +381,23 @@ __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__res
             const int64_t nitem = (int64_t)(nvirt - a) * nocc;
             const RT *Rb = R + e.offB + (int64_t)nocc * ((int64_t)a * nvirt - (int64_t)a * (a - 1) / 2);
             const double ea = ev[a];
-            for (int64_t q = threadIdx.x; q < nitem; q += EP_NT) {
-                const int bo = (int)(q / nocc), i = (int)(q - (int64_t)bo * nocc);
-                const double id = 1.0 / (w + eo[i] - ea - ev[a + bo]);
-                const double ri = (double)Rb[q] * id;
-                s0 += ri;
-                s1 -= ri * id;
+            for (int64_t q0 = threadIdx.x; q0 < nitem; q0 += (int64_t)SU * EP_NT) {
+                double rv[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int64_t q = q0 + (int64_t)u * EP_NT;
+                    rv[u] = (double)Rb[q < nitem ? q : nitem - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int64_t q = q0 + (int64_t)u * EP_NT;
+                    if (q >= nitem) break;
+                    const int bo = (int)(q / nocc), i = (int)(q - (int64_t)bo * nocc);
+                    const double id = 1.0 / (w + eo[i] - ea - ev[a + bo]);
+                    const double ri = rv[u] * id;
+                    s0 += ri;
+                    s1 -= ri * id;
+                }
             }
         }
     }
@@ -363,8 +417,17 @@ __global__ void reduce_partials_kernel(const double *__restrict__ part, int nsc,
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nsc * T * 2) return;
     int s = idx / (T * 2), tc = idx - s * T * 2;
+    // in block order, eight loads in flight at a time
+    constexpr int U = 8;
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[((int64_t)s * nblk + b) * T * 2 + tc];
+    for (int b0 = 0; b0 < nblk; b0 += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = b0 + u < nblk ? part[((int64_t)s * nblk + b0 + u) * T * 2 + tc] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b0 + u < nblk) acc += v[u];
+    }
     out[idx] = acc;
 }
 
