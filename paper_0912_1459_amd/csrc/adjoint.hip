@@ -46,28 +46,45 @@ __global__ void zero_cols_kernel(T *__restrict__ B, int64_t nrows, int64_t ldk, 
 }
 
 // eps_bar[r] = sum over targets and blocks of the energy partials, + P*omega_bar on e_q
-__global__ void eps_bar_kernel(const double *__restrict__ epsA, const double *__restrict__ epsB, int nsel,
-                               int nocc, int nvirt, const int32_t *__restrict__ sel,
-                               const double *__restrict__ gscale, double *__restrict__ out)
+// eps_bar[r]: one workgroup per orbital r; the threads take the (target, virtual) partials in a
+// fixed stride, four loads in flight at a time, and the workgroup sums them in a fixed order
+__global__ __launch_bounds__(256) void eps_bar_kernel(const double *__restrict__ epsA, const double *__restrict__ epsB,
+                                                      int nsel, int nocc, int nvirt, const int32_t *__restrict__ sel,
+                                                      const double *__restrict__ gscale, double *__restrict__ out)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    int nmo = nocc + nvirt;
-    if (r >= nmo) return;
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    const int64_t per = (int64_t)nvirt * (nocc + 1);
     double acc = 0.0;
-    for (int s = 0; s < nsel; ++s) {
-        const double *A = epsA + (int64_t)s * nvirt * (nocc + 1);
-        const double *B = epsB + (int64_t)s * nvirt * (nocc + 1);
-        if (r < nocc) {
-            for (int a = 0; a < nvirt; ++a) acc += A[(int64_t)a * (nocc + 1) + r];
-            for (int a = 0; a < nvirt; ++a) acc += B[(int64_t)a * (nocc + 1) + r];
-        } else {
-            int a = r - nocc;
-            acc += A[(int64_t)a * (nocc + 1) + nocc];
-            acc += B[(int64_t)a * (nocc + 1) + nocc];
+    if (r < nocc) {
+        const int64_t n = (int64_t)nsel * nvirt;                 // (target, virtual) pairs
+        constexpr int U = 4;
+        for (int64_t q0 = threadIdx.x; q0 < n; q0 += (int64_t)U * 256) {
+            double va[U], vb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = q0 + (int64_t)u * 256 < n ? q0 + (int64_t)u * 256 : n - 1;
+                const int64_t s = q / nvirt, a = q - s * nvirt;
+                const int64_t off = s * per + a * (nocc + 1) + r;
+                va[u] = epsA[off];
+                vb[u] = epsB[off];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (q0 + (int64_t)u * 256 < n) acc += va[u] + vb[u];
         }
-        if (sel[s] == r) acc += gscale[s];
+    } else {
+        for (int s = threadIdx.x; s < nsel; s += 256) {
+            const int64_t off = (int64_t)s * per + (int64_t)(r - nocc) * (nocc + 1) + nocc;
+            acc += epsA[off] + epsB[off];
+        }
     }
-    out[r] = acc;
+    for (int s = threadIdx.x; s < nsel; s += 256)
+        if (sel[s] == r) acc += gscale[s];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[r] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 // S[kb][p][q] = Bbar^K[p][q] + Bbar^K[q][p] (FP64), Bbar scattered from the sel and vo blocks
@@ -188,6 +205,14 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
     void *G, *W;
     CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * per, &G));
     CDS_CALL(cds_ws(ctx, WS_AD_G, (size_t)csz * per, &W));
+    // K-contiguous copies of the operands the two products read across K (the GEMM's fast path
+    // loads rows along K): Bvo^T [nvec][nvo], then per chunk W^T [nvo][nsc*nmo] and the chunk's
+    // Bsel^T [nvec][nsc*nmo]
+    void *BvT, *WT, *BsT;
+    CDS_CALL(cds_ws(ctx, WS_AD_T1, (size_t)nvec * nvo * es, &BvT));
+    CDS_CALL(cds_ws(ctx, WS_AD_T2, (size_t)csz * per, &WT));
+    CDS_CALL(cds_ws(ctx, WS_AD_T3, (size_t)nvec * csz * nmo * es, &BsT));
+    CDS_CALL(cds_transpose(ctx, (int)es, nvo, nvec, Bv, ldk, BvT, nvo));
     for (int s0 = 0; s0 < nsel; s0 += csz) {
         const int nsc = std::min(csz, nsel - s0);
         CDS_CALL(cds_contract_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, s0, nsc, G));
@@ -198,15 +223,19 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
         GemmDesc d1 = {};
         d1.M = (int64_t)nsc * nmo; d1.N = nvec; d1.K = nvo; d1.batch = 1;
         d1.A = W; d1.sAm = nvo; d1.sAk = 1;
-        d1.B = Bv; d1.sBk = ldk; d1.sBn = 1;
+        d1.B = BvT; d1.sBk = 1; d1.sBn = nvo;
         d1.C = (unsigned char *)Bsel_bar + (size_t)s0 * nmo * ldk * es; d1.sCm = ldk; d1.sCn = 1;
         d1.alpha = 1.0; d1.beta = 0.0;
         CDS_CALL(cds_gemm_ex(ctx, gprec, d1, nullptr, nullptr));
         // Bvo_bar += W^T Bsel[s0..] : nvo x nvec, reduction over nsc*nmo
+        const int64_t kc = (int64_t)nsc * nmo;
+        CDS_CALL(cds_transpose(ctx, (int)es, kc, nvo, W, nvo, WT, kc));
+        CDS_CALL(cds_transpose(ctx, (int)es, kc, nvec, (const unsigned char *)Bs + (size_t)s0 * nmo * ldk * es, ldk,
+                               BsT, kc));
         GemmDesc d2 = {};
-        d2.M = nvo; d2.N = nvec; d2.K = (int64_t)nsc * nmo; d2.batch = 1;
-        d2.A = W; d2.sAm = 1; d2.sAk = nvo;
-        d2.B = (const unsigned char *)Bs + (size_t)s0 * nmo * ldk * es; d2.sBk = ldk; d2.sBn = 1;
+        d2.M = nvo; d2.N = nvec; d2.K = kc; d2.batch = 1;
+        d2.A = WT; d2.sAm = kc; d2.sAk = 1;
+        d2.B = BsT; d2.sBk = 1; d2.sBn = kc;
         d2.C = Bvo_bar; d2.sCm = ldk; d2.sCn = 1;
         d2.alpha = 1.0; d2.beta = s0 == 0 ? 0.0 : 1.0;
         CDS_CALL(cds_gemm_ex(ctx, gprec, d2, nullptr, nullptr));
@@ -225,7 +254,7 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
         }
         CDS_LAUNCHED(ctx);
     }
-    hipLaunchKernelGGL(eps_bar_kernel, dim3((unsigned)cds_ceil_div(nmo, 64)), dim3(64), 0, ctx->stream,
+    hipLaunchKernelGGL(eps_bar_kernel, dim3((unsigned)nmo), dim3(256), 0, ctx->stream,
                        (const double *)epsA, (const double *)epsB, nsel, nocc, nvirt, (const int32_t *)d_sel,
                        (const double *)d_scale, eps_bar);
     CDS_LAUNCHED(ctx);

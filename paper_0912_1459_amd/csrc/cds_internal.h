@@ -38,6 +38,9 @@ enum CdsSlot {
     WS_MP_S,        // MP2: per-(a, b) sums
     WS_DY_G,        // self-energy matrix: integrals of all selected orbitals
     WS_DY_PART,     // self-energy matrix: partial pair sums
+    WS_AD_T1,       // adjoint: K-contiguous copies of transposed GEMM operands
+    WS_AD_T2,
+    WS_AD_T3,
     WS_SLOTS
 };
 
@@ -158,3 +161,6 @@ struct GemmDesc {
 int cds_gemm(cds_ctx *ctx, int prec, const GemmDesc &d);
 // Alo/Blo: lo planes of BF16X3 operands (hi planes at d.A / d.B); NULL otherwise
 int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, const void *Blo);
+// out[c*ldo + r] = in[r*ldi + c] for r < rows, c < cols; elements of es bytes (4 or 8)
+int cds_transpose(cds_ctx *ctx, int es, int64_t rows, int64_t cols, const void *in, int64_t ldi, void *out,
+                  int64_t ldo);

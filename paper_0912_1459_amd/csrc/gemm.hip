@@ -450,6 +450,50 @@ int launch(cds_ctx *ctx, Args &a)
 
 }  // namespace
 
+namespace {
+// 32 x 32 tiles through LDS (33-word pitch), every load of a thread in flight before its stores
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ in, int64_t ldi, T *__restrict__ out,
+                                                        int64_t ldo, int64_t rows, int64_t cols)
+{
+    __shared__ T t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t r = r0 + ty + 8 * u, c = c0 + tx;
+        v[u] = (r < rows && c < cols) ? in[r * ldi + c] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[ty + 8 * u][tx] = v[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t c = c0 + ty + 8 * u, r = r0 + tx;
+        if (r < rows && c < cols) out[c * ldo + r] = t[tx][ty + 8 * u];
+    }
+}
+}  // namespace
+
+int cds_transpose(cds_ctx *ctx, int es, int64_t rows, int64_t cols, const void *in, int64_t ldi, void *out,
+                  int64_t ldo)
+{
+    CDS_REQUIRE(ctx, es == 4 || es == 8, "transpose: element size %d", es);
+    CDS_REQUIRE(ctx, rows >= 0 && cols >= 0 && ldi >= cols && ldo >= rows, "transpose: bad shape");
+    if (rows == 0 || cols == 0) return CDS_OK;
+    CDS_REQUIRE(ctx, cds_ceil_div(rows, 32) <= 65535, "transpose: too many rows");
+    const dim3 g((unsigned)cds_ceil_div(cols, 32), (unsigned)cds_ceil_div(rows, 32));
+    if (es == 8)
+        hipLaunchKernelGGL(transpose_kernel<double>, g, dim3(256), 0, ctx->stream, (const double *)in, ldi,
+                           (double *)out, ldo, rows, cols);
+    else
+        hipLaunchKernelGGL(transpose_kernel<float>, g, dim3(256), 0, ctx->stream, (const float *)in, ldi,
+                           (float *)out, ldo, rows, cols);
+    CDS_LAUNCHED(ctx);
+    return CDS_OK;
+}
+
 int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, const void *Blo)
 {
     Args a;

@@ -259,15 +259,28 @@ __global__ __launch_bounds__(EP_NT) void grad_a_kernel(EpArgs e)
     double sa = 0.0;
     for (int i = threadIdx.x; i < nocc; i += EP_NT) {
         double si = 0.0;
-        for (int j = 0; j < nocc; ++j) {
-            double x = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
-            double xt = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
-            double d = w0 + ea - eo[i] - eo[j];
-            double u = (2.0 * x - xt) * x, ut = (2.0 * xt - x) * xt;
-            double id = 1.0 / d;
-            ((GT *)e.W)[gbase + (int64_t)i * e.nvo + j] = (GT)(gs * (4.0 * x - 2.0 * xt) * id);
-            si += (u + ut) * id * id;     // d symmetric in (i, j)
-            sa -= u * id * id;
+        // JU columns at a time, their loads in flight before the first use (same order of terms)
+        constexpr int JU = 4;
+        for (int j0 = 0; j0 < nocc; j0 += JU) {
+            double xv[JU], xtv[JU];
+#pragma unroll
+            for (int u = 0; u < JU; ++u) {
+                const int j = j0 + u < nocc ? j0 + u : nocc - 1;
+                xv[u] = ld<GT>(e.G, gbase + (int64_t)i * e.nvo + j);
+                xtv[u] = ld<GT>(e.G, gbase + (int64_t)j * e.nvo + i);
+            }
+#pragma unroll
+            for (int u = 0; u < JU; ++u) {
+                const int j = j0 + u;
+                if (j >= nocc) break;
+                const double x = xv[u], xt = xtv[u];
+                double d = w0 + ea - eo[i] - eo[j];
+                double uu = (2.0 * x - xt) * x, ut = (2.0 * xt - x) * xt;
+                double id = 1.0 / d;
+                ((GT *)e.W)[gbase + (int64_t)i * e.nvo + j] = (GT)(gs * (4.0 * x - 2.0 * xt) * id);
+                si += (uu + ut) * id * id;     // d symmetric in (i, j)
+                sa -= uu * id * id;
+            }
         }
         e.epsA[((int64_t)s * e.nvirt + a) * (nocc + 1) + i] = gs * si;
     }
