@@ -117,8 +117,17 @@ __global__ void sum_parts_kernel(const double *__restrict__ part, int nb, int64_
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
+    // in vector order, eight loads in flight at a time
+    constexpr int U = 8;
     double acc = accumulate ? out[e] : 0.0;
-    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * ne + e];
+    for (int b0 = 0; b0 < nb; b0 += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = b0 + u < nb ? part[(int64_t)(b0 + u) * ne + e] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b0 + u < nb) acc += v[u];
+    }
     out[e] = acc;
 }
 
@@ -280,7 +289,12 @@ extern "C" int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, in
     CdsTimer tall;
     CDS_CALL(cds_timer_start(ctx, &tall));
     const int np_ = (int)(cds_ceil_div(nbf, 64) * 64);
-    const int kb = (int)std::min<int64_t>(64, nvec);
+    // vectors per batch: enough that the first product launches about 2048 tiles of 128 x 128,
+    // with the unpacked batch below 1 GiB (C_bar sums the vectors in order whatever the batch)
+    const int64_t tiles = cds_ceil_div(nmo, 128) * cds_ceil_div(nbf, 128);
+    int64_t kbw = std::max<int64_t>(64, cds_ceil_div(2048, tiles));
+    kbw = std::min<int64_t>(kbw, std::max<int64_t>(1, (int64_t)((1ull << 30) / ((size_t)nbf * np_ * 8))));
+    const int kb = (int)std::min<int64_t>(kbw, nvec);
     void *wl, *ws, *wk, *wsel, *wp;
     CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)kb * nbf * np_ * 8, &wl));
     CDS_CALL(cds_ws(ctx, WS_AD_TMP2, (size_t)kb * nmo * nmo * 8, &ws));
