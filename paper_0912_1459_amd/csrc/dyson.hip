@@ -51,7 +51,9 @@ __global__ __launch_bounds__(DY_NT) void sigma_pairs_kernel(const GT *__restrict
                                                            const double *__restrict__ omega, int T, int64_t nA,
                                                            int64_t nE, int64_t cpb, double *__restrict__ part)
 {
-    __shared__ double su[DY_MAXSEL][DY_CH], sv[DY_MAXSEL][DY_CH];
+    // rows padded by one element: lanes of a wave read one element l of different orbitals s,
+    // which a pitch of DY_CH doubles would put in one bank
+    __shared__ double su[DY_MAXSEL][DY_CH + 1], sv[DY_MAXSEL][DY_CH + 1];
     __shared__ double sw[DY_TT][DY_CH], swi[DY_TT][DY_CH];
     __shared__ int64_t ou[DY_CH], ov[DY_CH];
     const int npair = nsel * (nsel + 1) / 2;
@@ -108,11 +110,27 @@ __global__ __launch_bounds__(DY_NT) void sigma_pairs_kernel(const GT *__restrict
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < nsel * DY_CH; q += DY_NT) {
-            const int s = q / DY_CH, l = q - s * DY_CH;
-            const bool ok = e0 + l < nE;
-            su[s][l] = ok ? (double)G[s * gstride + ou[l]] : 0.0;
-            sv[s][l] = ok ? (double)G[s * gstride + ov[l]] : 0.0;
+        {
+            // every gathered load of a thread in flight before its LDS stores
+            constexpr int QN = (DY_MAXSEL * DY_CH + DY_NT - 1) / DY_NT;
+            double gu[QN], gv[QN];
+#pragma unroll
+            for (int u = 0; u < QN; ++u) {
+                const int q = threadIdx.x + u * DY_NT;
+                const int s = q / DY_CH, l = q - s * DY_CH;
+                const bool ok = q < nsel * DY_CH && e0 + l < nE;
+                gu[u] = ok ? (double)G[s * gstride + ou[l]] : 0.0;
+                gv[u] = ok ? (double)G[s * gstride + ov[l]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < QN; ++u) {
+                const int q = threadIdx.x + u * DY_NT;
+                const int s = q / DY_CH, l = q - s * DY_CH;
+                if (q < nsel * DY_CH) {
+                    su[s][l] = gu[u];
+                    sv[s][l] = gv[u];
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
