@@ -42,13 +42,24 @@ __global__ __launch_bounds__(MP_NT) void mp2_block_kernel(const GT *__restrict__
     const int nb = (nocc + 31) / 32;
     for (int IB = 0; IB < nb; ++IB)
         for (int JB = IB; JB < nb; ++JB) {
-            __syncthreads();
-            for (int q = threadIdx.x; q < 1024; q += MP_NT) {
+            // both tiles: every load in flight before the LDS stores
+            constexpr int QN = 1024 / MP_NT;
+            double v1[QN], v2[QN];
+#pragma unroll
+            for (int u = 0; u < QN; ++u) {
+                const int q = threadIdx.x + MP_NT * u;
                 const int r = q >> 5, c = q & 31;
                 const int i1 = IB * 32 + r, j1 = JB * 32 + c;   // t1[r][c] = X[i1][j1]
                 const int i2 = JB * 32 + r, j2 = IB * 32 + c;   // t2[r][c] = X[i2][j2]
-                t1[r][c] = (i1 < nocc && j1 < nocc) ? ldg(G, base + (int64_t)i1 * ldg_ + j1) : 0.0;
-                t2[r][c] = (i2 < nocc && j2 < nocc) ? ldg(G, base + (int64_t)i2 * ldg_ + j2) : 0.0;
+                v1[u] = (i1 < nocc && j1 < nocc) ? ldg(G, base + (int64_t)i1 * ldg_ + j1) : 0.0;
+                v2[u] = (i2 < nocc && j2 < nocc) ? ldg(G, base + (int64_t)i2 * ldg_ + j2) : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < QN; ++u) {
+                const int q = threadIdx.x + MP_NT * u;
+                t1[q >> 5][q & 31] = v1[u];
+                t2[q >> 5][q & 31] = v2[u];
             }
             __syncthreads();
             for (int q = threadIdx.x; q < 1024; q += MP_NT) {
@@ -78,10 +89,25 @@ __global__ __launch_bounds__(MP_RED_NT) void mp2_sum_kernel(const double *__rest
                                                             double *__restrict__ out)
 {
     __shared__ double sh[MP_RED_NT / 64];
+    // each thread's terms in a fixed order (column offset b - a, then a), eight rows a of loads in
+    // flight at a time
+    constexpr int AU = 8;
     double acc = 0.0;
-    for (int a = 0; a < nvirt; ++a)
-        for (int b = a + threadIdx.x; b < nvirt; b += MP_RED_NT)
-            acc += (b == a ? 1.0 : 2.0) * S[(int64_t)a * nvirt + b];
+    for (int b0 = threadIdx.x; b0 < nvirt; b0 += MP_RED_NT) {     // b = a + b0: one column offset per pass
+        for (int a0 = 0; a0 < nvirt; a0 += AU) {
+            double v[AU];
+#pragma unroll
+            for (int u = 0; u < AU; ++u) {
+                const int a = a0 + u, b = a + b0;
+                v[u] = (a < nvirt && b < nvirt) ? S[(int64_t)a * nvirt + b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < AU; ++u) {
+                const int a = a0 + u, b = a + b0;
+                if (a < nvirt && b < nvirt) acc += (b == a ? 1.0 : 2.0) * v[u];
+            }
+        }
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (l == 0) sh[w] = acc;
