@@ -199,7 +199,8 @@ def main():
         "misses_per_cd": st["n_cd_miss"] / args.steps,
         "speculative": {"blocks_per_cd": st["n_cd_spec_block"] / args.steps,
                         "steps_per_cd": st["n_cd_spec"] / args.steps,
-                        "ms_per_cd": round(st["t_cd_spec_ms"] / args.steps, 3)},
+                        "ms_per_cd": round(st["t_cd_spec_ms"] / args.steps, 3),
+                        "state_reads_per_cd": st["n_cd_state_read"] / args.steps},
     }
     traffic = committed_traffic(args.workload)
     if t_pass >= t_step:

@@ -107,6 +107,8 @@ typedef struct cds_stats {
     double t_cd_spec_ms;     /* speculative blocks (with kernel timing on)    */
     int64_t n_cd_spec;       /* Cholesky steps committed by speculative blocks */
     int64_t n_cd_spec_block; /* speculative blocks tried                      */
+    int64_t n_cd_state_read; /* Cholesky state reads that waited for the stream
+                                to drain (speculative path)                   */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`

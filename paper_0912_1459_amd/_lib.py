@@ -43,6 +43,7 @@ class Stats(ctypes.Structure):
         ("n_cd_step_launch", ctypes.c_int64), ("n_cd_pass_launch", ctypes.c_int64),
         ("t_mp2_ms", ctypes.c_double), ("flops_mp2", ctypes.c_double), ("t_dyson_ms", ctypes.c_double),
         ("t_cd_spec_ms", ctypes.c_double), ("n_cd_spec", ctypes.c_int64), ("n_cd_spec_block", ctypes.c_int64),
+        ("n_cd_state_read", ctypes.c_int64),
     ]
 
 

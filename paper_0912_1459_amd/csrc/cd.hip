@@ -44,6 +44,7 @@
 #include "cds_internal.h"
 
 #include <cfloat>
+#include <chrono>
 #include <climits>
 
 namespace {
@@ -89,7 +90,21 @@ struct CdState {
     int32_t nmap;    // entries of the row -> candidate slot map that are set (cand[0 .. nmap))
     int32_t pad2;
     double dnc;      // bound on the residual diagonals of the eligible rows that are not candidates
+    int64_t nblk;    // speculative blocks that reached their commit (kept steps or stalled)
 };
+
+// Host mailbox word, written by each speculative block's commit: the committed step count,
+// the stall flag and the block count (modulo 2^23), in one 64-bit store the host can read
+// while later blocks run.
+constexpr int MB_KBITS = 40;
+constexpr uint64_t MB_KMASK = (1ull << MB_KBITS) - 1;
+constexpr int MB_NSHIFT = MB_KBITS + 1;
+constexpr uint64_t MB_NMASK = (1ull << (64 - MB_NSHIFT)) - 1;
+__host__ __device__ inline uint64_t mb_word(int64_t nblk, int stall, int64_t k)
+{
+    return (((uint64_t)nblk & MB_NMASK) << MB_NSHIFT) | ((uint64_t)(stall != 0) << MB_KBITS) |
+           ((uint64_t)k & MB_KMASK);
+}
 
 // Per 64-row tile, over its non-pivot rows: the largest and smallest residual diagonal,
 // and the lowest row whose residual is within the tie window of the largest (with that
@@ -786,8 +801,8 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
 // eligible row has a residual above the candidates' maximum, nor a residual in its tie
 // window at a lower index than the chosen pivot (candidate rows cannot, since both
 // kernels evaluate them with the same operations), nor any non-pivot row a residual
-// below -psd_tol.  The host commits the steps before the first one that fails
-// (cd_commit_kernel) and starts the next block there.
+// below -psd_tol.  cd_commit_kernel commits the steps before the first one that fails, and
+// the next block starts there.
 struct SpecOut {
     int32_t nspec;           // speculated steps
     int32_t pad;
@@ -1229,12 +1244,18 @@ __global__ void reset_super_kernel(CdBufs b, CdParams cp, const CdState *st, con
 // commit the first nc speculated steps: residuals, pivot marks and tile records into the
 // buffers of parity w (the step k0 + nc reads them), pivots and the state
 __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, const double *__restrict__ Dbuf,
-                                                        const SpecOut *so, CdState *st, int64_t *__restrict__ piv)
+                                                        const SpecOut *so, CdState *st, int64_t *__restrict__ piv,
+                                                        uint64_t *mail)
 {
     if (spec_idle(st)) return;
     const int nc = spec_keep(so);
     if (nc == 0) {                               // nothing stands: one per-step launch next
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->stall = 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->stall = 1;
+            const int64_t nb = st->nblk + 1;
+            st->nblk = nb;
+            if (mail) __hip_atomic_store(mail, mb_word(nb, 1, st->k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
         return;
     }
     __shared__ int64_t sp[CD_SPEC_MAX];
@@ -1260,6 +1281,9 @@ __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, c
         st->k = k0 + nc;
         st->dmax = so->cmax[nc - 1];
         st->nspec += nc;
+        const int64_t nb = st->nblk + 1;
+        st->nblk = nb;
+        if (mail) __hip_atomic_store(mail, mb_word(nb, 0, k0 + nc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1695,6 +1719,47 @@ void launch_step_any(cds_ctx *ctx, int vw, int tb, const CdBufs &b, const CdPara
         launch_step<1, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
 }
 
+// The mailbox word (coherent pinned host memory, written by the device over the bus), made
+// once per context; false where it cannot be had or was seen not to follow the state.
+bool mail_ready(cds_ctx *ctx)
+{
+    if (ctx->mail_off) return false;
+    if (!ctx->mail) {
+        void *h = nullptr, *d = nullptr;
+        if (hipHostMalloc(&h, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            ctx->mail_off = true;
+            return false;
+        }
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipHostFree(h);
+            ctx->mail_off = true;
+            return false;
+        }
+        ctx->mail = (uint64_t *)h;
+        ctx->mail_dev = (uint64_t *)d;
+    }
+    return true;
+}
+
+// Spin until the word shows a block count in (seen, upto] (modulo its field); false once
+// limit_ms passed without one.
+bool mail_wait(const uint64_t *mail, int64_t seen, int64_t upto, double limit_ms, uint64_t *w)
+{
+    const uint64_t span = (uint64_t)(upto - seen);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t it = 1;; ++it) {
+        const uint64_t v = __atomic_load_n(mail, __ATOMIC_ACQUIRE);
+        const uint64_t d = ((v >> MB_NSHIFT) - (uint64_t)seen) & MB_NMASK;
+        if (d != 0 && d <= span) {
+            *w = v;
+            return true;
+        }
+        if ((it & 255) == 0 &&
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > limit_ms)
+            return false;
+    }
+}
+
 int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                   const double *alpha, int64_t npairs, const double *V, int64_t ldv, double delta,
                   double tau, double psd_tol, int64_t max_vec, double *L, int64_t ldl,
@@ -1797,6 +1862,9 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     CdState st0 = {};
     st0.k = nvec_in;
     st0.kdone = INT64_MAX;
+    // block counts of successive calls start 2^16 apart, so no word a call left can be taken
+    // for one of the next call's commits
+    st0.nblk = (int64_t)(ctx->mail_base += (1 << 16));
     *(CdState *)hp = st0;
     CDS_HIP(ctx, hipMemcpyAsync(st, hp, sizeof(CdState), hipMemcpyHostToDevice, ctx->stream));
     if (nvec_in == 0) {
@@ -1815,14 +1883,80 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     const dim3 grid((unsigned)ntile);
     CdsTimer tk;
     bool run_timed = false;
-    // speculative blocks, chained on the device: NB blocks are queued per read of the state;
-    // a stall (a block that kept no step: a termination or a failed first check) gets one
-    // per-step launch at the same start, whose candidates and residual columns still hold
+    // speculative blocks, chained on the device.  With the mailbox, two blocks stay queued:
+    // each commit's word tells the host to queue one more, and the stream is drained only at a
+    // stall.  Without it, NB blocks are queued per read of the state.  A stall (a block that
+    // kept no step: a termination or a failed first check) gets one per-step launch at the same
+    // start, whose candidates and residual columns still hold.
     constexpr int NB = 4;
+    constexpr int MB_AHEAD = 2;            // blocks queued beyond the last commit seen
+    constexpr double MB_WAIT_MS = 1000.0;  // then the state is read after a drain instead
+    const bool mb = spec_on && mail_ready(ctx);
+    if (mb) __atomic_store_n(ctx->mail, mb_word(st0.nblk, 0, 0), __ATOMIC_RELEASE);
+    bool blocks_ran = false;               // speculative blocks since the last read of the state
+    auto queue_block = [&]() -> int {
+        hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
+                           st, cand, so);
+        CDS_LAUNCHED(ctx);
+        const int64_t cgx = cds_ceil_div(npairs, 256);
+        const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
+        const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCAND + gy));
+        if (dense)
+            hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                               npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
+                               ldl, Pc);
+        else
+            hipLaunchKernelGGL(cd_candcol_gather_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                               npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
+                               ldl, Pc);
+        CDS_LAUNCHED(ctx);
+        CdsTimer tp;
+        if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
+        hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
+                           (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                           (const signed char *)bf.slot, bf.rc);
+        CDS_LAUNCHED(ctx);
+        if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
+        if (hook && hook->block) CDS_CALL(hook->block(hook->user));
+        CdsTimer tsp;
+        if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
+        const unsigned nrb = (unsigned)cds_ceil_div(npairs, 256);
+        const unsigned nlb = (unsigned)cds_ceil_div(npairs, CD_LS_ROWS);
+        if (nlb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path) {
+            hipLaunchKernelGGL(cd_lockstep_kernel, dim3(nlb), dim3(64 + CD_LS_ROWS), 0, ctx->stream, bf, cp,
+                               (const int64_t *)cand, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf,
+                               so);
+            CDS_LAUNCHED(ctx);
+        } else {
+            hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
+                               (const CdState *)st, so);
+            CDS_LAUNCHED(ctx);
+            hipLaunchKernelGGL(cd_rows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp, (const CdState *)st,
+                               (const double *)Rc, ldr, L, ldl, Dbuf, so);
+            CDS_LAUNCHED(ctx);
+        }
+        if (!bf.flat) {
+            hipLaunchKernelGGL(reset_super_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const CdState *)st,
+                               (const SpecOut *)so);
+            CDS_LAUNCHED(ctx);
+        }
+        hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
+                           ctx->stream, bf, cp, (const double *)Dbuf, (const SpecOut *)so, st, piv,
+                           mb && !ctx->mail_off ? ctx->mail_dev : nullptr);
+        CDS_LAUNCHED(ctx);
+        if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
+        return CDS_OK;
+    };
     while (spec_on) {
         CDS_HIP(ctx, hipMemcpyAsync(hp, st, sizeof(CdState), hipMemcpyDeviceToHost, ctx->stream));
         CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
         hs = *(CdState *)hp;
+        ctx->stats.n_cd_state_read += 1;
+        // every commit has landed: the word must show the last one (else it is not used again)
+        if (mb && blocks_ran && hs.nblk != st0.nblk &&
+            __atomic_load_n(ctx->mail, __ATOMIC_ACQUIRE) != mb_word(hs.nblk, hs.stall, hs.k))
+            ctx->mail_off = true;
+        blocks_ran = false;
         if (hs.done) break;
         k = hs.k;
         if (k > max_vec)
@@ -1844,56 +1978,19 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             ctx->stats.n_cd_step_launch += 1;
             continue;
         }
-        for (int bi = 0; bi < NB; ++bi) {
-            hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
-                               st, cand, so);
-            CDS_LAUNCHED(ctx);
-            const int64_t cgx = cds_ceil_div(npairs, 256);
-            const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
-            const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCAND + gy));
-            if (dense)
-                hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
-                                   npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
-                                   ldl, Pc);
-            else
-                hipLaunchKernelGGL(cd_candcol_gather_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
-                                   npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
-                                   ldl, Pc);
-            CDS_LAUNCHED(ctx);
-            CdsTimer tp;
-            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
-            hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
-                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc);
-            CDS_LAUNCHED(ctx);
-            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
-            if (hook && hook->block) CDS_CALL(hook->block(hook->user));
-            CdsTimer tsp;
-            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
-            const unsigned nrb = (unsigned)cds_ceil_div(npairs, 256);
-            const unsigned nlb = (unsigned)cds_ceil_div(npairs, CD_LS_ROWS);
-            if (nlb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path) {
-                hipLaunchKernelGGL(cd_lockstep_kernel, dim3(nlb), dim3(64 + CD_LS_ROWS), 0, ctx->stream, bf, cp,
-                                   (const int64_t *)cand, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf,
-                                   so);
-                CDS_LAUNCHED(ctx);
-            } else {
-                hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
-                                   (const CdState *)st, so);
-                CDS_LAUNCHED(ctx);
-                hipLaunchKernelGGL(cd_rows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp, (const CdState *)st,
-                                   (const double *)Rc, ldr, L, ldl, Dbuf, so);
-                CDS_LAUNCHED(ctx);
-            }
-            if (!bf.flat) {
-                hipLaunchKernelGGL(reset_super_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const CdState *)st,
-                                   (const SpecOut *)so);
-                CDS_LAUNCHED(ctx);
-            }
-            hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
-                               ctx->stream, bf, cp, (const double *)Dbuf, (const SpecOut *)so, st, piv);
-            CDS_LAUNCHED(ctx);
-            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
+        blocks_ran = true;
+        if (!mb || ctx->mail_off) {
+            for (int bi = 0; bi < NB; ++bi) CDS_CALL(queue_block());
+            continue;
+        }
+        int64_t seen = hs.nblk, queued = hs.nblk;
+        for (;;) {
+            for (; queued < seen + MB_AHEAD; ++queued) CDS_CALL(queue_block());
+            uint64_t w;
+            if (!mail_wait(ctx->mail, seen, queued, MB_WAIT_MS, &w)) break;
+            seen += (int64_t)(((w >> MB_NSHIFT) - (uint64_t)seen) & MB_NMASK);
+            if ((w >> MB_KBITS) & 1) break;            // stalled: the blocks after it do nothing
+            if (hook) CDS_CALL(hook->committed(hook->user, (int64_t)(w & MB_KMASK)));
         }
     }
     for (; !spec_on;) {

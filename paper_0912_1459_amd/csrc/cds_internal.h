@@ -69,6 +69,10 @@ struct cds_ctx {
     hipStream_t stream2 = nullptr;   // side stream (default priority) of the overlapped transform
     hipEvent_t join = nullptr;       // orders stream2 after / before the caller's stream
     hipEvent_t gate = nullptr;       // orders a stream2 batch after a point of the caller's stream
+    uint64_t *mail = nullptr;        // coherent pinned word the Cholesky commits write (host address)
+    uint64_t *mail_dev = nullptr;    // the same word's device address
+    bool mail_off = false;           // 1: the word did not follow the state (state read after every batch)
+    uint64_t mail_base = 0;          // block count the last Cholesky call started from
 };
 
 // error helpers -------------------------------------------------------------
@@ -128,9 +132,10 @@ __device__ __forceinline__ void cds_pair_decode(int64_t I, int64_t &mu, int64_t 
 static inline size_t cds_prec_bytes(int prec) { return prec == CDS_PREC_FP64 ? 8 : 4; }
 
 // internal entry points shared between translation units ----------------------
-// Progress of a decomposition: after each read of its device state the host loop calls
-// committed(user, k) with the number of vectors that are final (no later kernel of the
-// decomposition writes L[0..k) again, and the caller's stream has completed their writes).
+// Progress of a decomposition: after each read of its device state, and of the mailbox word a
+// speculative block's commit writes, the host loop calls committed(user, k) with the number
+// of vectors that are final (no later kernel of the decomposition writes L[0..k) again, and
+// the kernels that wrote them have completed).
 // A non-zero return ends the decomposition with that status.
 // block(user) is called after each look-ahead block's pass has been queued on the caller's
 // stream (may be NULL).

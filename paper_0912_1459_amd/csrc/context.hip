@@ -149,6 +149,7 @@ void cds_destroy(cds_ctx *ctx)
     for (int s = 0; s < WS_SLOTS; ++s)
         if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->mail) (void)hipHostFree(ctx->mail);
     delete ctx;
 }
 

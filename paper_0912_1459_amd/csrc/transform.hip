@@ -386,13 +386,13 @@ struct StreamScope {
 };
 
 // Transform of the decomposition's vectors while it runs, on the side stream.  With look-ahead
-// blocks, each block's pass is followed (through an event) by a piece of at most OVL_PIECE of
-// the vectors known to be final, so the piece runs in the block's single-workgroup and
-// row-update kernels, where most of the device is idle, rather than beside the passes (pieces
-// of 96 measured better than 32, 48, 128, 192 or 256, and than batches queued at each read of
-// the state, which slowed the decomposition by 0.65 ms on c60).  Without blocks (per-step
-// launches), the vectors made since the last batch go at each read of the state, at least
-// OVL_MIN of them.
+// blocks, once OVL_PIECE vectors are known to be final and not yet queued, the next block's
+// pass is followed (through an event) by a piece of OVL_PIECE of them, so the piece runs in
+// the block's single-workgroup and row-update kernels, where most of the device is idle,
+// rather than beside the passes (pieces of 96 measured better than 32, 48, 128, 192 or 256,
+// and than batches queued as soon as vectors are final, which slowed the decomposition by
+// 0.65 ms on c60).  Without blocks (per-step launches), the vectors made since the last batch
+// go at each read of the state, at least OVL_MIN of them.
 constexpr int64_t OVL_MIN = 128;
 constexpr int64_t OVL_PIECE = 96;
 constexpr int64_t OVL_CAP = 512;    // batch size the workspace holds
@@ -431,7 +431,7 @@ int overlap_block(void *user)
 {
     Overlap &o = *(Overlap *)user;
     o.gated = true;
-    if (o.kfinal - o.kdone < OVL_PIECE / 2) return CDS_OK;
+    if (o.kfinal - o.kdone < OVL_PIECE) return CDS_OK;
     CDS_HIP(o.ctx, hipEventRecord(o.ctx->gate, o.ctx->stream));
     CDS_HIP(o.ctx, hipStreamWaitEvent(o.ctx->stream2, o.ctx->gate, 0));
     return overlap_queue(o, std::min<int64_t>(o.kfinal, o.kdone + OVL_PIECE));

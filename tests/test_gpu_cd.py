@@ -162,6 +162,10 @@ def test_cd_speculative_blocks(cds, name, delta):
     assert torch.all((got.L - base.L).abs().max(dim=1).values <= tol)
     assert torch.all((got.D - base.D).abs() <= 1e3 * np.finfo(float).eps * E.eri_diagonal(w.centres, w.alpha).max())
     assert st["n_cd_spec"] >= got.nvec // 2
+    # the host follows the blocks through the mailbox word: the stream drains only at the first
+    # read, at a stall and after the stall's one per-step launch
+    log(f"  {st['n_cd_state_read']} state reads, {st['n_cd_step_launch']} per-step launches")
+    assert st["n_cd_state_read"] <= 1 + 2 * st["n_cd_step_launch"]
 
 
 def test_cd_cap_status_and_resume(cds):
