@@ -249,11 +249,12 @@ int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const d
  * The decomposition of cds_cholesky_sgauss from a fresh start (nvec_in = 0)
  * and the transform of cds_transform of its vectors (Eq. (transformation)) in
  * one call, the transform overlapped with the decomposition: vectors become
- * final when the decomposition's host loop reads its device state, and after
- * each look-ahead block's pass a piece of them (up to 96) is transformed on a
- * second stream of the library (default priority), which fills the device
- * while the block's single-workgroup kernels run; the remaining vectors
- * follow the last one.  The results are those of
+ * final when the decomposition's host loop reads its device state or the word
+ * a look-ahead block's commit writes to pinned host memory, and once 96 of
+ * them wait, the next block's pass is followed by their transform on a second
+ * stream of the library (default priority), which fills the device while the
+ * block's single-workgroup kernels run; the remaining vectors follow the last
+ * one.  The results are those of
  * cds_cholesky_sgauss(..., nvec_in = 0, ...) followed by cds_transform(...,
  * nvec = *h_nvec, ...) with the same arguments, bit for bit (each vector's
  * blocks do not depend on how the vectors are batched).
