@@ -140,6 +140,15 @@ int cds_set_cd_lookahead(cds_ctx *ctx, int32_t block_steps);
  * 0 = a look-ahead pass every block_steps steps and per-step kernels.  The
  * pivots are the same either way. */
 int cds_set_cd_speculate(cds_ctx *ctx, int32_t on);
+/* How the host follows speculative blocks: 1 (default) = each block's commit
+ * writes a word (committed step count, stall flag, block count) to coherent
+ * pinned host memory of the context; the host keeps two blocks queued beyond
+ * the last commit it has seen and reads the device state only at a stall.
+ * 0 = four blocks are queued per read of the device state.  Results are the
+ * same either way; 1 falls back to 0 by itself where the word cannot be
+ * allocated or does not follow the device state.  cds_stats.n_cd_state_read
+ * counts the reads. */
+int cds_set_cd_mailbox(cds_ctx *ctx, int32_t on);
 /* Cholesky code path by problem size: 0 (default) = automatic; 1 = the path of
  * large pair counts at any size (pivot search through 64 super-tile maxima,
  * then tiles, then rows, instead of one sweep over all 64-row tile records; four

@@ -114,6 +114,11 @@ class Context:
         """Speculative look-ahead blocks in the Cholesky decomposition (default on)."""
         self.check(self.lib.cds_set_cd_speculate(self.h, int(bool(on))))
 
+    def set_cd_mailbox(self, on: bool):
+        """Speculative blocks report each commit through a word in pinned host memory (True,
+        default), or the host reads the device state after every four blocks (False)."""
+        self.check(self.lib.cds_set_cd_mailbox(self.h, int(bool(on))))
+
     def set_cd_large_path(self, on: bool):
         """Cholesky code path of large pair counts (hierarchical pivot search, four tiles per
         step block) at any size (True), or chosen by size (False)."""

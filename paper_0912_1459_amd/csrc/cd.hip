@@ -1723,7 +1723,7 @@ void launch_step_any(cds_ctx *ctx, int vw, int tb, const CdBufs &b, const CdPara
 // once per context; false where it cannot be had or was seen not to follow the state.
 bool mail_ready(cds_ctx *ctx)
 {
-    if (ctx->mail_off) return false;
+    if (ctx->mail_off || !ctx->cd_mailbox) return false;
     if (!ctx->mail) {
         void *h = nullptr, *d = nullptr;
         if (hipHostMalloc(&h, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
@@ -2182,6 +2182,14 @@ int cds_set_cd_speculate(cds_ctx *ctx, int32_t on)
     if (!ctx) return CDS_EINVAL;
     if (on != 0 && on != 1) return cds_fail(ctx, CDS_EINVAL, "on must be 0 or 1");
     ctx->cd_speculate = on;
+    return CDS_OK;
+}
+
+int cds_set_cd_mailbox(cds_ctx *ctx, int32_t on)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (on != 0 && on != 1) return cds_fail(ctx, CDS_EINVAL, "on must be 0 or 1");
+    ctx->cd_mailbox = on;
     return CDS_OK;
 }
 

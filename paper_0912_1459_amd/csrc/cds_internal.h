@@ -72,6 +72,7 @@ struct cds_ctx {
     uint64_t *mail = nullptr;        // coherent pinned word the Cholesky commits write (host address)
     uint64_t *mail_dev = nullptr;    // the same word's device address
     bool mail_off = false;           // 1: the word did not follow the state (state read after every batch)
+    int cd_mailbox = 1;              // 0: the caller turned the word off
     uint64_t mail_base = 0;          // block count the last Cholesky call started from
 };
 

@@ -168,6 +168,28 @@ def test_cd_speculative_blocks(cds, name, delta):
     assert st["n_cd_state_read"] <= 1 + 2 * st["n_cd_step_launch"]
 
 
+@pytest.mark.parametrize("name,delta", [("plain", 1e-8), ("c60", 1e-6)])
+def test_cd_state_reads_without_mailbox(cds, name, delta):
+    # the host's two ways of following the speculative blocks give the same decomposition,
+    # bit for bit; without the word the state is read after every four blocks
+    w = workload(name)
+    log(f"cd speculative blocks without the mailbox word {name} delta={delta}")
+    c, a = _dev(w.centres), _dev(w.alpha)
+    ctx0 = cds.Context(0)
+    base = cds.cholesky(delta, centres=c, alpha=a, ctx=ctx0)
+    ctx1 = cds.Context(0)
+    ctx1.set_cd_mailbox(False)
+    got = cds.cholesky(delta, centres=c, alpha=a, ctx=ctx1)
+    st0, st1 = ctx0.stats(), ctx1.stats()
+    log(f"  state reads {st0['n_cd_state_read']} with the word, {st1['n_cd_state_read']} without")
+    assert got.nvec == base.nvec and got.status == base.status
+    assert torch.equal(got.piv[: got.nvec], base.piv[: base.nvec])
+    assert torch.equal(got.L.contiguous().view(torch.int64), base.L.contiguous().view(torch.int64))
+    assert torch.equal(got.D.view(torch.int64), base.D.view(torch.int64))
+    assert st1["n_cd_state_read"] >= st1["n_cd_spec_block"] // 4
+    assert st0["n_cd_state_read"] <= 1 + 2 * st0["n_cd_step_launch"]
+
+
 def test_cd_cap_status_and_resume(cds):
     w = workload("plain")
     log("cd cap plain")
