@@ -259,7 +259,7 @@ int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const d
  * and the transform of cds_transform of its vectors (Eq. (transformation)) in
  * one call, the transform overlapped with the decomposition: vectors become
  * final when the decomposition's host loop reads its device state or the word
- * a look-ahead block's commit writes to pinned host memory, and once 96 of
+ * a look-ahead block's commit writes to pinned host memory, and once 112 of
  * them wait, the next block's pass is followed by their transform on a second
  * stream of the library (default priority), which fills the device while the
  * block's single-workgroup kernels run; the remaining vectors follow the last
