@@ -1,19 +1,25 @@
 """Benchmark of the Cholesky-decomposition Sigma(2) quasi-particle path on one GPU.
 
-One step = the whole hot path over one synthetic C60-shaped workload with its
-inputs resident in HBM:
-  pivoted incomplete Cholesky of the ERI supermatrix to delta = 1e-6 (FP64,
-  on-demand s-Gaussian ERI columns)  ->  B^K = C^T L^K C blocks  ->  Newton
-  quasi-particle solves (Delta = 1e-5) for the 20 orbitals HOMO-9 ... LUMO+9.
-The headline precision runs the transform and contraction in split-bf16
-(3-term, FP32 accumulation); FP32 and FP64 are measured beside it, and the
-quasi-particle error of each against the FP64 path is reported in meV.
+One step = the whole hot path over one synthetic workload with its inputs resident in HBM:
+  pivoted incomplete Cholesky of the ERI supermatrix (FP64, on-demand s-Gaussian ERI
+  columns)  ->  B^K = C^T L^K C blocks (the transform runs beside the decomposition)  ->
+  Newton quasi-particle solves (Delta = 1e-5) of the target orbitals.
+The default workload is the large one (truncated-icosahedron cage, 16 s-Gaussians per
+centre, N = 960, 461,280 pairs, delta = 1e-4, 16 targets) and the headline runs every step
+in FP64, the paper's arithmetic.  Beside it: the same step with the transform and the
+contraction in FP32 and in split-bf16 (3 products, FP32 accumulation), each
+quasi-particle energy's error against the FP64 oracle in meV, the backward pass (adjoint
+of the solve and of the transform), MP2 and the Dyson search; then a secondary block on the
+C60-shaped workload (N = 240) with the per-orbital precision report beside the error the
+decomposition alone causes (against exact integrals), the delta sweep and the atomic CD;
+and the oracle timed on the host cores on a bounded sample of the large workload.
 
 Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix peak
 METRIC = "quasi-particle solves/s + contraction TFLOP/s, FP32/BF16x3 vs FP64 at ≤1 meV"
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def parse():
@@ -36,14 +43,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
-    p.add_argument("--workload", default="c60", choices=["c60", "large"])
+    p.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--workload", default="large", choices=["c60", "large"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-overlap", action="store_true",
                    help="decomposition, then transform (instead of the transform beside the decomposition)")
-    p.add_argument("--cpu-targets", type=int, default=4, help="targets in the oracle Newton sample")
     p.add_argument("--quick", action="store_true",
-                   help="timed steps and roofline only (no precision, MP2, sweep, aCD or Dyson reports)")
+                   help="timed steps and roofline only (no precision, backward, MP2, Dyson or secondary reports)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run an elementwise device copy of MIB MiB three times (scales HBM counters)")
     return p.parse_args()
@@ -66,43 +72,349 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def src_sha(name: str) -> str:
+    with open(os.path.join(ROOT, "paper_0912_1459_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def committed_traffic(workload: str) -> dict:
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, per
-    kernel, if it was taken on this workload and the Cholesky source is unchanged since; else {}."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "cd_kernels_c60_traffic.json")
-    src = os.path.join(ROOT, "paper_0912_1459_amd", "csrc", "cd.hip")
+    """HBM bytes per launch per kernel from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summaries of this workload, for each kernel whose source file is unchanged since."""
+    out = {}
+    for fn in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
+        if not fn.endswith("_traffic.json"):
+            continue
+        try:
+            with open(os.path.join(ROOT, "profiles", fn)) as f:
+                rec = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if rec.get("workload_key") != workload:
+            continue
+        shas = rec.get("source_sha256", {})
+        if not shas or any(src_sha(s) != h for s, h in shas.items()):
+            continue
+        for k, v in rec.get("kernels", {}).items():
+            out[k] = v["hbm_bytes_per_launch"]
+    return out
+
+
+def load_golden(name: str):
     try:
-        with open(path) as f:
-            rec = json.load(f)
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        with open(os.path.join(GOLDEN, name)) as f:
+            return json.load(f)
     except OSError:
-        return {}
-    if rec.get("cd_hip_sha256") != sha or rec.get("workload_key") != workload:
-        return {}
-    return {k: v["hbm_bytes_per_launch"] for k, v in rec.get("kernels", {}).items()}
+        return None
 
 
-def cpu_baseline(w, delta: float, conv: float, ntarget: int) -> dict:
-    """The oracle as it stands on the host cores: CD + transform in full, Newton on a sample."""
+class Runner:
+    """One workload on the device: inputs resident in HBM, a library context, the step."""
+
+    def __init__(self, workload: str, overlap: bool = True):
+        import torch
+        import paper_0912_1459_amd.core as C
+        from paper_0912_1459_amd import inputs as I
+        self.C = C
+        self.torch = torch
+        self.w = w = I.make(workload)
+        self.workload = workload
+        dev = "cuda:0"
+        self.centres = torch.tensor(w.centres, device=dev)
+        self.alpha = torch.tensor(w.alpha, device=dev)
+        self.Cm = torch.tensor(w.C, device=dev)
+        self.eps = torch.tensor(w.eps, device=dev)
+        self.stream = torch.cuda.current_stream()
+        self.ctx = C.Context(0, self.stream)
+        if workload == "large":
+            # C = S^-1/2 Q with lambda_min(S) ~ 2e-7: rounding inside an FP32 or split-bf16
+            # transform would be amplified ~1/lambda_min, so the transform runs in FP64 and
+            # only the blocks are rounded for the contraction
+            self.ctx.set_transform_fp64(True)
+        self.overlap = overlap
+        self.max_vec = (12 if workload == "c60" else 6) * w.nbf   # room for either workload's delta
+        self.conv = 1e-5
+
+    def step(self, prec):
+        C, w = self.C, self.w
+        if not self.overlap:
+            cd = C.cholesky(w.delta, centres=self.centres, alpha=self.alpha, max_vec=self.max_vec, grow=True,
+                            ctx=self.ctx)
+            B = C.transform(cd.Lbuf, cd.nvec, self.Cm, w.nocc, w.targets, prec, ctx=self.ctx)
+        else:
+            # the transform of the vectors made so far runs beside the decomposition
+            cd, B = C.cholesky_transform(w.delta, centres=self.centres, alpha=self.alpha, C=self.Cm, nocc=w.nocc,
+                                         sel=w.targets, prec=prec, max_vec=self.max_vec, ctx=self.ctx)
+        qp = C.qp_solve(B, self.eps, conv=self.conv, mode="residues", ctx=self.ctx)
+        return cd, B, qp
+
+    def timed(self, prec, steps, warmup):
+        """(ms per step, library stats of the timed steps, last step's results); HIP events on
+        the library's stream bracket the K steps."""
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(prec)
+        torch.cuda.synchronize()
+        self.ctx.reset_stats()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(self.stream)
+        for _ in range(steps):
+            res = self.step(prec)
+        ev1.record(self.stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps, self.ctx.stats(), res
+
+
+def cd_report(st: dict, steps: int, npairs: int, M: int) -> dict:
+    """Cholesky kernels from a kernel-timing run: launches, times, the pass's hardware and
+    method flops (method: the plain algorithm's 2 npairs k products per step, of which the
+    pass stands in for the vectors before each block's start)."""
+    n_step, n_pass = st["n_cd_step_launch"], st["n_cd_pass_launch"]
+    t_step, t_pass = st["t_cd_kernel_ms"] / 1e3, st["t_cd_pass_ms"] / 1e3
+    t_cd = st["t_cd_ms"] / 1e3
+    plain_flops = 2.0 * npairs * (M * (M - 1) / 2.0) * steps      # sum_k 2 npairs k
+    return {
+        "step": {"launches_per_cd": n_step / steps, "total_ms_per_cd": round(t_step * 1e3 / steps, 3),
+                 "avg_us": round(t_step / max(n_step, 1) * 1e6, 3)},
+        "pass": {"launches_per_cd": n_pass / steps, "total_ms_per_cd": round(t_pass * 1e3 / steps, 3),
+                 "avg_us": round(t_pass / max(n_pass, 1) * 1e6, 3),
+                 "hardware_tflops_fp64": round(st["flops_cd_pass"] / t_pass / 1e12, 2) if t_pass > 0 else None,
+                 "hardware_frac": round(st["flops_cd_pass"] / t_pass / 1e12 / FP64_MFMA_TFLOPS, 4) if t_pass > 0 else None,
+                 "method_tflops_fp64": round(st["flops_cd_pass_method"] / t_pass / 1e12, 2) if t_pass > 0 else None,
+                 "method_frac": round(st["flops_cd_pass_method"] / t_pass / 1e12 / FP64_MFMA_TFLOPS, 4) if t_pass > 0 else None,
+                 "units": ("hardware: 2 x pairs x k0 x 64 candidate columns per launch; method: 2 x pairs x k0 "
+                           "per step the block keeps")},
+        "speculative": {"blocks_per_cd": st["n_cd_spec_block"] / steps, "steps_per_cd": st["n_cd_spec"] / steps,
+                        "state_reads_per_cd": st["n_cd_state_read"] / steps},
+        "decomposition": {"ms": round(t_cd * 1e3 / steps, 3), "method_tflops_fp64": round(plain_flops / t_cd / 1e12, 2),
+                          "method_frac": round(plain_flops / t_cd / 1e12 / FP64_MFMA_TFLOPS, 4),
+                          "units": "sum over steps k of 2 x pairs x k (the plain left-looking products)"},
+        # bytes the plain one-vector-per-step algorithm streams, over the whole decomposition
+        "plain_algorithm_equivalent_gbs": round(st["bytes_cd"] / t_cd / 1e9, 1),
+    }
+
+
+def contraction_roofline(st: dict, prec: str, traffic: dict) -> dict:
+    """Roofline of the contraction kernel from HIP events around its launches (library stream)."""
+    n = max(st["n_contract"], 1)
+    t = st["t_contract_ms"] / 1e3
+    per_launch = st["flops_contract"] / n
+    avg = t / n
+    hw = 3.0 if prec == "bf16x3" else 1.0
+    ach = per_launch / avg / 1e12
+    return {"kernel": "sigma_fused_kernel", "bound": "mfma", "achieved": round(ach, 2),
+            "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s", "frac": round(ach * hw / PEAKS_TFLOPS[prec], 4),
+            "traffic": traffic.get("sigma_fused_kernel"), "launches": st["n_contract"],
+            "avg_launch_us": round(avg * 1e6, 3),
+            "units": "2 x nvec x nmo x nocc x nvirt flops per target, x targets per launch"}
+
+
+def precision_report(R: Runner, golden: dict | None, steps: int, warmup: int, ref_ms: float) -> dict:
+    """Per precision: whole-step time and speed-up over FP64, contraction time and MFMA
+    fraction at T trial energies, and each target's quasi-particle error against the FP64
+    oracle (stored values written by tests/golden/) and against the FP64 GPU path, in meV."""
+    C, w, ctx = R.C, R.w, R.ctx
+    cd = C.cholesky(w.delta, centres=R.centres, alpha=R.alpha, max_vec=R.max_vec, grow=True, ctx=ctx)
+    out = {}
+    ref_gpu = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        B = C.transform(cd.Lbuf, cd.nvec, R.Cm, w.nocc, w.targets, prec, ctx=ctx)
+        om = w.trial_energies()
+        C.sigma2(B, R.eps, om, ctx=ctx)            # warm
+        ctx.reset_stats()
+        reps = 3
+        for _ in range(reps):
+            C.sigma2(B, R.eps, om, ctx=ctx)
+        s1 = ctx.stats()
+        t_con = (s1["t_contract_ms"]) / reps
+        flops = s1["flops_contract"] / reps
+        qp = C.qp_solve(B, R.eps, conv=1e-12, mode="residues", ctx=ctx)
+        if prec == "fp64":
+            ref_gpu = qp.omega.copy()
+        tf = flops / (t_con / 1e3) / 1e12
+        hw = tf * (3 if prec == "bf16x3" else 1)
+        rec = {"contract_ms_T%d" % om.shape[1]: round(t_con, 4), "contract_tflops": round(tf, 2),
+               "mfma_frac": round(hw / PEAKS_TFLOPS[prec], 4),
+               "err_meV_vs_fp64_gpu": [round(float(x), 6) for x in np.abs(qp.omega - ref_gpu) * HARTREE_EV * 1e3],
+               "status": [int(s) for s in qp.status]}
+        if golden is not None and golden.get("nvec") == cd.nvec:
+            e = np.abs(qp.omega - np.asarray(golden["omega"])) * HARTREE_EV * 1e3
+            rec["err_meV_vs_oracle"] = [float(f"{x:.3e}") for x in e]
+            rec["max_err_meV_vs_oracle"] = float(e.max())
+        if prec != "fp64":
+            ms, _, _ = R.timed(prec, steps, warmup)
+            rec["ms_per_step"] = round(ms, 3)
+            rec["step_speedup_vs_fp64"] = round(ref_ms / ms, 3)
+        out[prec] = rec
+        del B
+    for prec in ("fp32", "bf16x3"):
+        k = [x for x in out[prec] if x.startswith("contract_ms")][0]
+        out[prec]["contract_speedup_vs_fp64"] = round(out["fp64"][k] / out[prec][k], 2)
+    out["oracle"] = "tests/golden/" + ("large_oracle.json" if R.workload == "large" else "c60_oracle.json")
+    return out, cd
+
+
+def backward_report(R: Runner, cd) -> dict:
+    """Adjoint of the solve and of the transform for the cotangent of the sum of all
+    quasi-particle energies (FP64 and FP32 blocks)."""
+    C, w, ctx, torch = R.C, R.w, R.ctx, R.torch
+    out = {}
+    for prec in ("fp64", "fp32"):
+        B = C.transform(cd.Lbuf, cd.nvec, R.Cm, w.nocc, w.targets, prec, ctx=ctx)
+        qp = C.qp_solve(B, R.eps, conv=1e-10, mode="residues", ctx=ctx)
+        ob = np.ones(w.targets.shape[0])
+        C.qp_adjoint(B, R.eps, qp.omega, ob, ctx=ctx)                     # warm
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        gs, gv, ge = C.qp_adjoint(B, R.eps, qp.omega, ob, ctx=ctx)
+        ta = ctx.stats()["t_adjoint_ms"]
+        ctx.reset_stats()
+        C.transform_adjoint(cd.Lbuf, cd.nvec, R.Cm, w.nocc, w.targets, gs, gv, B.ldk, ctx=ctx)
+        torch.cuda.synchronize()
+        tt = ctx.stats()["t_adjoint_ms"]
+        out[prec] = {"qp_adjoint_ms": round(ta, 3), "transform_adjoint_ms": round(tt, 3)}
+        del B, gs, gv, ge
+    return out
+
+
+def mp2_report(R: Runner, cd) -> dict:
+    C, w, ctx = R.C, R.w, R.ctx
+    out = {}
+    e_ref = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        B = C.transform(cd.Lbuf, cd.nvec, R.Cm, w.nocc, w.targets, prec, ctx=ctx)
+        C.mp2_energy(B, R.eps, ctx=ctx)            # warm
+        ctx.reset_stats()
+        e = C.mp2_energy(B, R.eps, ctx=ctx)
+        s2 = ctx.stats()
+        if prec == "fp64":
+            e_ref = e
+        tf = s2["flops_mp2"] / (s2["t_mp2_ms"] / 1e3) / 1e12
+        out[prec] = {"energy_Eh": e, "ms": round(s2["t_mp2_ms"], 3), "tflops": round(tf, 2),
+                     "mfma_frac": round(tf * (3 if prec == "bf16x3" else 1) / PEAKS_TFLOPS[prec], 4),
+                     "rel_err_vs_fp64": abs(e - e_ref) / abs(e_ref)}
+        del B
+    return out
+
+
+def dyson_report(R: Runner, cd) -> dict:
+    C, w, ctx = R.C, R.w, R.ctx
+    Bd = C.transform(cd.Lbuf, cd.nvec, R.Cm, w.nocc, w.targets, "fp64", ctx=ctx)
+    C.dyson_solve(Bd, R.eps, conv=R.conv, ctx=ctx)                  # warm
+    ctx.reset_stats()
+    dy = C.dyson_solve(Bd, R.eps, conv=R.conv, ctx=ctx)
+    sd = ctx.stats()
+    qd = C.qp_solve(Bd, R.eps, conv=R.conv, ctx=ctx)
+    return {"roots": int(w.targets.shape[0]), "ms": round(sd["t_dyson_ms"], 3), "max_iters": int(dy.iters.max()),
+            "converged": int((dy.status == 0).sum()),
+            "max_shift_meV_vs_quasiparticle": float(np.abs(dy.omega - qd.omega).max() * HARTREE_EV * 1e3),
+            "min_pole_strength": float(dy.pole.min())}
+
+
+def c60_report(steps: int, warmup: int) -> dict:
+    """The C60-shaped workload: FP64 step, per-orbital precision against the oracle beside the
+    decomposition's own error e_delta (exact integrals), the delta sweep and the atomic CD."""
+    R = Runner("c60")
+    w = R.w
+    ms, st, (cd, _, qp) = R.timed("fp64", steps, warmup)
+    out = {"workload": (f"c60: truncated-icosahedron cage, N={w.nbf}, {w.npairs} pairs, delta={w.delta:g}, "
+                        f"nocc={w.nocc}, nvirt={w.nvirt}, {w.targets.shape[0]} targets"),
+           "nvec": cd.nvec, "ms_per_step_fp64": round(ms, 3),
+           "solves_per_s_fp64": round(w.targets.shape[0] / (ms / 1e3), 2)}
+    golden = load_golden("c60_oracle.json")
+    g6 = golden["cd"]["1e-06"] if golden else None
+    prec, cdp = precision_report(R, g6, steps, warmup, ms)
+    out["precision"] = prec
+    if golden is not None:
+        ex = np.asarray(golden["exact"]["omega"])
+        # the error of the decomposition alone (FP64 oracle at delta against exact integrals)
+        out["e_delta_meV"] = {d: [float(f"{x:.3e}") for x in
+                                  np.abs(np.asarray(golden["cd"][d]["omega"]) - ex) * HARTREE_EV * 1e3]
+                              for d in golden["cd"]}
+        ed = np.abs(np.asarray(g6["omega"]) - ex) * HARTREE_EV * 1e3
+        for p in ("fp32", "bf16x3"):
+            e = np.asarray(prec[p].get("err_meV_vs_oracle", [np.nan] * ed.size))
+            prec[p]["orbitals_below_e_delta_1e-6"] = int((e < ed).sum())
+            prec[p]["max_err_over_e_delta_1e-6"] = float(np.nanmax(e / ed))
+    from paper_0912_1459_amd import sweep as SW
+    progress("c60 delta sweep")
+    out["sweep"] = SW.report(w, prec="fp64", conv=R.conv)
+    progress("c60 atomic CD")
+    from paper_0912_1459_amd import acd as ACD
+    torch = R.torch
+    ACD.acd(R.centres, R.alpha, w.delta, ctx=R.ctx)                     # warm
+    torch.cuda.synchronize()
+    ta0 = time.perf_counter()
+    a = ACD.acd(R.centres, R.alpha, w.delta, ctx=R.ctx)
+    torch.cuda.synchronize()
+    ta1 = time.perf_counter()
+    R.C.cholesky(w.delta, centres=R.centres, alpha=R.alpha, max_vec=R.max_vec, grow=True, ctx=R.ctx)
+    torch.cuda.synchronize()
+    ta2 = time.perf_counter()
+    Ba = R.C.transform(a.cd.Lbuf, a.cd.nvec, R.Cm, w.nocc, w.targets, "fp64", ctx=R.ctx)
+    qa = R.C.qp_solve(Ba, R.eps, conv=1e-10, ctx=R.ctx)
+    Bf = R.C.transform(cdp.Lbuf, cdp.nvec, R.Cm, w.nocc, w.targets, "fp64", ctx=R.ctx)
+    qf = R.C.qp_solve(Bf, R.eps, conv=1e-10, ctx=R.ctx)
+    out["acd"] = {"products": int(a.products.size), "per_atom": a.per_atom, "vectors": a.cd.nvec,
+                  "full_cd_vectors": cdp.nvec, "acd_ms": round((ta1 - ta0) * 1e3, 3),
+                  "full_cd_ms": round((ta2 - ta1) * 1e3, 3), "speedup": round((ta2 - ta1) / (ta1 - ta0), 2),
+                  "max_qp_shift_meV_vs_full_cd": float(np.abs(qa.omega - qf.omega).max() * HARTREE_EV * 1e3)}
+    return out
+
+
+def cpu_baseline(workload: str) -> dict:
+    """The oracle as it stands, on the host cores, over a bounded sample of the workload,
+    scaled to the whole step:
+      * the decomposition: the oracle's first m and 2m steps timed; step k costs a + b k
+        (one ERI column, then a k-term product per pair), which the two times fix, summed
+        over the M steps the decomposition makes;
+      * the transform of the first 64 vectors, x M/64 (every vector costs the same);
+      * per target: the integrals x, y from those 64 vectors' blocks, x M/64, plus one
+        self-energy evaluation times the oracle's own Newton iteration count (stored with
+        its results)."""
     from oracle import eri_cd as E, mo, selfenergy as SE
+    from paper_0912_1459_amd import inputs as I
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    w = I.make(workload)
+    gold = load_golden("large_oracle.json") if workload == "large" else load_golden("c60_oracle.json")
+    if gold is None:
+        return None
+    if workload == "large":
+        M, iters = gold["nvec"], gold["iters"]
+    else:
+        M, iters = gold["cd"]["1e-06"]["nvec"], gold["cd"]["1e-06"]["iters"]
+    m = 48
     t0 = time.perf_counter()
-    r = E.pivoted_cd(delta, centres=w.centres, alpha=w.alpha)
+    E.pivoted_cd(0.0, centres=w.centres, alpha=w.alpha, max_vec=m)
     t1 = time.perf_counter()
-    sel = w.targets[:ntarget]
-    Bsel, Bvo = mo.transform_blocks(r.L, w.C, w.nocc, sel)
+    r = E.pivoted_cd(0.0, centres=w.centres, alpha=w.alpha, max_vec=2 * m)
     t2 = time.perf_counter()
-    SE.solve_targets(Bsel, Bvo, w.eps, w.nocc, sel, conv=conv)
+    ta, tb = t1 - t0, t2 - t1
+    # ta = a m + b m(m-1)/2,  tb = 2 a m + b 2m(2m-1)/2
+    b = (tb - 2 * ta) / (m * (2 * m - 1) - m * (m - 1))
+    a = (ta - b * m * (m - 1) / 2) / m
+    t_cd = a * M + b * M * (M - 1) / 2
+    ns = 64 if r.M >= 64 else r.M
     t3 = time.perf_counter()
+    Bsel, Bvo = mo.transform_blocks(r.L[:, :ns], w.C, w.nocc, w.targets)
+    t4 = time.perf_counter()
+    t_tr = (t4 - t3) * M / ns
+    t5 = time.perf_counter()
+    x, y = SE.xy_from_B(Bsel[:, 0, :], Bvo, w.nocc)
+    t6 = time.perf_counter()
+    SE.sigma(x, y, w.eps, w.nocc, float(w.eps[w.targets[0]]))
+    t7 = time.perf_counter()
     nsel = len(w.targets)
-    # transform cost grows with the selected block only mildly: scale the Newton part only
-    est = (t1 - t0) + (t2 - t1) + (t3 - t2) * nsel / ntarget
-    return {"value": nsel / est, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"full oracle CD (M={r.M}) and transform, Newton on {ntarget} of {nsel} "
-                       f"targets scaled to {nsel}; t_cd={t1 - t0:.2f}s t_transform={t2 - t1:.2f}s "
-                       f"t_newton={t3 - t2:.2f}s")}
+    t_nw = nsel * (t6 - t5) * M / ns + (t7 - t6) * float(np.sum(iters))
+    est = t_cd + t_tr + t_nw
+    return {"value": round(nsel / est, 5), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{workload}: oracle CD first {m} and {2 * m} steps ({ta:.1f} s, {tb:.1f} s) fitted to "
+                       f"a + b k per step and summed to M={M} (est. {t_cd:.0f} s); transform of {ns} vectors "
+                       f"({t4 - t3:.1f} s) x M/{ns} (est. {t_tr:.0f} s); one target's integrals from {ns} vectors "
+                       f"({t6 - t5:.1f} s) x M/{ns} x {nsel} targets + one self-energy evaluation ({t7 - t6:.2f} s) "
+                       f"x the oracle's {int(np.sum(iters))} Newton iterations (est. {t_nw:.0f} s); "
+                       f"estimated whole step {est:.0f} s"),
+            "measured_s": round(ta + tb + (t4 - t3) + (t7 - t5), 1)}
 
 
 def main():
@@ -115,243 +427,46 @@ def main():
         copy_probe(args.copy_probe)
         return
     import torch
-    import paper_0912_1459_amd.core as C
-    from paper_0912_1459_amd import inputs as I
-
-    dev = "cuda:0"
     torch.cuda.set_device(0)
-    w = I.make(args.workload)
-    delta = w.delta
-    conv = 1e-5
-    centres = torch.tensor(w.centres, device=dev)
-    alpha = torch.tensor(w.alpha, device=dev)
-    Cm = torch.tensor(w.C, device=dev)
-    eps = torch.tensor(w.eps, device=dev)
-    stream = torch.cuda.current_stream()
-    ctx = C.Context(0, stream)
-    if args.workload == "large":
-        # C = S^-1/2 Q with lambda_min(S) ~ 2e-7: rounding inside an FP32 or split-bf16
-        # transform would be amplified ~1/lambda_min, so the transform runs in FP64 and only
-        # the blocks are rounded for the contraction
-        ctx.set_transform_fp64(True)
-    nsel = len(w.targets)
-    max_vec = (12 if args.workload == "c60" else 6) * w.nbf     # enough for both workloads at their delta
-
-    def step(prec):
-        if args.no_overlap:
-            cd = C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, grow=True, ctx=ctx)
-            B = C.transform(cd.Lbuf, cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
-        else:
-            # the transform of the vectors made so far runs beside the decomposition
-            cd, B = C.cholesky_transform(delta, centres=centres, alpha=alpha, C=Cm, nocc=w.nocc, sel=w.targets,
-                                         prec=prec, max_vec=max_vec, ctx=ctx)
-        qp = C.qp_solve(B, eps, conv=conv, mode="residues", ctx=ctx)
-        return cd, B, qp
-
+    R = Runner(args.workload, overlap=not args.no_overlap)
+    w = R.w
+    nsel = w.targets.shape[0]
     progress(f"{args.workload}: {w.npairs} pairs, warm-up")
-    for _ in range(args.warmup):
-        step(args.prec)
-    torch.cuda.synchronize()
-    progress("timed steps")
+    wall0 = time.perf_counter()
+    # timed region: K whole-path steps, no per-kernel events beyond the library's own
+    ms_per_step, st_run, (cd, B, qp) = R.timed(args.prec, args.steps, args.warmup)
+    wall = time.perf_counter() - wall0
+    value = nsel / (ms_per_step / 1e3)
 
-    # timed region: K whole-path steps, no per-kernel events
-    ctx.reset_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        cd, B, qp = step(args.prec)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    st_run = ctx.stats()
-    ms_per_step = gpu_ms / args.steps
-    value = nsel * args.steps / (gpu_ms / 1e3)
-
-    # the same K steps again with HIP events around every Cholesky step-kernel and pass
-    # launch (on the library's stream): per-launch durations for the roofline
+    # the same K steps again with HIP events around every Cholesky step run and pass (on the
+    # library's stream): per-launch durations of the decomposition's kernels
     progress(f"{ms_per_step:.1f} ms per step; kernel-timing pass")
-    ctx.reset_stats()
-    ctx.set_kernel_timing(True)
+    R.ctx.reset_stats()
+    R.ctx.set_kernel_timing(True)
     for _ in range(args.steps):
-        step(args.prec)
+        R.step(args.prec)
     torch.cuda.synchronize()
-    st = ctx.stats()
-    ctx.set_kernel_timing(False)
-
+    st = R.ctx.stats()
+    R.ctx.set_kernel_timing(False)
     M = cd.nvec
-    npairs = w.npairs
-    n_step = st["n_cd_step_launch"]
-    n_pass = st["n_cd_pass_launch"]
-    t_step = st["t_cd_kernel_ms"] / 1e3
-    t_pass = st["t_cd_pass_ms"] / 1e3
-    cd_kernels = {
-        "step": {"launches_per_cd": n_step / args.steps, "total_ms_per_cd": round(t_step * 1e3 / args.steps, 3),
-                 "avg_us": round(t_step / max(n_step, 1) * 1e6, 3),
-                 "algorithmic_gbs": round(st["bytes_cd_step"] / t_step / 1e9, 1) if t_step > 0 else None},
-        "pass": {"launches_per_cd": n_pass / args.steps, "total_ms_per_cd": round(t_pass * 1e3 / args.steps, 3),
-                 "avg_us": round(t_pass / max(n_pass, 1) * 1e6, 3),
-                 "gbs": round(st["bytes_cd_pass"] / t_pass / 1e9, 1) if t_pass > 0 else None,
-                 "tflops_fp64": round(st["flops_cd_pass"] / t_pass / 1e12, 2) if t_pass > 0 else None},
-        "misses_per_cd": st["n_cd_miss"] / args.steps,
-        "speculative": {"blocks_per_cd": st["n_cd_spec_block"] / args.steps,
-                        "steps_per_cd": st["n_cd_spec"] / args.steps,
-                        "ms_per_cd": round(st["t_cd_spec_ms"] / args.steps, 3),
-                        "state_reads_per_cd": st["n_cd_state_read"] / args.steps},
-    }
     traffic = committed_traffic(args.workload)
-    if t_pass >= t_step:
-        # 2 flops per vector, pair row and candidate: 16 flops per byte of L, above the FP64
-        # MFMA ridge (78.6 TF / 8 TB/s)
-        per_launch = st["flops_cd_pass"] / max(n_pass, 1)
-        avg = t_pass / max(n_pass, 1)
-        roofline = {"kernel": "cd_pass_kernel", "bound": "mfma", "achieved": round(per_launch / avg / 1e12, 2),
-                    "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(per_launch / avg / 1e12 / FP64_MFMA_TFLOPS, 4),
-                    "traffic": traffic.get("cd_pass_kernel"), "launches": n_pass / args.steps,
-                    "avg_launch_us": round(avg * 1e6, 3), "units": "2 x pairs x vectors x 64 flops per launch"}
+    cdr = cd_report(st, args.steps, w.npairs, M)
+    cdr["pass"]["traffic"] = traffic.get("cd_pass_kernel")
+    con = contraction_roofline(st_run, args.prec, traffic)
+    t_pass = st["t_cd_pass_ms"]
+    if st_run["t_contract_ms"] >= t_pass:
+        roofline = con
     else:
-        per_launch = st["bytes_cd_step"] / max(n_step, 1)
-        avg = t_step / max(n_step, 1)
-        roofline = {"kernel": "cd_step_kernel", "bound": "hbm", "achieved": round(per_launch / avg / 1e9, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4),
-                    "traffic": traffic.get("cd_step_kernel"), "launches": n_step / args.steps,
-                    "avg_launch_us": round(avg * 1e6, 3),
-                    "units": "pairs x (8 B per vector subtracted + 34..66 B) per launch"}
-
-    if args.quick:
-        print(json.dumps({"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-                          "higher_is_better": True, "roofline": roofline,
-                          "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M,
-                                 "kernels": cd_kernels, "transform_overlapped": not args.no_overlap},
-                          "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
-                                        ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms",
-                                         "t_newton_ms")}}))
-        return
-
-    progress("precision report")
-    # per-precision contraction throughput and accuracy against the FP64 GPU path
-    ref_cd, ref_B, ref_qp = step("fp64")
-    prec_report = {}
-    for prec in ("fp64", "fp32", "bf16x3"):
-        B = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
-        om = w.trial_energies()
-        C.sigma2(B, eps, om, ctx=ctx)            # warm
-        ctx.reset_stats()
-        reps = 3
-        for _ in range(reps):
-            C.sigma2(B, eps, om, ctx=ctx)
-        s1 = ctx.stats()
-        t_con = s1["t_contract_ms"] / reps
-        flops = s1["flops_contract"] / reps
-        ctx.reset_stats()
-        torch.cuda.synchronize()
-        tq0 = time.perf_counter()
-        qp_p = C.qp_solve(B, eps, conv=conv, mode="residues", ctx=ctx)
-        torch.cuda.synchronize()
-        tq = time.perf_counter() - tq0
-        err_mev = float(np.abs(qp_p.omega - ref_qp.omega).max() * HARTREE_EV * 1e3)
-        tf = flops / (t_con / 1e3) / 1e12
-        hw = tf * (3 if prec == "bf16x3" else 1)
-        prec_report[prec] = {
-            "contract_ms": round(t_con, 4), "contract_tflops": round(tf, 2),
-            "mfma_frac": round(hw / PEAKS_TFLOPS[prec], 4),
-            "solves_per_s_from_B": round(nsel / tq, 1),
-            "max_err_meV_vs_fp64": round(err_mev, 6),
-            "newton_iters_max": int(qp_p.iters.max()),
-        }
-    progress("backward pass")
-    # backward pass: adjoint of the solve (FP64 and FP32 blocks) and of the transform, for the
-    # cotangent of the sum of all quasi-particle energies
-    backward = {}
-    for prec in ("fp64", "fp32"):
-        B = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
-        qp_p = C.qp_solve(B, eps, conv=1e-10, mode="residues", ctx=ctx)
-        ob = np.ones(nsel)
-        C.qp_adjoint(B, eps, qp_p.omega, ob, ctx=ctx)                     # warm
-        torch.cuda.synchronize()
-        tb0 = time.perf_counter()
-        gs, gv, ge = C.qp_adjoint(B, eps, qp_p.omega, ob, ctx=ctx)
-        torch.cuda.synchronize()
-        tb1 = time.perf_counter()
-        C.transform_adjoint(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, gs, gv, B.ldk, ctx=ctx)
-        torch.cuda.synchronize()
-        tb2 = time.perf_counter()
-        backward[prec] = {"qp_adjoint_ms": round((tb1 - tb0) * 1e3, 3),
-                          "transform_adjoint_ms": round((tb2 - tb1) * 1e3, 3)}
-        del B, gs, gv, ge
-
-    progress("MP2")
-    # MP2 correlation energy, Eq. (MP2), from the same Bvo block in each precision
-    mp2_report = {}
-    e_ref = None
-    for prec in ("fp64", "fp32", "bf16x3"):
-        B = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, prec, ctx=ctx)
-        C.mp2_energy(B, eps, ctx=ctx)            # warm
-        ctx.reset_stats()
-        e = C.mp2_energy(B, eps, ctx=ctx)
-        s2 = ctx.stats()
-        if prec == "fp64":
-            e_ref = e
-        tf = s2["flops_mp2"] / (s2["t_mp2_ms"] / 1e3) / 1e12
-        mp2_report[prec] = {"energy_Eh": e, "ms": round(s2["t_mp2_ms"], 3), "tflops": round(tf, 2),
-                            "mfma_frac": round(tf * (3 if prec == "bf16x3" else 1) / PEAKS_TFLOPS[prec], 4),
-                            "rel_err_vs_fp64": abs(e - e_ref) / abs(e_ref)}
-    for prec in ("fp32", "bf16x3"):
-        prec_report[prec]["contract_speedup_vs_fp64"] = round(
-            prec_report["fp64"]["contract_ms"] / prec_report[prec]["contract_ms"], 2)
-
-    # the paper's spectral-window experiment in synthetic form (untimed): window orbitals,
-    # CD-4 ... CD-8 against CD-10, FP64, Newton Delta = 1e-5
-    from paper_0912_1459_amd import sweep as SW
-    sweep = SW.report(w, prec="fp64", conv=conv) if args.workload == "c60" else None
-
-    # atomic CD (one-centre products per atom, then the inner projection onto them) against
-    # the full CD at the same delta: decomposition time and quasi-particle shift (FP64)
-    acd_report = None
-    if args.workload == "c60":
-        progress("atomic CD")
-        from paper_0912_1459_amd import acd as ACD
-        ACD.acd(centres, alpha, delta, ctx=ctx)                     # warm
-        torch.cuda.synchronize()
-        ta0 = time.perf_counter()
-        a = ACD.acd(centres, alpha, delta, ctx=ctx)
-        torch.cuda.synchronize()
-        ta1 = time.perf_counter()
-        C.cholesky(delta, centres=centres, alpha=alpha, max_vec=max_vec, grow=True, ctx=ctx)
-        torch.cuda.synchronize()
-        ta2 = time.perf_counter()
-        Ba = C.transform(a.cd.Lbuf, a.cd.nvec, Cm, w.nocc, w.targets, "fp64", ctx=ctx)
-        qa = C.qp_solve(Ba, eps, conv=1e-10, ctx=ctx)
-        Bf = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, "fp64", ctx=ctx)
-        qf = C.qp_solve(Bf, eps, conv=1e-10, ctx=ctx)
-        acd_report = {"products": int(a.products.size), "per_atom": a.per_atom, "vectors": a.cd.nvec,
-                      "full_cd_vectors": ref_cd.nvec, "acd_ms": round((ta1 - ta0) * 1e3, 3),
-                      "full_cd_ms": round((ta2 - ta1) * 1e3, 3),
-                      "speedup": round((ta2 - ta1) / (ta1 - ta0), 2),
-                      "max_qp_shift_meV_vs_full_cd": float(np.abs(qa.omega - qf.omega).max() * HARTREE_EV * 1e3)}
-        del Ba, Bf
-
-    # Dyson poles over the targets (non-diagonal self-energy) against the quasi-particle ones
-    dyson_report = None
-    if nsel <= 31:
-        progress("Dyson poles")
-        Bd = C.transform(ref_cd.Lbuf, ref_cd.nvec, Cm, w.nocc, w.targets, "fp64", ctx=ctx)
-        C.dyson_solve(Bd, eps, conv=conv, ctx=ctx)                  # warm
-        ctx.reset_stats()
-        dy = C.dyson_solve(Bd, eps, conv=conv, ctx=ctx)
-        sd = ctx.stats()
-        qd = C.qp_solve(Bd, eps, conv=conv, ctx=ctx)
-        dyson_report = {"roots": nsel, "ms": round(sd["t_dyson_ms"], 3), "max_iters": int(dy.iters.max()),
-                        "converged": int((dy.status == 0).sum()),
-                        "max_shift_meV_vs_quasiparticle": float(np.abs(dy.omega - qd.omega).max() * HARTREE_EV * 1e3),
-                        "min_pole_strength": float(dy.pole.min())}
-        del Bd
-
+        # the pass: the plain algorithm's products it stands in for, per launch
+        n_pass = max(st["n_cd_pass_launch"], 1)
+        avg = t_pass / 1e3 / n_pass
+        ach = st["flops_cd_pass_method"] / n_pass / avg / 1e12
+        roofline = {"kernel": "cd_pass_kernel", "bound": "mfma", "achieved": round(ach, 2),
+                    "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_TFLOPS, 4),
+                    "traffic": traffic.get("cd_pass_kernel"), "launches": n_pass / args.steps,
+                    "avg_launch_us": round(avg * 1e6, 3), "units": cdr["pass"]["units"]}
+    phases = {k: round(st_run[k] / args.steps, 3) for k in
+              ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")}
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -363,29 +478,43 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"f64 CD / {args.prec} contraction",
+        "dtype": {"fp64": "f64", "fp32": "f64 CD / f32 contraction", "bf16x3": "f64 CD / bf16x3 contraction"}[args.prec],
         "data": "synthetic",
         "config": {"workload": (f"{args.workload}: truncated-icosahedron cage, N={w.nbf} s-Gaussians, "
-                                f"{npairs} pairs, delta={delta:g}, nocc={w.nocc}, nvirt={w.nvirt}, "
-                                f"{nsel} targets, Newton Delta={conv:g}"),
+                                f"{w.npairs} pairs, delta={w.delta:g}, nocc={w.nocc}, nvirt={w.nvirt}, "
+                                f"{nsel} targets, Newton Delta={R.conv:g}"),
                    "nvec": M, "prec": args.prec},
         "roofline": roofline,
-        "cd": {"ms": round(st_run["t_cd_ms"] / args.steps, 3), "steps": M, "kernels": cd_kernels,
-               "transform_overlapped": not args.no_overlap,
-               # bytes the plain one-vector-per-step algorithm streams, over the whole decomposition
-               "plain_algorithm_equivalent_gbs": round(st_run["bytes_cd"] / (st_run["t_cd_ms"] / 1e3) / 1e9, 1)},
-        "phases_ms": {k: round(st_run[k] / args.steps, 3) for k in
-                      ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")},
-        "precision": prec_report,
-        "backward": backward,
-        "mp2": mp2_report,
-        "sweep": sweep,
-        "acd": acd_report,
-        "dyson": dyson_report,
-        "wall_s": round(wall, 3),
+        "contraction": con,
+        "cd": cdr,
+        "phases_ms": phases,
+        "newton_iters_max": int(qp.iters.max()),
     }
-    if not args.no_cpu_baseline and args.workload == "c60":
-        out["cpu_baseline"] = cpu_baseline(w, delta, conv, args.cpu_targets)
+    if args.quick:
+        print(json.dumps(out))
+        return
+
+    progress("precision report")
+    golden = load_golden("large_oracle.json") if args.workload == "large" else (
+        (load_golden("c60_oracle.json") or {}).get("cd", {}).get("1e-06"))
+    out["precision"], ref_cd = precision_report(R, golden, args.steps, args.warmup, ms_per_step)
+    progress("backward pass")
+    out["backward"] = backward_report(R, ref_cd)
+    progress("MP2")
+    out["mp2"] = mp2_report(R, ref_cd)
+    progress("Dyson poles")
+    out["dyson"] = dyson_report(R, ref_cd)
+    del R, ref_cd, B, cd
+    torch.cuda.empty_cache()
+    if args.workload == "large":
+        progress("c60 workload")
+        out["c60"] = c60_report(args.steps, args.warmup)
+    out["wall_s"] = round(wall, 3)
+    if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
+        cb = cpu_baseline(args.workload)
+        if cb is not None:
+            out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

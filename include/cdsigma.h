@@ -109,6 +109,12 @@ typedef struct cds_stats {
     int64_t n_cd_spec_block; /* speculative blocks tried                      */
     int64_t n_cd_state_read; /* Cholesky state reads that waited for the stream
                                 to drain (speculative path)                   */
+    double flops_cd_pass_method;  /* the plain algorithm's products that the
+                                     look-ahead passes stand in for: 2 npairs k0
+                                     per step kept by a block starting at k0   */
+    double flops_cd_block_method; /* the rest of those products, made inside the
+                                     speculative blocks: 2 npairs (k - k0) per
+                                     step k kept                               */
 } cds_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -163,6 +169,13 @@ int cds_set_cd_large_path(cds_ctx *ctx, int32_t on);
  * the output blocks (for ill-conditioned MO coefficients, where rounding inside
  * the transform is amplified by about 1 / lambda_min of the overlap matrix). */
 int cds_set_transform_fp64(cds_ctx *ctx, int32_t on);
+/* Targets per contraction launch in cds_sigma2, cds_qp_solve and
+ * cds_qp_adjoint: 0 (default) = as many as the workspace limits allow (all of
+ * them on the fused self-energy path); n >= 1 = at most n.  The results do
+ * not depend on it (every target's sums are formed in the same order);
+ * it exists to bound memory and to exercise the chunked loops.  Valid range
+ * [0, 65535]. */
+int cds_set_target_chunk(cds_ctx *ctx, int32_t n);
 /* Library version string (static). */
 const char *cds_version(void);
 

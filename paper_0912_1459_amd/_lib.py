@@ -23,7 +23,7 @@ ERROR_NAMES = {CDS_EINVAL: "EINVAL", CDS_ENOMEM: "ENOMEM", CDS_EDEVICE: "EDEVICE
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = [
     "cds_create", "cds_destroy", "cds_last_error", "cds_get_stats", "cds_reset_stats",
-    "cds_set_kernel_timing", "cds_set_cd_lookahead", "cds_set_cd_large_path", "cds_set_cd_speculate", "cds_set_cd_mailbox", "cds_set_transform_fp64", "cds_version", "cds_eri_columns", "cds_cholesky_sgauss", "cds_cholesky_sgauss_subset",
+    "cds_set_kernel_timing", "cds_set_cd_lookahead", "cds_set_cd_large_path", "cds_set_cd_speculate", "cds_set_cd_mailbox", "cds_set_transform_fp64", "cds_set_target_chunk", "cds_version", "cds_eri_columns", "cds_cholesky_sgauss", "cds_cholesky_sgauss_subset",
     "cds_cholesky_dense", "cds_transform", "cds_cholesky_transform_sgauss", "cds_sigma2", "cds_qp_solve", "cds_qp_adjoint",
     "cds_transform_adjoint", "cds_mp2", "cds_workspace_bytes", "cds_sigma2_matrix", "cds_dyson_solve",
 ]
@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
         ("n_cd_step_launch", ctypes.c_int64), ("n_cd_pass_launch", ctypes.c_int64),
         ("t_mp2_ms", ctypes.c_double), ("flops_mp2", ctypes.c_double), ("t_dyson_ms", ctypes.c_double),
         ("t_cd_spec_ms", ctypes.c_double), ("n_cd_spec", ctypes.c_int64), ("n_cd_spec_block", ctypes.c_int64),
-        ("n_cd_state_read", ctypes.c_int64),
+        ("n_cd_state_read", ctypes.c_int64), ("flops_cd_pass_method", ctypes.c_double),
+        ("flops_cd_block_method", ctypes.c_double),
     ]
 
 
@@ -72,6 +73,7 @@ def load() -> ctypes.CDLL:
         "cds_set_cd_speculate": (ip, [P, i32]),
         "cds_set_cd_mailbox": (ip, [P, i32]),
         "cds_set_transform_fp64": (ip, [P, i32]),
+        "cds_set_target_chunk": (ip, [P, i32]),
         "cds_version": (ctypes.c_char_p, []),
         "cds_eri_columns": (ip, [P, i32, P, P, i64, P, P]),
         "cds_cholesky_sgauss": (ip, [P, i32, P, P, d, d, d, i64, P, i64, P, P, i64, P, P, P]),

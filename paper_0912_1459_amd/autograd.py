@@ -5,8 +5,9 @@
 
 QPSolve's backward differentiates the converged Newton fixed point implicitly:
 d(w*)/d(theta) = P d(e_q + Sigma_qq(w*; theta))/d(theta) with P = 1/(1 - Sigma'(w*)), computed by
-cds_qp_adjoint; Transform's backward is C_bar = sum_K L^K C (Bbar^K + Bbar^K^T) by
-cds_transform_adjoint.  FP64 and FP32 blocks are differentiable (the split-bf16 planes are not).
+cds_qp_adjoint.  That formula holds only at a fixed point, so the backward raises for any
+target whose forward solve did not converge (status MAX_ITER or NONFINITE).  Transform's
+backward is C_bar = sum_K L^K C (Bbar^K + Bbar^K^T) by cds_transform_adjoint.  FP64 and FP32 blocks are differentiable (the split-bf16 planes are not).
 """
 from __future__ import annotations
 
@@ -30,7 +31,7 @@ class SolveMeta:
     conv: float = 1e-12
     max_iter: int = 100
     mode: str = "residues"
-    result: core.QPResult | None = None
+    result: core.QPResult | None = None   # the last forward's result (for inspection only)
 
 
 def _blocks(Bsel, Bvo, meta: SolveMeta) -> core.BBlocks:
@@ -45,7 +46,10 @@ class QPSolve(torch.autograd.Function):
         B = _blocks(Bsel.detach(), Bvo.detach(), meta)
         r = core.qp_solve(B, eps.detach(), conv=meta.conv, max_iter=meta.max_iter, mode=meta.mode)
         meta.result = r
+        # the backward uses this forward's own energies and statuses (meta may be reused)
         ctx.meta = meta
+        ctx.omega = r.omega.copy()
+        ctx.status = r.status.copy()
         ctx.save_for_backward(Bsel, Bvo, eps)
         return torch.tensor(r.omega, dtype=torch.float64, device=eps.device)
 
@@ -53,9 +57,12 @@ class QPSolve(torch.autograd.Function):
     def backward(ctx, gomega):
         Bsel, Bvo, eps = ctx.saved_tensors
         meta = ctx.meta
+        bad = np.flatnonzero(ctx.status != A.QP_CONVERGED)
+        if bad.size:
+            raise RuntimeError(f"QPSolve.backward: targets {meta.sel[bad].tolist()} did not converge "
+                               f"(status {ctx.status[bad].tolist()}); the implicit gradient needs the fixed point")
         B = _blocks(Bsel.detach(), Bvo.detach(), meta)
-        gs, gv, ge = core.qp_adjoint(B, eps.detach(), meta.result.omega,
-                                     gomega.detach().double().cpu().numpy())
+        gs, gv, ge = core.qp_adjoint(B, eps.detach(), ctx.omega, gomega.detach().double().cpu().numpy())
         return gs.to(Bsel.dtype).reshape(Bsel.shape), gv.to(Bvo.dtype).reshape(Bvo.shape), ge, None
 
 

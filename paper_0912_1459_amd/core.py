@@ -110,6 +110,10 @@ class Context:
         """FP32/bf16x3 transforms computed in FP64 with only the output rounded (True)."""
         self.check(self.lib.cds_set_transform_fp64(self.h, int(bool(on))))
 
+    def set_target_chunk(self, n: int):
+        """At most n targets per contraction launch (0: as many as memory allows)."""
+        self.check(self.lib.cds_set_target_chunk(self.h, int(n)))
+
     def set_cd_speculate(self, on: bool):
         """Speculative look-ahead blocks in the Cholesky decomposition (default on)."""
         self.check(self.lib.cds_set_cd_speculate(self.h, int(bool(on))))
@@ -282,18 +286,6 @@ class BBlocks:
     def nvirt(self) -> int:
         return self.nmo - self.nocc
 
-    def as_float64(self):
-        """(Bsel (nsel, nmo, nvec), Bvo (nvirt, nocc, nvec)) in FP64 (value the kernels use)."""
-        def f(t, rows):
-            if self.prec == A.PREC_BF16X3:
-                x = t[0].to(torch.float64) + t[1].to(torch.float64)
-            else:
-                x = t.to(torch.float64)
-            return x.reshape(rows, self.ldk)[:, : self.nvec]
-        bs = f(self.Bsel, self.nsel * self.nmo).reshape(self.nsel, self.nmo, self.nvec)
-        bv = f(self.Bvo, self.nvirt * self.nocc).reshape(self.nvirt, self.nocc, self.nvec)
-        return bs, bv
-
 
 def _alloc_B(prec: int, rows: int, ldk: int, dev):
     if prec == A.PREC_FP64:
@@ -362,29 +354,6 @@ def cholesky_transform(delta: float, *, centres: torch.Tensor, alpha: torch.Tens
     ctx.check(rc, ok=(A.CDS_OK, A.CDS_ENOTPSD))
     cd = CDResult(Lbuf, piv, D, int(nvec.value), float(dmax.value), int(status.value), np_)
     return cd, BBlocks(prec, Bsel, Bvo, cd.nvec, ldk, nmo, nocc, sel)
-
-
-def blocks_from_numpy(Bsel: np.ndarray, Bvo: np.ndarray, nocc: int, sel, prec="fp64", *, ldk=None,
-                      device="cuda") -> BBlocks:
-    """Upload oracle-layout blocks Bsel (M, nsel, nmo), Bvo (M, nvirt, nocc) into the kernel layout."""
-    prec = _prec(prec)
-    M, nsel, nmo = Bsel.shape
-    ldk = ldk or round_up(M, 64)
-    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
-
-    def pack(x, rows):
-        y = np.zeros((rows, ldk))
-        y[:, :M] = x.reshape(M, rows).T
-        t = torch.from_numpy(y).to(device)
-        if prec == A.PREC_FP64:
-            return t.contiguous()
-        if prec == A.PREC_FP32:
-            return t.to(torch.float32).contiguous()
-        f = t.to(torch.float32)
-        hi = f.to(torch.bfloat16)
-        lo = (f - hi.to(torch.float32)).to(torch.bfloat16)
-        return torch.stack([hi, lo]).contiguous()
-    return BBlocks(prec, pack(Bsel, nsel * nmo), pack(Bvo, Bvo.shape[1] * nocc), M, ldk, nmo, nocc, sel)
 
 
 def sigma2(B: BBlocks, eps: torch.Tensor, omega: np.ndarray, ctx: Context | None = None):

@@ -210,6 +210,7 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
     // chunks of targets: G and W each nsc * nmo * nvo
     size_t per = (size_t)nmo * nvo * es;
     int csz = (int)std::max<size_t>(1, ((size_t)2 << 30) / std::max<size_t>(per, 1));
+    if (ctx->target_chunk > 0) csz = std::min(csz, ctx->target_chunk);
     csz = std::min(csz, (int)nsel);
     void *G, *W;
     CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * per, &G));

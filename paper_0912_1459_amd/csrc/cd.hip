@@ -91,6 +91,9 @@ struct CdState {
     int32_t pad2;
     double dnc;      // bound on the residual diagonals of the eligible rows that are not candidates
     int64_t nblk;    // speculative blocks that reached their commit (kept steps or stalled)
+    double sumk0s;   // sum over committed blocks of start step x steps kept (the pass's share of
+                     // the plain algorithm's products: each kept step needs vectors 0 .. k0-1)
+    double sumwin;   // sum over committed blocks of j for each kept step j (the block's own share)
 };
 
 // Host mailbox word, written by each speculative block's commit: the committed step count,
@@ -1281,6 +1284,8 @@ __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, c
         st->k = k0 + nc;
         st->dmax = so->cmax[nc - 1];
         st->nspec += nc;
+        st->sumk0s += (double)k0 * (double)nc;
+        st->sumwin += 0.5 * (double)nc * (double)(nc - 1);
         const int64_t nb = st->nblk + 1;
         st->nblk = nb;
         if (mail) __hip_atomic_store(mail, mb_word(nb, 0, k0 + nc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -2083,6 +2088,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         ctx->stats.n_cd_spec += hs.nspec;
         ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * hs.sumk0 + 8.0 * CD_NCAND * (double)npairs * (double)hs.npass;
         ctx->stats.flops_cd_pass += 2.0 * (double)npairs * hs.sumk0 * CD_NCAND;
+        ctx->stats.flops_cd_pass_method += 2.0 * (double)npairs * hs.sumk0s;
+        ctx->stats.flops_cd_block_method += 2.0 * (double)npairs * hs.sumwin;
     }
     if (bsteps > 0 && !spec_on)
         for (int64_t j = nvec_in; j < hs.k; j += bsteps) {

@@ -66,6 +66,7 @@ struct cds_ctx {
     int cd_large_path = 0;           // 1: Cholesky code path of large pair counts at any size
     int cd_speculate = 1;            // 1: speculative look-ahead blocks
     int transform_fp64 = 0;          // 1: transform GEMMs in FP64, output rounded to its precision
+    int target_chunk = 0;            // >0: at most this many targets per contraction launch
     hipStream_t stream2 = nullptr;   // side stream (default priority) of the overlapped transform
     hipEvent_t join = nullptr;       // orders stream2 after / before the caller's stream
     hipEvent_t gate = nullptr;       // orders a stream2 batch after a point of the caller's stream

@@ -467,13 +467,14 @@ int check_shape(cds_ctx *ctx, const SigmaShape &sh, const int32_t *h_sel, const 
     return CDS_OK;
 }
 
-// targets per chunk so that G stays below ~4 GiB
-int chunk_targets(const SigmaShape &sh)
+// targets per chunk so that G stays below ~4 GiB (and at most the context's target chunk)
+int chunk_targets(const cds_ctx *ctx, const SigmaShape &sh)
 {
     size_t es = sh.prec == CDS_PREC_FP64 ? 8 : 4;
     size_t per = (size_t)sh.nmo * sh.nvo * es;
     size_t lim = (size_t)4 << 30;
     int n = (int)std::max<size_t>(1, lim / std::max<size_t>(per, 1));
+    if (ctx->target_chunk > 0) n = std::min(n, ctx->target_chunk);
     return std::min(n, sh.nsel);
 }
 
@@ -557,7 +558,7 @@ int launch_epilogue(cds_ctx *ctx, const SigmaShape &sh, EpArgs &e, bool fp64)
 int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void *Bvo,
                const double *eps, const double *d_omega, int T, double *h_out)
 {
-    const int csz = chunk_targets(sh);
+    const int csz = chunk_targets(ctx, sh);
     const size_t es = sh.prec == CDS_PREC_FP64 ? 8 : 4;
     void *G, *part, *out;
     CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * sh.nmo * sh.nvo * es, &G));
@@ -643,6 +644,14 @@ int cds_grad_epilogue_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int ns
     return launch_epilogue<EP_GRAD>(ctx, sh, e, prec == CDS_PREC_FP64);
 }
 
+extern "C" int cds_set_target_chunk(cds_ctx *ctx, int32_t n)
+{
+    if (!ctx) return CDS_EINVAL;
+    if (n < 0 || n > 65535) return cds_fail(ctx, CDS_EINVAL, "target chunk must be in [0, 65535]");
+    ctx->target_chunk = n;
+    return CDS_OK;
+}
+
 extern "C" int cds_sigma2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
                           int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
                           const void *Bvo, const double *eps, int32_t T, const double *h_omega,
@@ -698,7 +707,7 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
     const int nblkA = sh.nvirt, nblkB = (sh.nvirt + 1) / 2;
     if (mode == CDS_QP_RESIDUES) {
         CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * nres * res_es + (size_t)nsel * 4, &R));
-        const int csz = chunk_targets(sh);
+        const int csz = chunk_targets(ctx, sh);
         void *G;
         CDS_CALL(cds_ws(ctx, WS_SG_G, (size_t)csz * nmo * sh.nvo * res_es, &G));
         for (int s0 = 0; s0 < nsel; s0 += csz) {

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from oracle import selfenergy as SE
+from tests._blocks import blocks_from_numpy
 from tests._cases import log, oracle_blocks, oracle_cd, workload
 
 pytestmark = pytest.mark.gpu
@@ -49,7 +50,7 @@ def test_qp_adjoint_fp64(cds, name):
     sel = w.targets[sel_idx]
     wbar = np.array([1.0, -0.5])
     oms, gBs, gBv, ge = _oracle_grads(name, sel_idx, wbar)
-    B = cds.blocks_from_numpy(Bs[:, sel_idx, :], Bv, w.nocc, sel, "fp64")
+    B = blocks_from_numpy(Bs[:, sel_idx, :], Bv, w.nocc, sel, "fp64")
     gs, gv, gE = cds.qp_adjoint(B, _dev(w.eps), oms, wbar)
     M = Bs.shape[0]
     gs = gs.cpu().numpy().reshape(len(sel), w.nmo, B.ldk)
@@ -70,25 +71,30 @@ def test_qp_adjoint_fp32_against_fp64_oracle(cds):
     sel_idx = [list(w.targets).index(w.nocc - 1), list(w.targets).index(w.nocc)]
     wbar = np.array([1.0, 1.0])
     oms, gBs, gBv, ge = _oracle_grads("c60", sel_idx, wbar)
-    B = cds.blocks_from_numpy(Bs[:, sel_idx, :], Bv, w.nocc, w.targets[sel_idx], "fp32")
+    B = blocks_from_numpy(Bs[:, sel_idx, :], Bv, w.nocc, w.targets[sel_idx], "fp32")
     gs, gv, gE = cds.qp_adjoint(B, _dev(w.eps), oms, wbar)
     M = Bs.shape[0]
     gv = gv.cpu().numpy().reshape(w.nvirt, w.nocc, B.ldk)[:, :, :M]
+    gs = gs.cpu().numpy().reshape(len(sel_idx), w.nmo, B.ldk)[:, :, :M]
     refv = gBv.transpose(1, 2, 0)
+    refs = gBs[:, sel_idx, :].transpose(1, 2, 0)
     rel = np.linalg.norm(gv - refv) / np.linalg.norm(refv)
-    log(f"  fp32 Bvo_bar relative error {rel:.2e}")
-    assert rel <= 1e-4
+    rel_s = np.linalg.norm(gs - refs) / np.linalg.norm(refs)
+    log(f"  fp32 Bvo_bar relative error {rel:.2e}, Bsel_bar {rel_s:.2e}")
+    assert rel <= 1e-4 and rel_s <= 1e-4
     assert np.abs(gE.cpu().numpy() - ge).max() <= 1e-4 * np.abs(ge).max()
 
 
-def test_transform_adjoint_fp64(cds):
-    w = workload("plain")
-    log("transform adjoint plain")
-    r = oracle_cd("plain", 1e-6)
-    Bs, Bv = oracle_blocks("plain", 1e-6)
-    sel_idx = [w.nocc - 1, w.nocc]
+@pytest.mark.parametrize("name", ["plain", "c60"])
+def test_transform_adjoint_fp64(cds, name):
+    # C-bar = sum_K L^K C (Bbar^K + Bbar^K^T) against the oracle, fed the oracle's own gradient
+    # of the HOMO/LUMO energies with respect to the blocks
+    w = workload(name)
+    log(f"transform adjoint {name}")
+    r = oracle_cd(name, 1e-6)
+    sel_idx = [list(w.targets).index(w.nocc - 1), list(w.targets).index(w.nocc)]
     wbar = np.array([0.7, -1.3])
-    oms, gBs, gBv, ge = _oracle_grads("plain", sel_idx, wbar)
+    oms, gBs, gBv, ge = _oracle_grads(name, sel_idx, wbar)
     ref = SE.transform_adjoint(r.L, w.C, w.nocc, w.targets, gBs, gBv)
     M = r.M
     ldk = (M + 63) // 64 * 64

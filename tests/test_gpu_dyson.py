@@ -9,6 +9,7 @@ import pytest
 import torch
 
 from oracle import dyson as DY
+from tests._blocks import blocks_from_numpy
 from tests._cases import log, oracle_blocks, workload
 
 pytestmark = pytest.mark.gpu
@@ -43,7 +44,7 @@ def test_sigma_matrix(cds, name):
     om = np.array([w.eps[sel[0]] - 0.05, 0.5 * (w.eps[w.nocc - 1] + w.eps[w.nocc]), w.eps[sel[-1]] + 0.05])
     ref = [DY.sigma_matrix(xs, ys, w.eps, w.nocc, o) for o in om]
     for prec in ("fp64", "fp32", "bf16x3"):
-        B = cds.blocks_from_numpy(Bs, Bv, w.nocc, sel, prec)
+        B = blocks_from_numpy(Bs, Bv, w.nocc, sel, prec)
         s, ds = cds.sigma2_matrix(B, _dev(w.eps), om)
         for t in range(om.size):
             e1 = np.abs(s[t] - ref[t][0]).max() / np.abs(ref[t][0]).max()
@@ -57,7 +58,7 @@ def test_dyson_roots(cds, name):
     w, Bs, Bv, sel = _case(name)
     xs, ys = DY.xys_from_B(Bs, Bv, w.nocc)
     ref = DY.dyson_roots(xs, ys, w.eps, w.nocc, sel, conv=1e-12)
-    B = cds.blocks_from_numpy(Bs, Bv, w.nocc, sel, "fp64")
+    B = blocks_from_numpy(Bs, Bv, w.nocc, sel, "fp64")
     got = cds.dyson_solve(B, _dev(w.eps), conv=1e-12)
     for k, r in enumerate(ref):
         assert got.status[k] == r.status
@@ -66,7 +67,7 @@ def test_dyson_roots(cds, name):
     log(f"dyson {name}: {sel.size} roots, max iterations {got.iters.max()}")
     # one orbital: the quasi-particle Newton solve of Eq. (iter)
     for k in (0, sel.size - 1):
-        B1 = cds.blocks_from_numpy(np.ascontiguousarray(Bs[:, k:k + 1, :]), Bv, w.nocc, sel[k:k + 1], "fp64")
+        B1 = blocks_from_numpy(np.ascontiguousarray(Bs[:, k:k + 1, :]), Bv, w.nocc, sel[k:k + 1], "fp64")
         d1 = cds.dyson_solve(B1, _dev(w.eps), conv=1e-12)
         q1 = cds.qp_solve(B1, _dev(w.eps), conv=1e-12)
         assert abs(d1.omega[0] - q1.omega[0]) <= 1e-11 and abs(d1.pole[0] - q1.pole[0]) <= 1e-10

@@ -9,6 +9,7 @@ import torch
 
 from oracle import selfenergy as SE
 from paper_0912_1459_amd import inputs as I
+from tests._blocks import blocks_from_numpy
 from tests._cases import log, oracle_blocks, oracle_cd, workload
 
 pytestmark = pytest.mark.gpu
@@ -71,7 +72,7 @@ def test_gradient_wrt_B_against_oracle(setup, prec, tol):
     log(f"grad c60: B ({prec}) vs oracle gradient")
     Bs, Bv = oracle_blocks("c60", 1e-6)
     idx = [list(w.targets).index(q) for q in sel]
-    B = C.blocks_from_numpy(Bs[:, idx, :], Bv, w.nocc, sel, prec)
+    B = blocks_from_numpy(Bs[:, idx, :], Bv, w.nocc, sel, prec)
     Bsel = B.Bsel.clone().requires_grad_(True)
     Bvo = B.Bvo.clone().requires_grad_(True)
     eps = _dev(w.eps).requires_grad_(True)
@@ -79,7 +80,9 @@ def test_gradient_wrt_B_against_oracle(setup, prec, tol):
     om = AG.QPSolve.apply(Bsel, Bvo, eps, meta)
     (-(om[0] + om[1])).backward()
     gv = Bvo.grad.double().cpu().numpy().reshape(w.nvirt, w.nocc, B.ldk)[:, :, : B.nvec]
+    gs = Bsel.grad.double().cpu().numpy().reshape(len(sel), w.nmo, B.ldk)[:, :, : B.nvec]
     refv = np.zeros_like(Bv)
+    refs = np.zeros((len(sel), w.nmo, B.nvec))
     ge_ref = np.zeros(w.nmo)
     for k, s in enumerate(idx):
         q = int(w.targets[s])
@@ -87,11 +90,13 @@ def test_gradient_wrt_B_against_oracle(setup, prec, tol):
         o = SE.newton(x, y, w.eps, w.nocc, q, conv=1e-14, max_iter=100).omega
         g = SE.qp_gradient(Bs[:, s, :], Bv, w.eps, w.nocc, q, o)
         refv -= g.Bvo
+        refs[k] -= g.Bsel_q.T
         ge_ref -= g.eps
     rel = np.linalg.norm(gv - refv.transpose(1, 2, 0)) / np.linalg.norm(refv)
+    rel_s = np.linalg.norm(gs - refs) / np.linalg.norm(refs)
     rel_e = np.abs(eps.grad.cpu().numpy() - ge_ref).max() / np.abs(ge_ref).max()
-    log(f"  |dBvo| rel {rel:.2e}, |deps| rel {rel_e:.2e}")
-    assert rel <= tol and rel_e <= tol
+    log(f"  |dBvo| rel {rel:.2e}, |dBsel| rel {rel_s:.2e}, |deps| rel {rel_e:.2e}")
+    assert rel <= tol and rel_s <= tol and rel_e <= tol
 
 
 def test_gradient_wrt_B_fd_fp64(setup):
@@ -100,7 +105,7 @@ def test_gradient_wrt_B_fd_fp64(setup):
     log("grad c60: B vs central differences (fp64)")
     Bs, Bv = oracle_blocks("c60", 1e-6)
     idx = [list(w.targets).index(q) for q in sel]
-    B = C.blocks_from_numpy(Bs[:, idx, :], Bv, w.nocc, sel, "fp64")
+    B = blocks_from_numpy(Bs[:, idx, :], Bv, w.nocc, sel, "fp64")
     eps = _dev(w.eps)
     om = C.qp_solve(B, eps, conv=1e-14, max_iter=100)
     gs, gv, ge = C.qp_adjoint(B, eps, om.omega, np.array([-1.0, -1.0]))
@@ -108,7 +113,7 @@ def test_gradient_wrt_B_fd_fp64(setup):
     gnorm = np.sqrt((gs ** 2).sum() + (gv ** 2).sum())
     g = np.random.default_rng(I.SEED_ROOT + 3)
     worst = 0.0
-    for _ in range(16):
+    for _ in range(NDIR):
         ds = g.standard_normal(gs.shape)
         dv = g.standard_normal(gv.shape)
         ds[:, B.nvec:] = 0
@@ -126,3 +131,21 @@ def test_gradient_wrt_B_fd_fp64(setup):
         worst = max(worst, _rel(an, fd, gnorm))
     log(f"  worst relative error: {worst:.2e}")
     assert worst <= 1e-6
+
+
+def test_backward_refuses_unconverged_solve(setup):
+    # the implicit gradient holds only at the fixed point: a solve stopped by max_iter must not
+    # return a gradient
+    AG, C, w, r, sel = setup
+    log("grad c60: backward of an unconverged solve raises")
+    Bs, Bv = oracle_blocks("c60", 1e-6)
+    idx = [list(w.targets).index(q) for q in sel]
+    B = blocks_from_numpy(Bs[:, idx, :], Bv, w.nocc, sel, "fp64")
+    Bsel = B.Bsel.clone().requires_grad_(True)
+    Bvo = B.Bvo.clone().requires_grad_(True)
+    eps = _dev(w.eps).requires_grad_(True)
+    meta = AG.SolveMeta(B.nvec, B.ldk, w.nmo, w.nocc, sel, B.prec, conv=1e-14, max_iter=1)
+    om = AG.QPSolve.apply(Bsel, Bvo, eps, meta)
+    assert np.all(meta.result.status == 1)
+    with pytest.raises(RuntimeError, match="did not converge"):
+        om.sum().backward()

@@ -12,6 +12,7 @@ import torch
 
 from oracle import mp2 as MP
 from paper_0912_1459_amd import inputs as I
+from tests._blocks import blocks_from_numpy
 from tests._cases import log, oracle_blocks, workload
 
 pytestmark = pytest.mark.gpu
@@ -36,7 +37,7 @@ def test_mp2_from_oracle_blocks(cds, name):
     ref = MP.mp2_from_B(Bv, w.eps, w.nocc)
     log(f"mp2 {name}: oracle E = {ref:.12f}")
     for prec in ("fp64", "fp32", "bf16x3"):
-        B = cds.blocks_from_numpy(Bs, Bv, w.nocc, w.targets, prec)
+        B = blocks_from_numpy(Bs, Bv, w.nocc, w.targets, prec)
         got = cds.mp2_energy(B, _dev(w.eps))
         rel = abs(got - ref) / abs(ref)
         log(f"  {prec}: rel {rel:.2e}")
@@ -66,7 +67,7 @@ def test_mp2_ragged_random_blocks(cds, nocc, nvirt, M):
     Bs = np.ascontiguousarray(Bfull[:, :1, :])
     ref = MP.mp2_from_B(Bv, eps, nocc)
     for prec in ("fp64", "fp32", "bf16x3"):
-        B = cds.blocks_from_numpy(Bs, Bv, nocc, [0], prec)
+        B = blocks_from_numpy(Bs, Bv, nocc, [0], prec)
         got = cds.mp2_energy(B, _dev(eps))
         assert abs(got - ref) <= TOL[prec] * abs(ref), (prec, got, ref)
 
@@ -74,7 +75,7 @@ def test_mp2_ragged_random_blocks(cds, nocc, nvirt, M):
 def test_mp2_deterministic_and_invalid(cds):
     w = workload("plain")
     Bs, Bv = oracle_blocks("plain", 1e-6)
-    B = cds.blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp32")
+    B = blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp32")
     eps = _dev(w.eps)
     e1 = cds.mp2_energy(B, eps)
     e2 = cds.mp2_energy(B, eps)

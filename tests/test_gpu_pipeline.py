@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import paper_0912_1459_amd._lib as A
+from tests._blocks import as_float64
 from tests._cases import log, oracle_blocks, workload
 
 pytestmark = pytest.mark.gpu
@@ -66,7 +67,7 @@ def test_fused_fp64_matches_oracle(C, name, delta):
                                  prec="fp64", max_vec=min(C.npairs(w.nbf), 12 * w.nbf))
     refs, refv = oracle_blocks(name, delta)
     assert cd.nvec == refs.shape[0]
-    gs, gv = (x.cpu().numpy() for x in B.as_float64())
+    gs, gv = (x.cpu().numpy() for x in as_float64(B))
     # vectors of the two decompositions agree to rounding (same pivots); B follows them
     scale = max(np.abs(refs).max(), np.abs(refv).max())
     assert np.abs(gs - refs.transpose(1, 2, 0)).max() <= 1e-9 * scale

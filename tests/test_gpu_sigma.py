@@ -10,6 +10,7 @@ import torch
 
 from oracle import mo, selfenergy as SE
 from paper_0912_1459_amd import inputs as I
+from tests._blocks import as_float64, blocks_from_numpy
 from tests._cases import EV, log, oracle_blocks, oracle_cd, oracle_qp, workload
 
 pytestmark = pytest.mark.gpu
@@ -39,7 +40,7 @@ def test_transform_fp64(cds, name, delta):
     Ld, M = _L_on_device(name, delta)
     refs, refv = oracle_blocks(name, delta)
     B = cds.transform(Ld, M, _dev(w.C), w.nocc, w.targets, "fp64")
-    gs, gv = B.as_float64()
+    gs, gv = as_float64(B)
     gs, gv = gs.cpu().numpy(), gv.cpu().numpy()
     scale = max(np.abs(refs).max(), np.abs(refv).max())
     assert np.abs(gs - refs.transpose(1, 2, 0)).max() <= 1e-12 * scale
@@ -48,18 +49,32 @@ def test_transform_fp64(cds, name, delta):
     assert torch.all(B.Bsel.reshape(-1, B.ldk)[:, M:] == 0)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16x3", 1e-4)])
-def test_transform_reduced(cds, prec, tol):
+# Per-element bound of a reduced-precision transform, relative to (|C|^T |L^K| |C|)_pq (the sum
+# of the absolute values of the terms of B^K_pq): two products, each over at most nbf terms with
+# FP32 accumulation (nbf * 2^-24 per product); split-bf16 operands hi + lo represent an FP32
+# value to 2^-18 relative and the dropped lo*lo term is below 2^-18 of the product, so each
+# split product adds 3 * 2^-18.  Doubled for the two stages.
+_U = {"fp32": lambda n: 2 * n * 2.0 ** -24, "bf16x3": lambda n: 2 * (n * 2.0 ** -24 + 3 * 2.0 ** -18)}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_transform_reduced(cds, prec):
     name, delta = "c60", 1e-6
     w = workload(name)
     log(f"transform {prec} {name}")
     Ld, M = _L_on_device(name, delta)
     refs, refv = oracle_blocks(name, delta)
+    r = oracle_cd(name, delta)
+    abss, absv = mo.transform_blocks(np.abs(r.L), np.abs(w.C), w.nocc, w.targets)
     B = cds.transform(Ld, M, _dev(w.C), w.nocc, w.targets, prec)
-    gs, gv = B.as_float64()
+    gs, gv = as_float64(B)
+    u = _U[prec](w.nbf)
+    rs = np.abs(gs.cpu().numpy() - refs.transpose(1, 2, 0)) / (u * abss.transpose(1, 2, 0) + 1e-300)
+    rv = np.abs(gv.cpu().numpy() - refv.transpose(1, 2, 0)) / (u * absv.transpose(1, 2, 0) + 1e-300)
     scale = max(np.abs(refs).max(), np.abs(refv).max())
-    assert np.abs(gs.cpu().numpy() - refs.transpose(1, 2, 0)).max() <= tol * scale
-    assert np.abs(gv.cpu().numpy() - refv.transpose(1, 2, 0)).max() <= tol * scale
+    log(f"  max error / per-element bound = {max(rs.max(), rv.max()):.3e}; max error / max |B| = "
+        f"{max(np.abs(gs.cpu().numpy() - refs.transpose(1, 2, 0)).max(), np.abs(gv.cpu().numpy() - refv.transpose(1, 2, 0)).max()) / scale:.2e}")
+    assert rs.max() <= 1.0 and rv.max() <= 1.0
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-7), ("bf16x3", 2e-5)])
@@ -74,7 +89,7 @@ def test_transform_fp64_working_precision(cds, prec, tol):
     ctx = cds.Context(0)
     ctx.set_transform_fp64(True)
     B = cds.transform(Ld, M, _dev(w.C), w.nocc, w.targets, prec, ctx=ctx)
-    gs, gv = B.as_float64()
+    gs, gv = as_float64(B)
     scale = max(np.abs(refs).max(), np.abs(refv).max())
     es = np.abs(gs.cpu().numpy() - refs.transpose(1, 2, 0)).max() / scale
     ev = np.abs(gv.cpu().numpy() - refv.transpose(1, 2, 0)).max() / scale
@@ -87,7 +102,7 @@ def test_sigma2_fp64_trial_energies(cds, name):
     w = workload(name)
     log(f"sigma2 fp64 {name}")
     Bs, Bv = oracle_blocks(name, 1e-6)
-    B = cds.blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp64")
+    B = blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp64")
     eps = _dev(w.eps)
     om = w.trial_energies() if w.n_trial > 1 else np.stack([w.eps[w.targets], w.eps[w.targets] + 0.03], 1)
     s, ds = cds.sigma2(B, eps, om)
@@ -106,7 +121,7 @@ def test_qp_solve_fp64(cds, name, mode):
     log(f"qp_solve fp64 {name} {mode}")
     Bs, Bv = oracle_blocks(name, 1e-6)
     ref = oracle_qp(name, 1e-6, 1e-12)
-    B = cds.blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp64")
+    B = blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp64")
     got = cds.qp_solve(B, _dev(w.eps), conv=1e-12, max_iter=50, mode=mode)
     assert list(got.status) == [r.status for r in ref]
     om = np.array([r.omega for r in ref])
@@ -147,7 +162,7 @@ def test_reduced_precision_within_one_mev(cds, prec):
 def test_qp_statuses_forced(cds):
     w = workload("plain")
     Bs, Bv = oracle_blocks("plain", 1e-6)
-    B = cds.blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp64")
+    B = blocks_from_numpy(Bs, Bv, w.nocc, w.targets, "fp64")
     got = cds.qp_solve(B, _dev(w.eps), conv=1e-14, max_iter=1)
     assert np.all(got.status == 1)
     # start on a pole of the 2h1p family of target HOMO
@@ -172,6 +187,6 @@ def test_ragged_random_blocks(cds):
     Bv = np.ascontiguousarray(Bfull[:, nocc:, :nocc])
     ref = SE.solve_targets(Bs, Bv, eps, nocc, sel, conv=1e-12)
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 1e-4)):
-        B = cds.blocks_from_numpy(Bs, Bv, nocc, sel, prec)
+        B = blocks_from_numpy(Bs, Bv, nocc, sel, prec)
         got = cds.qp_solve(B, _dev(eps), conv=1e-12)
         assert np.abs(got.omega - np.array([r.omega for r in ref])).max() <= tol, prec
