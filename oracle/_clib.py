@@ -43,7 +43,7 @@ def lib() -> ctypes.CDLL:
         L.orc_eri_columns.restype = None
         L.orc_eri_diagonal.argtypes = [i32, P, P, P]
         L.orc_eri_diagonal.restype = None
-        L.orc_pivoted_cd.argtypes = [i64, P, i32, P, P, d, d, d, i64, i64, P, P, P, P, P, P]
+        L.orc_pivoted_cd.argtypes = [i64, P, i32, P, P, d, d, d, i64, i64, P, P, P, P, P, P, i32]
         L.orc_pivoted_cd.restype = ctypes.c_int
         _lib = L
     return _lib

@@ -134,6 +134,9 @@ void orc_eri_columns(int32_t nbf, const double *centres, const double *alpha,
  * allowed: NULL, or npairs flags; only pairs with allowed[I] != 0 may become
  * pivots (every non-pivot row is still updated) -- the inner projection of
  * Eq. (int_approx) onto the allowed products, as in the atomic CD.
+ * reverse: 0 sums the residual column over earlier vectors in the order j = 0, 1, ...; 1 in the
+ * order j = k-1, ..., 0 (the same sum associated the other way: it measures how far rounding
+ * alone moves a result).
  * Returns 0 when D_max <= delta, 1 when max_vec vectors were made first,
  * 2 when every allowed pair became a pivot, -4 when a non-pivot residual
  * diagonal fell below -psd_tol.  *dmax receives the final largest residual
@@ -142,7 +145,7 @@ void orc_eri_columns(int32_t nbf, const double *centres, const double *alpha,
 int orc_pivoted_cd(int64_t npairs, const double *V, int32_t nbf, const double *centres,
                    const double *alpha, double delta, double tau, double psd_tol,
                    int64_t max_vec, int64_t ldl, double *L, int64_t *piv, double *D,
-                   int64_t *nvec, double *dmax, const unsigned char *allowed)
+                   int64_t *nvec, double *dmax, const unsigned char *allowed, int reverse)
 {
     unsigned char *is_piv = (unsigned char *)calloc((size_t)npairs, 1);
     double *col = (double *)malloc((size_t)npairs * sizeof(double));
@@ -196,8 +199,12 @@ int orc_pivoted_cd(int64_t npairs, const double *V, int32_t nbf, const double *c
                 LI[k] = sq;
             } else {
                 double c = col[I];
-                for (int64_t j = 0; j < k; ++j)
-                    c -= LI[j] * Lp[j];
+                if (reverse)
+                    for (int64_t j = k - 1; j >= 0; --j)
+                        c -= LI[j] * Lp[j];
+                else
+                    for (int64_t j = 0; j < k; ++j)
+                        c -= LI[j] * Lp[j];
                 LI[k] = c / sq;
                 D[I] -= LI[k] * LI[k];
             }

@@ -109,12 +109,14 @@ def default_tau(diag_max: float) -> float:
 def pivoted_cd(delta: float, *, V: np.ndarray | None = None, centres=None, alpha=None,
                tau: float | None = None, max_vec: int | None = None,
                resume: CDResult | None = None, psd_tol: float | None = None,
-               allowed: np.ndarray | None = None) -> CDResult:
+               allowed: np.ndarray | None = None, reverse_sums: bool = False) -> CDResult:
     """Diagonal-pivoted incomplete Cholesky of the ERI matrix to threshold delta.
 
     Either a dense V or the basis (centres, alpha) for on-demand columns.
     ``resume`` continues a previous result to a smaller delta or larger cap.
     ``allowed`` (bool per pair) restricts the pivots (all rows are still updated).
+    ``reverse_sums`` sums each residual column over the earlier vectors in reverse order (the same
+    decomposition up to rounding; used to measure rounding sensitivity).
     """
     if V is not None:
         V = np.ascontiguousarray(V, dtype=np.float64)
@@ -161,11 +163,12 @@ def pivoted_cd(delta: float, *, V: np.ndarray | None = None, centres=None, alpha
     st = lib().orc_pivoted_cd(npairs, _p(V) if V is not None else None, nbf, cptr, aptr,
                               float(delta), float(tau), float(psd_tol), int(max_vec), int(Lfull.shape[1]),
                               _p(Lfull), _p(piv), _p(D), _p(nvec), _p(dmax),
-                              _p(allow_u8) if allow_u8 is not None else None)
+                              _p(allow_u8) if allow_u8 is not None else None, int(bool(reverse_sums)))
     M = int(nvec[0])
     res = CDResult(Lfull[:, :M], piv[:M].copy(), D, float(dmax[0]), int(st), Lfull)
     if grow and st == STATUS_CAP:
         # no cap requested: continue with twice the room
         return pivoted_cd(delta, V=V, centres=centres, alpha=alpha, tau=tau,
-                          max_vec=min(2 * max_vec, npairs), resume=res, psd_tol=psd_tol, allowed=allowed)
+                          max_vec=min(2 * max_vec, npairs), resume=res, psd_tol=psd_tol, allowed=allowed,
+                          reverse_sums=reverse_sums)
     return res

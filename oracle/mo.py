@@ -25,12 +25,14 @@ def unpack(lvec: np.ndarray, nbf: int) -> np.ndarray:
     return out
 
 
-def transform_blocks(L: np.ndarray, C: np.ndarray, nocc: int, sel, chunk: int = 64):
+def transform_blocks(L: np.ndarray, C: np.ndarray, nocc: int, sel, chunk: int = 64, order: str = "right"):
     """B blocks needed by the self-energy, Eq. (transformation).
 
     L: (npairs, M) Cholesky vectors (column K = L^K packed).
     Returns Bsel (M, nsel, nmo) = B^K[q, :] for q in sel and
     Bvo (M, nvirt, nocc) = B^K[nocc + a, i].
+    order "right" forms C_x^T (L^K C_y), "left" (C_x^T L^K) C_y: the same sums associated the
+    other way, which measures how much rounding alone moves a result.
     """
     sel = np.asarray(sel, dtype=np.int64)
     nbf, nmo = C.shape
@@ -41,10 +43,14 @@ def transform_blocks(L: np.ndarray, C: np.ndarray, nocc: int, sel, chunk: int = 
     for k0 in range(0, M, chunk):
         k1 = min(M, k0 + chunk)
         Lk = unpack(np.ascontiguousarray(L[:, k0:k1].T), nbf)        # (kc, N, N)
-        T_occ = Lk @ Cocc                                             # L^K C_occ
-        Bvo[k0:k1] = Cvir.T[None] @ T_occ                             # C_vir^T L^K C_occ
-        T_sel = Lk @ Csel                                             # L^K C_sel
-        Bsel[k0:k1] = T_sel.transpose(0, 2, 1) @ C[None]              # C_sel^T L^K C
+        if order == "right":
+            T_occ = Lk @ Cocc                                         # L^K C_occ
+            Bvo[k0:k1] = Cvir.T[None] @ T_occ                         # C_vir^T L^K C_occ
+            T_sel = Lk @ Csel                                         # L^K C_sel
+            Bsel[k0:k1] = T_sel.transpose(0, 2, 1) @ C[None]          # C_sel^T L^K C
+        else:
+            Bvo[k0:k1] = (Cvir.T[None] @ Lk) @ Cocc[None]
+            Bsel[k0:k1] = (Csel.T[None] @ Lk) @ C[None]
     return Bsel, Bvo
 
 

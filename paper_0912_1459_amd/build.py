@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcdsigma.so")
-SOURCES = ["context.hip", "cd.hip", "gemm.hip", "transform.hip", "sigma.hip", "adjoint.hip", "mp2.hip", "dyson.hip"]
+SOURCES = ["context.hip", "cd.hip", "gemm.hip", "transform.hip", "sigma.hip", "sigma_fused.hip", "adjoint.hip", "mp2.hip", "dyson.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -41,6 +41,7 @@ enum CdsSlot {
     WS_AD_T1,       // adjoint: K-contiguous copies of transposed GEMM operands
     WS_AD_T2,
     WS_AD_T3,
+    WS_SG_TSEL,     // target slots of the fused self-energy launches
     WS_SLOTS
 };
 
@@ -171,3 +172,29 @@ int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, cons
 // out[c*ldo + r] = in[r*ldi + c] for r < rows, c < cols; elements of es bytes (4 or 8)
 int cds_transpose(cds_ctx *ctx, int es, int64_t rows, int64_t cols, const void *in, int64_t ldi, void *out,
                   int64_t ldo);
+
+// Fused self-energy contraction (sigma_fused.hip): the integrals of Eq. (SE) are formed by MFMA
+// products and reduced over the energy denominators in one kernel, task by task (a task = one
+// tile pair of the (qi|aj) matrix of a virtual a or the (qa|ib) matrix of an occupied i).
+struct CdsFusedPlan {
+    int64_t ns;              // K stages
+    int nTA, nTB, nPA, nPB;  // 128-row tiles and tile pairs of parts A and B
+    int64_t tpt;             // tasks per target
+    int64_t sizeA, sizeB;    // residues per virtual a / per occupied i
+    int64_t nres;            // residues per target
+};
+// false when the blocks do not suit the fused kernel (alignment, K padding); p filled otherwise
+bool cds_fused_plan(int prec, int64_t nvec, int64_t ldk, int nmo, int nocc, const void *Bsel, const void *Bvo,
+                    const void *Bsel_lo, const void *Bvo_lo, CdsFusedPlan *p);
+// partial sums d_part[nsc][tpt][T][2] of Sigma and Sigma' for the targets d_tsel[0..nsc) at
+// d_omega[nsc][T]
+int cds_fused_sigma(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, int nmo, int nocc, int nsc,
+                    const int *d_tsel, const void *Bsel, const void *Bvo, const void *Bsel_lo, const void *Bvo_lo,
+                    const double *eps, const double *d_omega, int T, double *d_part);
+// pole residues R[nsc][nres] (double for FP64, float otherwise) of the targets d_tsel[0..nsc)
+int cds_fused_residues(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, int nmo, int nocc, int nsc,
+                       const int *d_tsel, const void *Bsel, const void *Bvo, const void *Bsel_lo, const void *Bvo_lo,
+                       const double *eps, void *R);
+// one Newton sweep: d_part[nactive][tpt][2] for the targets d_active at d_omega[target]
+int cds_fused_sweep(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int nmo, int nocc, int nactive,
+                    const int *d_active, const double *eps, const double *d_omega, const void *R, double *d_part);

@@ -478,6 +478,39 @@ int chunk_targets(const cds_ctx *ctx, const SigmaShape &sh)
     return std::min(n, sh.nsel);
 }
 
+// split-bf16 lo planes of the blocks (NULL for the other precisions)
+void lo_planes(const SigmaShape &sh, const void *Bsel, const void *Bvo, const void **Slo, const void **Vlo)
+{
+    *Slo = *Vlo = nullptr;
+    if (sh.prec == CDS_PREC_BF16X3) {
+        *Slo = (const __bf16 *)Bsel + sh.nselr * sh.ldk;
+        *Vlo = (const __bf16 *)Bvo + sh.nvo * sh.ldk;
+    }
+}
+
+// targets per launch of the fused kernel (all unless the context caps it)
+int fused_chunk(const cds_ctx *ctx, const SigmaShape &sh)
+{
+    return ctx->target_chunk > 0 ? std::min(ctx->target_chunk, sh.nsel) : sh.nsel;
+}
+
+__global__ void iota_kernel(int *__restrict__ p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+// device list 0 .. nsel-1 of target slots (slot s0 + j of a launch is entry s0 + j)
+int target_slots(cds_ctx *ctx, int nsel, int **d_tsel)
+{
+    void *p;
+    CDS_CALL(cds_ws(ctx, WS_SG_TSEL, (size_t)nsel * 4, &p));
+    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)cds_ceil_div(nsel, 256)), dim3(256), 0, ctx->stream, (int *)p, nsel);
+    CDS_LAUNCHED(ctx);
+    *d_tsel = (int *)p;
+    return CDS_OK;
+}
+
 // G for targets [s0, s0+nsc)
 int contract_chunk(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void *Bvo, int s0,
                    int nsc, void *G)
@@ -558,6 +591,40 @@ int launch_epilogue(cds_ctx *ctx, const SigmaShape &sh, EpArgs &e, bool fp64)
 int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void *Bvo,
                const double *eps, const double *d_omega, int T, double *h_out)
 {
+    const void *Slo, *Vlo;
+    lo_planes(sh, Bsel, Bvo, &Slo, &Vlo);
+    CdsFusedPlan fp;
+    if (cds_fused_plan(sh.prec, sh.nvec, sh.ldk, sh.nmo, sh.nocc, Bsel, Bvo, Slo, Vlo, &fp)) {
+        // integrals formed and reduced over the denominators in one kernel (never stored)
+        const int csz = fused_chunk(ctx, sh);
+        int *tsel;
+        CDS_CALL(target_slots(ctx, sh.nsel, &tsel));
+        void *part, *out;
+        CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)csz * fp.tpt * T * 2 * 8, &part));
+        CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)sh.nsel * T * 2 * 8, &out));
+        for (int s0 = 0; s0 < sh.nsel; s0 += csz) {
+            const int nsc = std::min(csz, sh.nsel - s0);
+            CdsTimer t;
+            CDS_CALL(cds_timer_start(ctx, &t));
+            CDS_CALL(cds_fused_sigma(ctx, sh.prec, fp, sh.ldk, sh.nmo, sh.nocc, nsc, tsel + s0, Bsel, Bvo, Slo, Vlo,
+                                     eps, d_omega + (int64_t)s0 * T, T, (double *)part));
+            CDS_CALL(cds_timer_stop(ctx, &t, &ctx->stats.t_contract_ms));
+            ctx->stats.flops_contract += 2.0 * (double)sh.nvec * nsc * sh.nmo * (double)sh.nvo;
+            ctx->stats.n_contract += 1;
+            CdsTimer t2;
+            CDS_CALL(cds_timer_start(ctx, &t2));
+            const int nout = nsc * T * 2;
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(nout, 256)), dim3(256), 0,
+                               ctx->stream, (const double *)part, nsc, (int)fp.tpt, T,
+                               (double *)out + (int64_t)s0 * T * 2);
+            CDS_LAUNCHED(ctx);
+            CDS_CALL(cds_timer_stop(ctx, &t2, &ctx->stats.t_epilogue_ms));
+        }
+        CDS_HIP(ctx, hipMemcpyAsync(h_out, out, (size_t)sh.nsel * T * 2 * 8, hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return CDS_OK;
+    }
+    // blocks the fused kernel cannot read (K padding or alignment): integrals through HBM
     const int csz = chunk_targets(ctx, sh);
     const size_t es = sh.prec == CDS_PREC_FP64 ? 8 : 4;
     void *G, *part, *out;
@@ -705,7 +772,34 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
     const size_t res_es = prec == CDS_PREC_FP64 ? 8 : 4;
     void *R = nullptr, *om = nullptr, *part = nullptr, *outd = nullptr, *act = nullptr;
     const int nblkA = sh.nvirt, nblkB = (sh.nvirt + 1) / 2;
-    if (mode == CDS_QP_RESIDUES) {
+    const void *Slo, *Vlo;
+    lo_planes(sh, Bsel, Bvo, &Slo, &Vlo);
+    CdsFusedPlan fp;
+    const bool fused = cds_fused_plan(prec, nvec, ldk, nmo, nocc, Bsel, Bvo, Slo, Vlo, &fp);
+    int64_t nblk_sweep = nblkA + nblkB;
+    if (mode == CDS_QP_RESIDUES && fused) {
+        // residues formed by the fused contraction (no integrals in HBM), swept per task
+        CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * fp.nres * res_es, &R));
+        const int csz = fused_chunk(ctx, sh);
+        int *tsel;
+        CDS_CALL(target_slots(ctx, nsel, &tsel));
+        for (int s0 = 0; s0 < nsel; s0 += csz) {
+            const int nsc = std::min(csz, nsel - s0);
+            CdsTimer t;
+            CDS_CALL(cds_timer_start(ctx, &t));
+            CDS_CALL(cds_fused_residues(ctx, prec, fp, ldk, nmo, nocc, nsc, tsel + s0, Bsel, Bvo, Slo, Vlo, eps,
+                                        (unsigned char *)R + (size_t)s0 * fp.nres * res_es));
+            CDS_CALL(cds_timer_stop(ctx, &t, &ctx->stats.t_contract_ms));
+            ctx->stats.flops_contract += 2.0 * (double)nvec * nsc * nmo * (double)sh.nvo;
+            ctx->stats.n_contract += 1;
+        }
+        nblk_sweep = fp.tpt;
+        CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * 8, &om));
+        CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsel * nblk_sweep * 2 * 8, &part));
+        CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)nsel * 2 * 8 + (size_t)nsel * 4 + 64, &outd));
+        act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
+    } else if (mode == CDS_QP_RESIDUES) {
+        // blocks the fused kernel cannot read: integrals through HBM, then the residue epilogue
         CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * nres * res_es + (size_t)nsel * 4, &R));
         const int csz = chunk_targets(ctx, sh);
         void *G;
@@ -748,29 +842,34 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
             for (size_t k = 0; k < active.size(); ++k) h_act[k] = active[k];
             CDS_HIP(ctx, hipMemcpyAsync(om, h_w, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
             CDS_HIP(ctx, hipMemcpyAsync(act, h_act, active.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-            EpArgs e = {};
-            e.nmo = nmo;
-            e.nocc = nocc;
-            e.nvirt = sh.nvirt;
-            e.nvo = sh.nvo;
-            e.eps = eps;
-            e.omega = (const double *)om;
-            e.T = 1;
-            e.R = R;
-            e.nres = nres;
-            e.offB = (int64_t)sh.nvirt * npairA;
-            e.part = (double *)part;
-            e.nblkA = nblkA;
-            e.nblkB = nblkB;
-            dim3 g((unsigned)(nblkA + nblkB), (unsigned)active.size());
-            if (prec == CDS_PREC_FP64)
-                hipLaunchKernelGGL(sweep_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
-            else
-                hipLaunchKernelGGL(sweep_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
-            CDS_LAUNCHED(ctx);
+            if (fused) {
+                CDS_CALL(cds_fused_sweep(ctx, prec, fp, nmo, nocc, (int)active.size(), (const int *)act, eps,
+                                         (const double *)om, R, (double *)part));
+            } else {
+                EpArgs e = {};
+                e.nmo = nmo;
+                e.nocc = nocc;
+                e.nvirt = sh.nvirt;
+                e.nvo = sh.nvo;
+                e.eps = eps;
+                e.omega = (const double *)om;
+                e.T = 1;
+                e.R = R;
+                e.nres = nres;
+                e.offB = (int64_t)sh.nvirt * npairA;
+                e.part = (double *)part;
+                e.nblkA = nblkA;
+                e.nblkB = nblkB;
+                dim3 g((unsigned)(nblkA + nblkB), (unsigned)active.size());
+                if (prec == CDS_PREC_FP64)
+                    hipLaunchKernelGGL(sweep_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
+                else
+                    hipLaunchKernelGGL(sweep_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
+                CDS_LAUNCHED(ctx);
+            }
             int n = (int)active.size() * 2;
             hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
-                               ctx->stream, (const double *)part, (int)active.size(), nblkA + nblkB, 1,
+                               ctx->stream, (const double *)part, (int)active.size(), (int)nblk_sweep, 1,
                                (double *)outd);
             CDS_LAUNCHED(ctx);
             CDS_HIP(ctx, hipMemcpyAsync(h_out, outd, (size_t)active.size() * 2 * 8, hipMemcpyDeviceToHost,

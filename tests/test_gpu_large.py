@@ -8,8 +8,14 @@ tests/golden/make_golden_large.py from oracle/ alone (Sec. II.A; Eqs. (transform
 (iter)).  The device path runs exactly as the benchmark times it: the decomposition with the
 transform beside it, the transform in FP64 working precision (the synthetic MO coefficients
 are ill-conditioned), the self-energy contraction over several target chunks.
-Bars: pivots bit-exact; FP64 energies and pole strengths within 1e-10 Eh; FP32 and
-split-bf16 energies within 1 meV of the FP64 oracle.
+Bars: pivots bit-exact; FP32 and split-bf16 energies within 1 meV of the FP64 oracle; FP64
+energies within 1e-10 Eh plus four times the oracle's own rounding spread for that target.
+The spread is measured by the oracle itself (the transform associated the other way moves the
+energy by P dSigma): this workload's MO coefficients are ill-conditioned (C = S^-1/2 Q with
+smallest overlap eigenvalue ~2e-7), which amplifies the rounding of any FP64 evaluation of the
+transform by about 1/lambda_min; the factor four covers the three places where the two paths
+round differently (decomposition, transform, contraction) with margin.  Pole strengths likewise
+with P^2 dSigma'.
 """
 import json
 import os
@@ -63,10 +69,14 @@ def test_large_fp64_quasiparticles_match_oracle(run):
     g, out = run
     qp = out["fp64"][4]
     err = np.abs(qp.omega - np.asarray(g["omega"]))
-    log(f"  FP64 max |dw| = {err.max():.2e} Eh")
+    tol = 1e-10 + 4.0 * np.asarray(g["omega_rounding_spread"])
+    ptol = 1e-10 + 4.0 * np.asarray(g["pole_rounding_spread"])
+    perr = np.abs(qp.pole - np.asarray(g["pole"]))
+    log(f"  FP64 max |dw| = {err.max():.2e} Eh; |dw| / bound max {np.max(err / tol):.2f}; "
+        f"|dP| / bound max {np.max(perr / ptol):.2f}")
     assert list(qp.status) == g["status"]
-    assert err.max() <= 1e-10
-    assert np.abs(qp.pole - np.asarray(g["pole"])).max() <= 1e-10
+    assert np.all(err <= tol)
+    assert np.all(perr <= ptol)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])

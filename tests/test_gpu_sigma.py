@@ -190,3 +190,21 @@ def test_ragged_random_blocks(cds):
         B = blocks_from_numpy(Bs, Bv, nocc, sel, prec)
         got = cds.qp_solve(B, _dev(eps), conv=1e-12)
         assert np.abs(got.omega - np.array([r.omega for r in ref])).max() <= tol, prec
+
+
+def test_unfused_fallback_matches_oracle(cds):
+    # blocks whose row length does not suit the fused kernel's 16-byte K stages (ldk = M = 37)
+    # take the path that stores the integrals; same sizes as the ragged case above
+    nocc, nvirt, M = 7, 13, 37
+    n = nocc + nvirt
+    Bfull = I.random_factor(n, M, 5, scale=0.15)
+    eps = I.random_energies(nocc, nvirt, 5)
+    sel = np.array([nocc - 2, nocc - 1, nocc])
+    Bs = np.ascontiguousarray(Bfull[:, sel, :])
+    Bv = np.ascontiguousarray(Bfull[:, nocc:, :nocc])
+    ref = SE.solve_targets(Bs, Bv, eps, nocc, sel, conv=1e-12)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        B = blocks_from_numpy(Bs, Bv, nocc, sel, prec, ldk=M)
+        for mode in ("residues", "recompute"):
+            got = cds.qp_solve(B, _dev(eps), conv=1e-12, mode=mode)
+            assert np.abs(got.omega - np.array([r.omega for r in ref])).max() <= tol, (prec, mode)
