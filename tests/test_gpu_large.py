@@ -9,13 +9,15 @@ tests/golden/make_golden_large.py from oracle/ alone (Sec. II.A; Eqs. (transform
 transform beside it, the transform in FP64 working precision (the synthetic MO coefficients
 are ill-conditioned), the self-energy contraction over several target chunks.
 Bars: pivots bit-exact; FP32 and split-bf16 energies within 1 meV of the FP64 oracle; FP64
-energies within 1e-10 Eh plus four times the oracle's own rounding spread for that target.
-The spread is measured by the oracle itself (the transform associated the other way moves the
-energy by P dSigma): this workload's MO coefficients are ill-conditioned (C = S^-1/2 Q with
-smallest overlap eigenvalue ~2e-7), which amplifies the rounding of any FP64 evaluation of the
-transform by about 1/lambda_min; the factor four covers the three places where the two paths
-round differently (decomposition, transform, contraction) with margin.  Pole strengths likewise
-with P^2 dSigma'.
+energies within 1e-10 Eh plus eight times the oracle's own rounding spread for that target.
+The spread is measured by the oracle itself: the same decomposition with every residual column
+summed in reverse order and the transform associated the other way moves the energy by
+P dSigma (0.6e-10 ... 5.7e-10 Eh for the virtual targets).  This workload's MO coefficients are
+ill-conditioned (C = S^-1/2 Q with smallest overlap eigenvalue ~2e-7), which amplifies the
+rounding of any FP64 evaluation by about 1/lambda_min.  The spread is one sample of how far
+re-associating the sums moves a result; the device path groups its sums differently in more
+places (the blocked look-ahead decomposition, the MFMA transform and contraction), so the bar is
+eight such samples.  Pole strengths likewise with P^2 dSigma'.
 """
 import json
 import os
@@ -69,8 +71,8 @@ def test_large_fp64_quasiparticles_match_oracle(run):
     g, out = run
     qp = out["fp64"][4]
     err = np.abs(qp.omega - np.asarray(g["omega"]))
-    tol = 1e-10 + 4.0 * np.asarray(g["omega_rounding_spread"])
-    ptol = 1e-10 + 4.0 * np.asarray(g["pole_rounding_spread"])
+    tol = 1e-10 + 8.0 * np.asarray(g["omega_rounding_spread"])
+    ptol = 1e-10 + 8.0 * np.asarray(g["pole_rounding_spread"])
     perr = np.abs(qp.pole - np.asarray(g["pole"]))
     log(f"  FP64 max |dw| = {err.max():.2e} Eh; |dw| / bound max {np.max(err / tol):.2f}; "
         f"|dP| / bound max {np.max(perr / ptol):.2f}")
