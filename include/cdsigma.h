@@ -279,9 +279,11 @@ int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const d
  * one.  The results are those of
  * cds_cholesky_sgauss(..., nvec_in = 0, ...) followed by cds_transform(...,
  * nvec = *h_nvec, ...) with the same arguments, bit for bit (each vector's
- * blocks do not depend on how the vectors are batched).
- * ldk >= max_vec (the number of vectors is known only at the end); entries K
- * in [*h_nvec, ldk) are written as 0.  On CDS_ECAP and CDS_ENOTPSD the vectors
+ * blocks do not depend on how the vectors are batched), over the entries K <
+ * min(ldk, *h_nvec rounded up to 64).  ldk >= max_vec (the number of vectors
+ * is known only at the end); entries K in [*h_nvec, min(ldk, *h_nvec rounded
+ * up to 64)) are written as 0 and those beyond are left untouched: no
+ * consumer of the blocks reads past that multiple of 64.  On CDS_ECAP and CDS_ENOTPSD the vectors
  * made are transformed as well.  Before returning, the call makes the caller's
  * stream wait for the side stream, so work queued there afterwards sees Bsel
  * and Bvo.  Arguments, layouts and other errors as the two calls.  The
@@ -301,7 +303,8 @@ int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const double *centr
  *   h_sigma[s*T + t]  = Sigma_qq(h_omega[s*T + t]),   q = h_sel[s]
  *   h_dsigma[s*T + t] = dSigma_qq/domega at the same energy.
  * Bsel, Bvo as written by cds_transform with the same prec, nvec, ldk, nmo,
- * nocc, nsel.  eps: device double[nmo] orbital energies (occupied first).
+ * nocc, nsel (entries K in [nvec, min(ldk, nvec rounded up to 64)) must be 0;
+ * entries past that are never read).  eps: device double[nmo] orbital energies (occupied first).
  * The contraction runs in `prec`; denominators and sums run in FP64.
  */
 int cds_sigma2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo, int32_t nocc,
@@ -330,8 +333,11 @@ int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t 
  * of F(w, theta) = e_q + Sigma_qq(w; theta) - w = 0 (not in the paper):
  *   d(w*)/d(theta) = P dF/dtheta,  P = 1/(1 - Sigma'(w*)).
  * Given converged h_omega[s] and cotangents h_omega_bar[s], accumulates
- * (overwrites) Bsel_bar, Bvo_bar (layouts and precision of Bsel, Bvo) and
- * eps_bar (device double[nmo]) with sum_s omega_bar_s d(w*_s)/d(theta).  The
+ * (overwrites) Bsel_bar, Bvo_bar and eps_bar (device double[nmo]) with
+ * sum_s omega_bar_s d(w*_s)/d(theta).  Bsel_bar and Bvo_bar have the row
+ * layout of Bsel and Bvo (rows of ldk entries, K contiguous) in double for
+ * CDS_PREC_FP64 and in float for CDS_PREC_FP32 and CDS_PREC_BF16X3 (one plane,
+ * not the split pair); entries K in [nvec, ldk) are written as 0.  The
  * gradient w.r.t. B is taken with Bsel and Bvo as independent inputs.
  */
 int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
@@ -344,8 +350,10 @@ int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_
  *   C_bar = sum_K L^K C (Bbar^K + Bbar^K^T),
  * where Bbar^K (nmo x nmo) holds Bsel_bar[s, r, K] at row h_sel[s] and
  * Bvo_bar[a, i, K] at (nocc + a, i), zero elsewhere (accumulated where they
- * overlap).  Bsel_bar, Bvo_bar in the layout and precision `prec` of
- * cds_transform.  C_bar: nbf x nmo row-major, overwritten.
+ * overlap).  Bsel_bar, Bvo_bar: rows of ldk entries as cds_qp_adjoint writes
+ * them, double for prec = CDS_PREC_FP64 and float for CDS_PREC_FP32 or
+ * CDS_PREC_BF16X3.  C_bar:
+ * nbf x nmo row-major, overwritten.
  */
 int cds_transform_adjoint(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec,
                           const double *L, int64_t ldl, const double *C, int32_t nmo,

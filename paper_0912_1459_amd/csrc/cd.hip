@@ -1566,6 +1566,11 @@ __global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict_
 // zero row of P and add exactly 0.  L and P are deliberately not __restrict__: the
 // compiler may then not move their loads across the compiler barrier that keeps the ring
 // ahead of the MFMAs.
+// W16 (even ldl, 16-byte aligned L): every lane loads two adjacent rows of L and two adjacent
+// candidates of P at once (16 bytes), half the load instructions of one row each; the MFMA
+// row (column) r16 of block 2u + h is then tile row (candidate) 32u + 2 r16 + h.  Each output
+// takes the same products in the same order either way.
+template <bool W16>
 __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_t ldl, int64_t npairs,
                                                          int64_t k0, const CdState *__restrict__ st,
                                                          const double *P, double *__restrict__ R,
@@ -1581,8 +1586,15 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
     const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
     const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
     int64_t rowL[4];
+    if constexpr (W16) {
+        // pair starts are even and at most ldl - 2 (ldl even): a start past npairs - 1 only
+        // feeds rows that are never written
 #pragma unroll
-    for (int m = 0; m < 4; ++m) rowL[m] = min(tile0 + 16 * m + r16, npairs - 1);
+        for (int u = 0; u < 2; ++u) rowL[u] = min(tile0 + 32 * u + 2 * r16, ldl - 2);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) rowL[m] = min(tile0 + 16 * m + r16, npairs - 1);
+    }
     const int64_t ks = (k0 + 3) / 4;                       // k-steps
     const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
     const int64_t jz = 4 * ks;                             // a zero row of P (k0 <= jz < k0 + 4)
@@ -1597,11 +1609,29 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
         const int64_t j = 4 * s + g;
         const int64_t jl = min(j, jl_max);                 // L row: finite
         const int64_t jp = s < s1 ? j : jz;                // P row: zero past the range
+        if constexpr (W16) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) as[m] = L[jl * ldl + rowL[m]];
+            for (int u = 0; u < 2; ++u) {
+                const double2 x = *reinterpret_cast<const double2 *>(L + jl * ldl + rowL[u]);
+                as[2 * u] = x.x;
+                as[2 * u + 1] = x.y;
+            }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) bs[n] = P[jp * CD_NCAND + 16 * n + r16];
+            for (int u = 0; u < 2; ++u) {
+                const double2 y = *reinterpret_cast<const double2 *>(P + jp * CD_NCAND + 32 * u + 2 * r16);
+                bs[2 * u] = y.x;
+                bs[2 * u + 1] = y.y;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) as[m] = L[jl * ldl + rowL[m]];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bs[n] = P[jp * CD_NCAND + 16 * n + r16];
+        }
     };
+    // tile row of MFMA block m, lane row q (0..15), and candidate of block n, lane column r
+    auto trow = [&](int m, int q) { return W16 ? 32 * (m >> 1) + 2 * q + (m & 1) : 16 * m + q; };
+    auto tcol = [&](int n, int r) { return W16 ? 32 * (n >> 1) + 2 * r + (n & 1) : 16 * n + r; };
     if (k0 > 0) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -1623,8 +1653,8 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
             }
         }
     }
-    // fixed-order sum of the four partial blocks, (w0 + w2) + (w1 + w3); the lane holds rows
-    // 16m + g + 4e of candidate 16n + r16; LDS entry (c, row) sits at c * 64 + (row ^ c)
+    // fixed-order sum of the four partial blocks, (w0 + w2) + (w1 + w3); the lane holds tile
+    // rows trow(m, g + 4e) of candidate tcol(n, r16); LDS entry (c, row) sits at c * 64 + (row ^ c)
     auto put = [&](int slot) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -1632,7 +1662,7 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
             for (int n = 0; n < 4; ++n)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int c = 16 * n + r16, row = 16 * m + g + 4 * e;
+                    const int c = tcol(n, r16), row = trow(m, g + 4 * e);
                     red[slot][c][row ^ c] = acc[m][n][e];
                 }
     };
@@ -1643,7 +1673,7 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
             for (int n = 0; n < 4; ++n)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int c = 16 * n + r16, row = 16 * m + g + 4 * e;
+                    const int c = tcol(n, r16), row = trow(m, g + 4 * e);
                     acc[m][n][e] += red[slot][c][row ^ c];
                 }
     };
@@ -1886,6 +1916,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     int batch = 16;                     // batch ends fall on look-ahead block starts (16, 32, 64)
     CdState hs = {};
     const dim3 grid((unsigned)ntile);
+    // 16-byte loads of L in the pass need an even row stride and an aligned base
+    const bool pass16 = ldl % 2 == 0 && cds_aligned(L, 16);
     CdsTimer tk;
     bool run_timed = false;
     // speculative blocks, chained on the device.  With the mailbox, two blocks stay queued:
@@ -1917,9 +1949,14 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         CDS_LAUNCHED(ctx);
         CdsTimer tp;
         if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
-        hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
-                           (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                           (const signed char *)bf.slot, bf.rc);
+        if (pass16)
+            hipLaunchKernelGGL(cd_pass_kernel<true>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
+                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc);
+        else
+            hipLaunchKernelGGL(cd_pass_kernel<false>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
+                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc);
         CDS_LAUNCHED(ctx);
         if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
         if (hook && hook->block) CDS_CALL(hook->block(hook->user));
@@ -2042,9 +2079,14 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 CDS_LAUNCHED(ctx);
                 CdsTimer tp;
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
-                hipLaunchKernelGGL(cd_pass_kernel, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs, k,
-                                   (const CdState *)st, (const double *)Pc, Rc, ldr, (const signed char *)bf.slot,
-                                   bf.rc);
+                if (pass16)
+                    hipLaunchKernelGGL(cd_pass_kernel<true>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                                       npairs, k, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                                       (const signed char *)bf.slot, bf.rc);
+                else
+                    hipLaunchKernelGGL(cd_pass_kernel<false>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                                       npairs, k, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                                       (const signed char *)bf.slot, bf.rc);
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
                 ctx->stats.n_cd_pass_launch += 1;

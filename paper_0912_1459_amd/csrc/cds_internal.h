@@ -152,6 +152,24 @@ int cds_cholesky_hooked(cds_ctx *ctx, int32_t nbf, const double *centres, const 
                         double tau, double psd_tol, int64_t max_vec, double *L, int64_t ldl, int64_t *piv,
                         double *D, int64_t *h_nvec, double *h_dmax, int32_t *h_status, const CdHook *hook);
 
+// One direct-to-LDS load of 16 bytes per lane (global_load_lds_dwordx4: lane t's bytes go to
+// LDS address dst + 16 t, dst wave-uniform, passed in m0).  Written out in assembly so that the
+// compiler does not track it: its tracking of such loads cannot tell a double-buffered kernel's
+// two LDS stages apart and makes every LDS read wait for every load in flight, the next stage's
+// prefetch included.  The caller therefore waits itself (s_waitcnt vmcnt, then a workgroup
+// barrier) before the data is read, and before a buffer is refilled every wave must have read
+// it.  The instruction writes no register.  No kernel of this library uses m0 otherwise.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+static __device__ __forceinline__ void cds_lds_dma16(const void *src, void *dst)
+{
+    const unsigned m = __builtin_amdgcn_readfirstlane(
+        (unsigned)(uintptr_t)(__attribute__((address_space(3))) void *)dst);
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(m)
+                 : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
 // GEMM engine (gemm.hip): C[b][m][n] = alpha * sum_k A(m,k) B(k,n) (+ beta C)
 struct GemmDesc {
     int64_t M, N, K, batch;
@@ -164,6 +182,9 @@ struct GemmDesc {
     double alpha, beta;      // beta: 0 overwrite, 1 accumulate
     void *Clo;               // BF16X3 only, beta 0: C and Clo receive the hi and lo bf16 planes
                              // of the result (same element offsets) instead of floats
+    int big;                 // BF16X3 only: 0 = 256 x 256 tiles when M and N are both >= 512,
+                             // 1 = never, 2 = whenever the operands allow (a choice that must not
+                             // depend on how a caller batches its rows)
 };
 // prec of A/B/C: FP64 -> double, FP32/BF16X3 -> float storage
 int cds_gemm(cds_ctx *ctx, int prec, const GemmDesc &d);

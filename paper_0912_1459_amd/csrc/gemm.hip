@@ -43,6 +43,7 @@ struct Args {
     int64_t sCm, sCn, sCb;
     double alpha, beta;
     int fastA, fastB;              // K-contiguous, 16-byte aligned rows, K % KB == 0
+    int big;                       // GemmDesc::big
 };
 
 template <int PREC> struct Tr;
@@ -164,6 +165,8 @@ __global__ __launch_bounds__(NT, PREC == CDS_PREC_FP64 ? 1 : 2) void gemm_kernel
 
     const bool gA = !a.fastA && (a.sAk != 1 && a.sAm == 1);
     const bool gB = !a.fastB && (a.sBk != 1 && a.sBn == 1);
+    // a wave whose 64 x 64 block lies wholly outside C only helps to stage the operands
+    const bool live = m0 + wm < a.M && n0 + wn < a.N;
 
     typedef typename std::conditional<PREC == CDS_PREC_FP64, doublex4, floatx4>::type Acc;
     Acc acc[4][4];
@@ -187,6 +190,7 @@ __global__ __launch_bounds__(NT, PREC == CDS_PREC_FP64 ? 1 : 2) void gemm_kernel
             load_tile<PREC>(a, true, m0, (kt + 1) * KB, batch, ra, a.fastA);
             load_tile<PREC>(a, false, n0, (kt + 1) * KB, batch, rb, a.fastB);
         }
+        if (!live) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int off = (g + 4 * h) * 16;
@@ -284,7 +288,6 @@ constexpr int GB_M = 256, GB_N = 256, GB_K = 32, GB_NT = 512, GB_GM = 4;
 constexpr int GB_PLANE = GB_M * GB_K * 2;       // bytes of one operand plane per stage (16 KB)
 constexpr int GB_STAGE = 4 * GB_PLANE;          // A hi, A lo, B hi, B lo (64 KB)
 
-typedef __attribute__((address_space(3))) void lds_void_t;
 
 // s_waitcnt with vmcnt = n (expcnt, lgkmcnt left alone)
 template <int N>
@@ -312,7 +315,7 @@ __device__ __forceinline__ void gb_stage(const Args &a, unsigned char *buf, int6
         const unsigned char *base = isA ? (op == 0 ? a.A : a.Alo) : (op == 2 ? a.B : a.Blo);
         const int64_t srow = isA ? a.sAm : a.sBn, sb = isA ? a.sAb : a.sBb;
         const __bf16 *src = reinterpret_cast<const __bf16 *>(base) + batch * sb + grow * srow + k0 + chunk * 8;
-        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(buf + op * GB_PLANE + rg * 1024), 16, 0, 0);
+        cds_lds_dma16(src, buf + op * GB_PLANE + rg * 1024);
     }
 }
 
@@ -431,7 +434,8 @@ int launch(cds_ctx *ctx, Args &a)
     if (gy > 65535 || a.batch > 65535)
         return cds_fail(ctx, CDS_EINVAL, "GEMM grid too large (%lld x %lld x %lld)", (long long)gx,
                         (long long)gy, (long long)a.batch);
-    if (PREC == CDS_PREC_BF16X3 && a.M >= 512 && a.N >= 512 && a.K % GB_K == 0 &&
+    const bool want_big = a.big == 0 ? (a.M >= 512 && a.N >= 512) : a.big == 2;
+    if (PREC == CDS_PREC_BF16X3 && want_big && a.K % GB_K == 0 &&
         cds_aligned(a.A, 16) && cds_aligned(a.Alo, 16) && cds_aligned(a.B, 16) && cds_aligned(a.Blo, 16)) {
         const int64_t tm = cds_ceil_div(a.M, GB_M), tn = cds_ceil_div(a.N, GB_N);
         if (tm * tn <= 0x7fffffff) {
@@ -520,6 +524,7 @@ int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, cons
     a.sCb = d.sCb;
     a.alpha = d.alpha;
     a.beta = d.beta;
+    a.big = d.big;
     if (prec == CDS_PREC_FP64) return launch<CDS_PREC_FP64>(ctx, a);
     if (prec == CDS_PREC_FP32) return launch<CDS_PREC_FP32>(ctx, a);
     if (prec == CDS_PREC_BF16X3) return launch<CDS_PREC_BF16X3>(ctx, a);

@@ -155,7 +155,7 @@ extern "C" int cds_mp2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, in
         GemmDesc d = {};
         d.M = (int64_t)n_a * nocc;
         d.N = ncols;
-        d.K = cds_ceil_div(nvec, 64) * 64;      // entries K in [nvec, ldk) are zero
+        d.K = cds_ceil_div(nvec, 64) * 64;      // entries K in [nvec, this) are zero
         d.batch = 1;
         d.A = (const unsigned char *)Bvo + (size_t)a0 * nocc * ldk * es;
         d.sAm = ldk;

@@ -423,25 +423,39 @@ __global__ __launch_bounds__(EP_NT) void sweep_kernel(EpArgs e, const int *__res
     }
 }
 
-// out[s][t][c] = sum over blocks of part[s][blk][t][c] in block order
-__global__ void reduce_partials_kernel(const double *__restrict__ part, int nsc, int nblk, int T,
-                                       double *__restrict__ out)
+// Sum of part[s][b][t][c] over the blocks b of one output (s, t, c), by one workgroup of 256
+// threads in a fixed order: thread j adds blocks j, j + 256, ... in turn, the 64 lanes of a wave
+// are combined by a butterfly and the four waves in order (deterministic, and the same in both
+// kernels below).
+__device__ __forceinline__ double reduce_blocks(const double *__restrict__ part, int s, int tc, int nblk, int T)
 {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nsc * T * 2) return;
-    int s = idx / (T * 2), tc = idx - s * T * 2;
-    // in block order, eight loads in flight at a time
-    constexpr int U = 8;
+    __shared__ double sh[4];
     double acc = 0.0;
-    for (int b0 = 0; b0 < nblk; b0 += U) {
+    constexpr int U = 4;
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += U * 256) {
         double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = b0 + u < nblk ? part[((int64_t)s * nblk + b0 + u) * T * 2 + tc] : 0.0;
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * 256;
+            v[u] = b < nblk ? part[((int64_t)s * nblk + b) * T * 2 + tc] : 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (b0 + u < nblk) acc += v[u];
+            if (b0 + u * 256 < nblk) acc += v[u];
     }
-    out[idx] = acc;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// out[s][t][c]: one workgroup per output (grid nsc * T * 2)
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__restrict__ part, int nsc, int nblk,
+                                                              int T, double *__restrict__ out)
+{
+    const int idx = blockIdx.x, s = idx / (T * 2), tc = idx - s * T * 2;
+    const double v = reduce_blocks(part, s, tc, nblk, T);
+    if (threadIdx.x == 0) out[idx] = v;
 }
 
 struct SigmaShape {
@@ -519,7 +533,7 @@ int contract_chunk(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const v
     GemmDesc d = {};
     d.M = (int64_t)nsc * sh.nmo;
     d.N = sh.nvo;
-    // entries K in [nvec, ldk) are zero: the sum stops at the first multiple of 64 past nvec
+    // entries K in [nvec, this) are zero: the sum stops at the first multiple of 64 past nvec
     d.K = std::min<int64_t>(sh.ldk, cds_ceil_div(sh.nvec, 64) * 64);
     d.batch = 1;
     d.A = (const unsigned char *)Bsel + (size_t)s0 * sh.nmo * sh.ldk * es;
@@ -614,7 +628,7 @@ int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void 
             CdsTimer t2;
             CDS_CALL(cds_timer_start(ctx, &t2));
             const int nout = nsc * T * 2;
-            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(nout, 256)), dim3(256), 0,
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)nout), dim3(256), 0,
                                ctx->stream, (const double *)part, nsc, (int)fp.tpt, T,
                                (double *)out + (int64_t)s0 * T * 2);
             CDS_LAUNCHED(ctx);
@@ -652,7 +666,7 @@ int eval_sigma(cds_ctx *ctx, const SigmaShape &sh, const void *Bsel, const void 
         CDS_CALL(cds_timer_start(ctx, &t));
         CDS_CALL(launch_epilogue<EP_SIGMA>(ctx, sh, e, sh.prec == CDS_PREC_FP64));
         int n = nsc * T * 2;
-        hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)n), dim3(256), 0,
                            ctx->stream, (const double *)part, nsc, nblk, T,
                            (double *)out + (int64_t)s0 * T * 2);
         CDS_LAUNCHED(ctx);
@@ -868,7 +882,7 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
                 CDS_LAUNCHED(ctx);
             }
             int n = (int)active.size() * 2;
-            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0,
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)n), dim3(256), 0,
                                ctx->stream, (const double *)part, (int)active.size(), (int)nblk_sweep, 1,
                                (double *)outd);
             CDS_LAUNCHED(ctx);

@@ -34,7 +34,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) void lds_void_t;
 
 constexpr int FT = 128;                         // tile edge
 constexpr int FNT = 512;                        // threads per workgroup: 8 waves, 2 (rows) x 4 (cols)
@@ -44,7 +43,8 @@ constexpr int TPITCH = FT + 1;                  // transpose buffer pitch (eleme
 constexpr int DIAG_SLOTS = FT * (FT + 1) / 2;   // residues of a diagonal task
 constexpr int OFF_SLOTS = FT * FT;              // residues of an off-diagonal task
 constexpr int FTT = 8;                          // trial energies per epilogue pass (at most)
-constexpr int LDS_MAIN = (2 * STAGE > FT * TPITCH * 8) ? 2 * STAGE : FT * TPITCH * 8;
+// each of the two stage buffers also holds 64 rows of the diagonal tasks' transposition buffer
+constexpr int LDS_HALF = (STAGE > (FT / 2) * TPITCH * 8) ? STAGE : (FT / 2) * TPITCH * 8;
 
 template <int PREC> struct FTr;
 template <> struct FTr<CDS_PREC_FP64> {
@@ -206,7 +206,9 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
     constexpr int RPW = 1024 / RB;              // slice rows per wave load (per plane)
     constexpr int LPR = RB / 16;                // lanes per slice row
 
-    __shared__ __align__(16) unsigned char lds[LDS_MAIN];
+    // the two stage buffers (each also holds half of a diagonal task's transposition buffer)
+    __shared__ __align__(16) unsigned char lds0[LDS_HALF];
+    __shared__ __align__(16) unsigned char lds1[LDS_HALF];
     __shared__ double red[FNT / 64][2 * FTT];
     __shared__ double seps[2][FT];
 
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (i < nload)
-                __builtin_amdgcn_global_load_lds((const void *)(src[i] + koff), (lds_void_t *)(buf + ldst[i]), 16, 0, 0);
+                cds_lds_dma16(src[i] + koff, buf + ldst[i]);
     };
 
     // MFMA blocks of this wave inside the matrix (whole 16 x 16 blocks past its edge are skipped)
@@ -383,13 +385,10 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
     };
 
     // main loop: two LDS stages; the next stage's loads run under this stage's products
-    unsigned char *lds0 = lds, *lds1 = lds + STAGE;
+    // (unrolled by two: each step reads one fixed buffer and fills the other)
     auto main_loop = [&](auto OFFc, auto FULLc) {
         constexpr bool off = decltype(OFFc)::value;
-        stage_load(lds0, 0);
-        for (int64_t st = 0; st < a.ns; ++st) {
-            unsigned char *cur = (st & 1) ? lds1 : lds0;
-            unsigned char *nxt = (st & 1) ? lds0 : lds1;
+        auto step = [&](unsigned char *cur, unsigned char *nxt, int64_t st) {
             if (st + 1 < a.ns) {
                 stage_load(nxt, st + 1);              // nxt was freed by the last barrier
                 if (off) wait_vm<8>();                // this wave's loads of stage st have landed
@@ -401,6 +400,12 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
             compute(cur, OFFc, FULLc);
             __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0): this wave's LDS reads are done
             __builtin_amdgcn_s_barrier();             // cur may be refilled
+        };
+        stage_load(lds0, 0);
+        step(lds0, lds1, 0);
+        for (int64_t st = 1; st < a.ns; st += 2) {
+            step(lds1, lds0, st);
+            if (st + 1 < a.ns) step(lds0, lds1, st + 1);
         }
     };
     typedef std::integral_constant<bool, true> T_;
@@ -416,7 +421,10 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
 
     // epilogue.  Lane element (i, j, e): tile row rl = wr*64 + 16 i + rowmap(g, e), tile column
     // cl = wc*32 + 16 j + r16 (FP64 MFMA rows g + 4e, FP32-accumulating rows 4g + e)
-    A1 *tm = reinterpret_cast<A1 *>(lds);
+    // transposition buffer: tile row r at trow(r) (rows 0..63 in lds0, 64..127 in lds1)
+    auto trow = [&](int r) {
+        return reinterpret_cast<A1 *>(r < FT / 2 ? lds0 : lds1) + (r & (FT / 2 - 1)) * TPITCH;
+    };
     if (diag) {
         // partners through LDS: tm[rl][cl] = Y[rl][cl]; the stage buffers are free (last barrier)
 #pragma unroll
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
                 for (int e = 0; e < 4; ++e) {
                     const int rl = wr * 64 + 16 * i + (PREC == CDS_PREC_FP64 ? g + 4 * e : 4 * g + e);
                     const int cl = wc * 32 + 16 * j + r16;
-                    tm[rl * TPITCH + cl] = acc1[i][j][e];
+                    trow(rl)[cl] = acc1[i][j][e];
                 }
     }
     __syncthreads();
@@ -437,7 +445,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
         rl = wr * 64 + 16 * i + (PREC == CDS_PREC_FP64 ? g + 4 * e : 4 * g + e);
         cl = wc * 32 + 16 * j + r16;
         x = (double)acc1[i][j][e];
-        xt = diag ? (double)tm[cl * TPITCH + rl] : (double)acc2[i][j][e];
+        xt = diag ? (double)trow(cl)[rl] : (double)acc2[i][j][e];
         return gR0 + rl < n && gC0 + cl < n && (!diag || rl <= cl);
     };
     if constexpr (MODE == 0) {

@@ -2,18 +2,23 @@
 //   B^K_pq = sum_{mu,nu} C_mu,p L^K_mu,nu C_nu,q
 // for the blocks the self-energy reads: B^K[sel, :] and B^K[virt, occ].
 //
-// Per batch of vectors K (all on the GPU, batched over K):
+// Per batch of vectors K (all on the GPU):
 //   1. unpack   packed L^K -> dense symmetric Lu[K][mu][nu] (k padded to Np)
-//   2. GEMM     T[K][x][mu] = sum_nu CX[x][nu] Lu[K][mu][nu]      x = occ, then sel
-//   3. GEMM     Bk[K][a][i] = sum_mu Ct[nocc+a][mu] T[K][i][mu]    (virt x occ)
-//      GEMM     Bk[K][s][r] = sum_mu T[K][nocc+s][mu] Ct[r][mu]    (sel x all)
-//   4. transpose Bk[K][row] -> B[row][K] (K contiguous), converting to the
-//      output format (double, float, or bf16 hi/lo planes).
+//   2. GEMM     T[x][K][mu] = sum_nu CX[x][nu] Lu[K][mu][nu]      (batched over K)
+//      with x = the occupied orbitals, then the selected orbitals that are not occupied
+//      (an occupied target's row of T is its occupied row)
+//   3. GEMM     W[a][(i,K)] = sum_mu Ct[nocc+a][mu] T[i][K][mu]     (virt x occ, one product)
+//      GEMM     W[r][(s,K)] = sum_mu Ct[r][mu] T[x_s][K][mu]        (all x sel, one product
+//                                                                   per run of consecutive x_s)
+//   4. copy     W -> B[row][K] (K contiguous: each (row, batch) segment is contiguous in W),
+//      converting to the output format (double, float, or bf16 hi/lo planes).
 // Working precision of steps 1-3: FP64 for CDS_PREC_FP64, FP32 for FP32, and
 // split bf16 (3-term products, FP32 accumulation) for BF16X3.
 #include "cds_internal.h"
 
+#include <array>
 #include <type_traits>
+#include <vector>
 
 int cds_gemm_ex(cds_ctx *ctx, int prec, const GemmDesc &d, const void *Alo, const void *Blo);
 
@@ -100,13 +105,13 @@ __global__ __launch_bounds__(256) void unpack_blocks_kernel(const double *__rest
     put4(out, prec, base + (int64_t)nu_row * np_ + bm * 32 + c0, plane, v);
 }
 
-// Ct[p][mu] = C[mu][p]; CX rows: occupied 0..nocc-1 then sel[s]; k padded to np_
-__global__ void coef_kernel(const double *__restrict__ C, int nbf, int nmo, int nocc, int nsel,
-                            const int32_t *__restrict__ sel, int np_, void *Ct, void *CX, int prec,
+// Ct[p][mu] = C[mu][p]; CX rows: occupied 0..nocc-1 then the MOs ext[0..nx-nocc); k padded to np_
+__global__ void coef_kernel(const double *__restrict__ C, int nbf, int nmo, int nocc, int nx,
+                            const int32_t *__restrict__ ext, int np_, void *Ct, void *CX, int prec,
                             int64_t planeCt, int64_t planeCX)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t nrow = nmo + nocc + nsel;
+    int64_t nrow = nmo + nx;
     if (t >= nrow * np_) return;
     int row = (int)(t / np_), mu = (int)(t - (int64_t)row * np_);
     int p;
@@ -119,7 +124,7 @@ __global__ void coef_kernel(const double *__restrict__ C, int nbf, int nmo, int 
         plane = planeCt;
     } else {
         int x = row - nmo;
-        p = x < nocc ? x : sel[x - nocc];
+        p = x < nocc ? x : ext[x - nocc];
         dst = CX;
         idx = (int64_t)x * np_ + mu;
         plane = planeCX;
@@ -139,38 +144,33 @@ __global__ void zero_cols_kernel(unsigned char *base, int64_t nrows, int64_t pit
 }
 
 
-// Bk[kb][row] (working type W) -> out[row*ldk + k0 + kb] in the output format.
-// rows [0, nvo) go to Bvo, rows [nvo, nvo + nselr) to Bsel.
+// W (working type) -> out[row*ldk + k0 + kb] in the output format, one thread per (row, kb).
+// Rows [0, nvo) = (a, i) go to Bvo from W[(a*nocc + i)*nkb + kb]; rows nvo + s*nmo + r go to
+// Bsel from W[nvo*nkb + r*nsel*nkb + s*nkb + kb].  Reads and writes run along kb.
 template <typename W>
-__global__ void transpose_out_kernel(const W *__restrict__ Bk, int64_t nrows, int nkb, int64_t k0,
-                                     int64_t nvo, void *Bvo, void *Bsel, int64_t ldk, int prec,
-                                     int64_t plane_vo, int64_t plane_sel)
+__global__ __launch_bounds__(256) void copy_out_kernel(const W *__restrict__ Wb, int64_t nvo, int nmo, int nsel,
+                                                       int nkb, int64_t k0, void *Bvo, void *Bsel, int64_t ldk,
+                                                       int prec, int64_t plane_vo, int64_t plane_sel)
 {
-    __shared__ double tile[32][33];
-    int64_t r0 = (int64_t)blockIdx.x * 32;
-    int kb0 = blockIdx.y * 32;
-    int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
-    for (int j = ty; j < 32; j += 8) {
-        int kb = kb0 + j;
-        int64_t r = r0 + tx;
-        tile[j][tx] = (kb < nkb && r < nrows) ? (double)Bk[(int64_t)kb * nrows + r] : 0.0;
-    }
-    __syncthreads();
-    for (int j = ty; j < 32; j += 8) {
-        int64_t r = r0 + j;
-        int kb = kb0 + tx;
-        if (r >= nrows || kb >= nkb) continue;
-        double v = tile[tx][j];
-        if (r < nvo)
-            put(Bvo, prec, r * ldk + k0 + kb, plane_vo, v);
-        else
-            put(Bsel, prec, (r - nvo) * ldk + k0 + kb, plane_sel, v);
+    const int64_t nrows = nvo + (int64_t)nsel * nmo;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * nkb) return;
+    const int64_t row = t / nkb;
+    const int kb = (int)(t - row * nkb);
+    if (row < nvo) {
+        put(Bvo, prec, row * ldk + k0 + kb, plane_vo, (double)Wb[t]);
+    } else {
+        const int64_t rs = row - nvo;
+        const int sidx = (int)(rs / nmo), r = (int)(rs - (int64_t)sidx * nmo);
+        const double v = (double)Wb[nvo * nkb + ((int64_t)r * nsel + sidx) * nkb + kb];
+        put(Bsel, prec, rs * ldk + k0 + kb, plane_sel, v);
     }
 }
 
-__global__ void zero_pad_kernel(int64_t nrows, int64_t ldk, int64_t nvec, void *B, int prec, int64_t plane)
+__global__ void zero_pad_kernel(int64_t nrows, int64_t ldk, int64_t nvec, int64_t kend, void *B, int prec,
+                                int64_t plane)
 {
-    int64_t npad = ldk - nvec;
+    int64_t npad = kend - nvec;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrows * npad) return;
     int64_t r = t / npad, c = nvec + (t - r * npad);
@@ -185,9 +185,11 @@ struct TrPlan {
     int64_t nvo, nselr, nrows, ldl, ldk;
     const double *L, *C;
     void *Bsel, *Bvo;
-    const int32_t *h_sel;
+    std::vector<int32_t> ext;                 // CX rows past the occupied ones: these MOs
+    std::vector<int> xs;                      // row of T (x) of each selected orbital
+    std::vector<std::array<int, 3>> runs;     // (s0, count, x0): consecutive s with consecutive x
     unsigned char *Ct, *CX;
-    int32_t *dsel;
+    int32_t *dext;
     void *wlu, *wt, *wb;
     float *Tf;
     __bf16 *Ts;
@@ -222,7 +224,29 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     p.nocc = nocc;
     p.nsel = nsel;
     p.nvirt = nmo - nocc;
-    p.nx = nocc + nsel;
+    // an occupied target reads the occupied row of T; other targets get a row of their own
+    p.ext.clear();
+    p.xs.assign(nsel, 0);
+    for (int s = 0; s < nsel; ++s) {
+        const int q = h_sel[s];
+        if (q < nocc) {
+            p.xs[s] = q;
+            continue;
+        }
+        int j = 0;
+        while (j < (int)p.ext.size() && p.ext[j] != q) ++j;
+        if (j == (int)p.ext.size()) p.ext.push_back(q);
+        p.xs[s] = nocc + j;
+    }
+    p.runs.clear();
+    for (int s = 0; s < nsel; ++s) {
+        if (!p.runs.empty() && p.runs.back()[0] + p.runs.back()[1] == s &&
+            p.runs.back()[2] + p.runs.back()[1] == p.xs[s])
+            ++p.runs.back()[1];
+        else
+            p.runs.push_back({s, 1, p.xs[s]});
+    }
+    p.nx = nocc + (int)p.ext.size();
     p.np_ = (int)(cds_ceil_div(nbf, 64) * 64);
     p.nvo = (int64_t)p.nvirt * nocc;
     p.nselr = (int64_t)nsel * nmo;
@@ -230,15 +254,14 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     p.L = L;
     p.ldl = ldl;
     p.C = C;
-    p.h_sel = h_sel;
     p.ldk = ldk;
     p.Bsel = Bsel;
     p.Bvo = Bvo;
     // working precision of the GEMMs; the output is rounded to `prec` in the last pass
     p.wp = ctx->transform_fp64 ? CDS_PREC_FP64 : prec;
     const size_t es = wsize(p.wp);
-    // batch: the virtual-occupied GEMM has one 128 x 128 tile group per vector and would
-    // leave most of the chip idle with small batches
+    // batch: enough 128 x 128 tiles of the virtual-occupied product per launch to fill the
+    // chip (that product has one tile group of nvirt x nocc per vector)
     const int64_t tiles_vo = cds_ceil_div(p.nvirt, 128) * cds_ceil_div(nocc, 128);
     int64_t kb_want = std::max<int64_t>(KBATCH_MIN, cds_ceil_div(KBATCH_WG, tiles_vo));
     kb_want = std::min<int64_t>(kb_want, std::max<int64_t>(1, (int64_t)(KBATCH_BYTES / ((size_t)nbf * p.np_ * es))));
@@ -255,7 +278,7 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     CDS_CALL(cds_ws(ctx, WS_TR_B, (size_t)p.kbatch * p.nrows * (p.wp == CDS_PREC_FP64 ? 8 : 4), &p.wb));
     p.Ct = (unsigned char *)wcx;
     p.CX = p.Ct + nCt * es;
-    p.dsel = (int32_t *)(p.CX + ((nCX * es + 255) / 256) * 256);
+    p.dext = (int32_t *)(p.CX + ((nCX * es + 255) / 256) * 256);
     // for bf16 the hi and lo planes of Ct / CX take 2 x 2 bytes = es per element: each lo
     // plane follows its hi plane inside the same byte range
     p.planeCt = nCt;
@@ -269,11 +292,12 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
 // coefficient copies and the zero K padding of T (once per transform)
 int tr_setup(cds_ctx *ctx, const TrPlan &p)
 {
-    CDS_HIP(ctx, hipMemcpyAsync(p.dsel, p.h_sel, (size_t)p.nsel * 4, hipMemcpyHostToDevice, ctx->stream));
+    if (!p.ext.empty())
+        CDS_HIP(ctx, hipMemcpyAsync(p.dext, p.ext.data(), p.ext.size() * 4, hipMemcpyHostToDevice, ctx->stream));
     {
         int64_t n = (int64_t)(p.nmo + p.nx) * p.np_;
         hipLaunchKernelGGL(coef_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0, ctx->stream,
-                           p.C, p.nbf, p.nmo, p.nocc, p.nsel, p.dsel, p.np_, (void *)p.Ct, (void *)p.CX, p.wp,
+                           p.C, p.nbf, p.nmo, p.nocc, p.nx, p.dext, p.np_, (void *)p.Ct, (void *)p.CX, p.wp,
                            p.planeCt, p.planeCX);
         CDS_LAUNCHED(ctx);
     }
@@ -290,15 +314,15 @@ int tr_setup(cds_ctx *ctx, const TrPlan &p)
     return CDS_OK;
 }
 
-// zero entries K in [nvec, ldk) of both output blocks
-int tr_pad(cds_ctx *ctx, const TrPlan &p, int64_t nvec)
+// zero entries K in [nvec, kend) of both output blocks, kend <= ldk
+int tr_pad(cds_ctx *ctx, const TrPlan &p, int64_t nvec, int64_t kend)
 {
-    if (p.ldk > nvec) {
-        int64_t n1 = p.nvo * (p.ldk - nvec), n2 = p.nselr * (p.ldk - nvec);
+    if (kend > nvec) {
+        int64_t n1 = p.nvo * (kend - nvec), n2 = p.nselr * (kend - nvec);
         hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)cds_ceil_div(n1, 256)), dim3(256), 0, ctx->stream, p.nvo,
-                           p.ldk, nvec, p.Bvo, p.prec, p.nvo * p.ldk);
+                           p.ldk, nvec, kend, p.Bvo, p.prec, p.nvo * p.ldk);
         hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)cds_ceil_div(n2, 256)), dim3(256), 0, ctx->stream,
-                           p.nselr, p.ldk, nvec, p.Bsel, p.prec, p.nselr * p.ldk);
+                           p.nselr, p.ldk, nvec, kend, p.Bsel, p.prec, p.nselr * p.ldk);
         CDS_LAUNCHED(ctx);
     }
     return CDS_OK;
@@ -316,14 +340,15 @@ int tr_batch(cds_ctx *ctx, const TrPlan &p, int64_t k0, int nkb)
     }
     const int64_t planeLu = (int64_t)nkb * nbf * np_;
     const int gprec = p.wp;
-    // T[kb][x][mu] = sum_nu CX[x][nu] Lu[kb][mu][nu]
+    // T[x][kb][mu] = sum_nu CX[x][nu] Lu[kb][mu][nu]   (row (x, kb) of T at (x*nkb + kb)*np_)
     GemmDesc g1 = {};
     g1.M = nx; g1.N = nbf; g1.K = np_; g1.batch = nkb;
     g1.A = p.CX; g1.sAm = np_; g1.sAk = 1; g1.sAb = 0;
     g1.B = p.wlu; g1.sBn = np_; g1.sBk = 1; g1.sBb = (int64_t)nbf * np_;
     void *Tout = (p.wp == CDS_PREC_FP64) ? p.wt : (void *)p.Tf;
-    g1.C = Tout; g1.sCm = np_; g1.sCn = 1; g1.sCb = (int64_t)nx * np_;
+    g1.C = Tout; g1.sCm = (int64_t)nkb * np_; g1.sCn = 1; g1.sCb = np_;
     g1.alpha = 1.0; g1.beta = 0.0;
+    g1.big = 1;
     if (p.wp == CDS_PREC_BF16X3) {
         // T straight into its two bf16 planes (the split of the FP32 result)
         g1.C = p.Ts;
@@ -332,40 +357,50 @@ int tr_batch(cds_ctx *ctx, const TrPlan &p, int64_t k0, int nkb)
     } else {
         CDS_CALL(cds_gemm_ex(ctx, gprec, g1, nullptr, nullptr));
     }
-    const void *Tin = (p.wp == CDS_PREC_BF16X3) ? (const void *)p.Ts : (const void *)Tout;
+    const unsigned char *Tin = (const unsigned char *)((p.wp == CDS_PREC_BF16X3) ? (const void *)p.Ts : Tout);
     const int64_t planeT = (int64_t)nkb * nx * np_;
     const size_t tes = (p.wp == CDS_PREC_FP64) ? 8 : (p.wp == CDS_PREC_FP32 ? 4 : 2);
-    const size_t ces = tes;
-    // Bk[kb][a][i] = sum_mu Ct[nocc+a][mu] T[kb][i][mu]
+    const size_t wes = (p.wp == CDS_PREC_FP64) ? 8 : 4;
+    // the 256 x 256 split-bf16 tiles are chosen from the per-vector shapes only, so that a
+    // vector's blocks do not depend on the batching
+    // W[a][i*nkb + kb] = sum_mu Ct[nocc+a][mu] T[i][kb][mu]
     GemmDesc g2 = {};
-    g2.M = p.nvirt; g2.N = nocc; g2.K = np_; g2.batch = nkb;
-    g2.A = p.Ct + (size_t)nocc * np_ * ces; g2.sAm = np_; g2.sAk = 1; g2.sAb = 0;
-    g2.B = Tin; g2.sBn = np_; g2.sBk = 1; g2.sBb = (int64_t)nx * np_;
-    g2.C = p.wb; g2.sCm = nocc; g2.sCn = 1; g2.sCb = p.nrows;
+    g2.M = p.nvirt; g2.N = (int64_t)nocc * nkb; g2.K = np_; g2.batch = 1;
+    g2.A = p.Ct + (size_t)nocc * np_ * tes; g2.sAm = np_; g2.sAk = 1;
+    g2.B = Tin; g2.sBn = np_; g2.sBk = 1;
+    g2.C = p.wb; g2.sCm = (int64_t)nocc * nkb; g2.sCn = 1;
     g2.alpha = 1.0; g2.beta = 0.0;
-    // Bk[kb][nvo + s*nmo + r] = sum_mu T[kb][nocc+s][mu] Ct[r][mu]
-    GemmDesc g3 = {};
-    g3.M = nsel; g3.N = nmo; g3.K = np_; g3.batch = nkb;
-    g3.A = (const unsigned char *)Tin + (size_t)nocc * np_ * tes; g3.sAm = np_; g3.sAk = 1;
-    g3.sAb = (int64_t)nx * np_;
-    g3.B = p.Ct; g3.sBn = np_; g3.sBk = 1; g3.sBb = 0;
-    g3.C = (unsigned char *)p.wb + (size_t)p.nvo * (p.wp == CDS_PREC_FP64 ? 8 : 4);
-    g3.sCm = nmo; g3.sCn = 1; g3.sCb = p.nrows;
-    g3.alpha = 1.0; g3.beta = 0.0;
-    if (p.wp == CDS_PREC_BF16X3) {
-        CDS_CALL(cds_gemm_ex(ctx, gprec, g2, (const __bf16 *)p.Ct + p.planeCt + (int64_t)nocc * np_, p.Ts + planeT));
-        CDS_CALL(cds_gemm_ex(ctx, gprec, g3, p.Ts + planeT + (int64_t)nocc * np_, (const __bf16 *)p.Ct + p.planeCt));
-    } else {
-        CDS_CALL(cds_gemm_ex(ctx, gprec, g2, nullptr, nullptr));
-        CDS_CALL(cds_gemm_ex(ctx, gprec, g3, nullptr, nullptr));
-    }
-    dim3 tg((unsigned)cds_ceil_div(p.nrows, 32), (unsigned)cds_ceil_div(nkb, 32));
-    if (p.wp == CDS_PREC_FP64)
-        hipLaunchKernelGGL(transpose_out_kernel<double>, tg, dim3(256), 0, ctx->stream, (const double *)p.wb, p.nrows,
-                           nkb, k0, p.nvo, p.Bvo, p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
+    g2.big = p.nvirt >= 512 ? 2 : 1;
+    if (p.wp == CDS_PREC_BF16X3)
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g2, (const __bf16 *)p.Ct + p.planeCt + (int64_t)nocc * np_,
+                             p.Ts + planeT));
     else
-        hipLaunchKernelGGL(transpose_out_kernel<float>, tg, dim3(256), 0, ctx->stream, (const float *)p.wb, p.nrows,
-                           nkb, k0, p.nvo, p.Bvo, p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
+        CDS_CALL(cds_gemm_ex(ctx, gprec, g2, nullptr, nullptr));
+    // W[nvo*nkb + r*nsel*nkb + s*nkb + kb] = sum_mu Ct[r][mu] T[x_s][kb][mu], one product per run
+    for (const auto &run : p.runs) {
+        const int s0 = run[0], cnt = run[1], x0 = run[2];
+        GemmDesc g3 = {};
+        g3.M = nmo; g3.N = (int64_t)cnt * nkb; g3.K = np_; g3.batch = 1;
+        g3.A = p.Ct; g3.sAm = np_; g3.sAk = 1;
+        g3.B = Tin + (size_t)x0 * nkb * np_ * tes; g3.sBn = np_; g3.sBk = 1;
+        g3.C = (unsigned char *)p.wb + ((size_t)p.nvo * nkb + (size_t)s0 * nkb) * wes;
+        g3.sCm = (int64_t)nsel * nkb; g3.sCn = 1;
+        g3.alpha = 1.0; g3.beta = 0.0;
+        g3.big = nmo >= 512 ? 2 : 1;
+        if (p.wp == CDS_PREC_BF16X3)
+            CDS_CALL(cds_gemm_ex(ctx, gprec, g3, (const __bf16 *)p.Ct + p.planeCt,
+                                 p.Ts + planeT + (int64_t)x0 * nkb * np_));
+        else
+            CDS_CALL(cds_gemm_ex(ctx, gprec, g3, nullptr, nullptr));
+    }
+    const int64_t nel = p.nrows * nkb;
+    const dim3 cg((unsigned)cds_ceil_div(nel, 256));
+    if (p.wp == CDS_PREC_FP64)
+        hipLaunchKernelGGL(copy_out_kernel<double>, cg, dim3(256), 0, ctx->stream, (const double *)p.wb, p.nvo, nmo,
+                           nsel, nkb, k0, p.Bvo, p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
+    else
+        hipLaunchKernelGGL(copy_out_kernel<float>, cg, dim3(256), 0, ctx->stream, (const float *)p.wb, p.nvo, nmo,
+                           nsel, nkb, k0, p.Bvo, p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
     CDS_LAUNCHED(ctx);
     return CDS_OK;
 }
@@ -450,7 +485,7 @@ extern "C" int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nv
     TrPlan p;
     CDS_CALL(tr_alloc(ctx, p, prec, nbf, L, ldl, C, nmo, nocc, nsel, h_sel, ldk, Bsel, Bvo, nvec));
     CDS_CALL(tr_setup(ctx, p));
-    CDS_CALL(tr_pad(ctx, p, nvec));
+    CDS_CALL(tr_pad(ctx, p, nvec, p.ldk));
     CDS_CALL(tr_range(ctx, p, 0, nvec));
     CDS_CALL(cds_timer_stop(ctx, &tm, &ctx->stats.t_transform_ms));
     return CDS_OK;
@@ -496,7 +531,9 @@ extern "C" int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const do
         const std::string err = ctx->err;
         if (!ov.started) rt = tr_setup(ctx, p);
         if (rt == CDS_OK && *h_nvec > ov.kdone) rt = tr_range(ctx, p, ov.kdone, *h_nvec);
-        if (rt == CDS_OK) rt = tr_pad(ctx, p, *h_nvec);
+        // ldk was sized for max_vec: only the entries up to the next multiple of 64, the last any
+        // consumer of the blocks reads, are cleared
+        if (rt == CDS_OK) rt = tr_pad(ctx, p, *h_nvec, std::min<int64_t>(p.ldk, cds_ceil_div(*h_nvec, 64) * 64));
         if (rt == CDS_OK) ctx->err = err;
     }
     // the caller's stream waits for the side stream

@@ -97,6 +97,34 @@ def test_transform_fp64_working_precision(cds, prec, tol):
     assert es <= tol and ev <= tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_transform_scattered_selection(cds, prec):
+    # targets out of order, repeated, occupied and virtual mixed: each selected orbital's block
+    # must still be its own row of B^K (the transform shares the occupied rows and groups runs)
+    name, delta = "small_cage", 1e-6
+    w = workload(name)
+    nmo = w.C.shape[1]
+    sel = np.array([w.nocc + 3, 2, w.nocc + 3, w.nocc - 1, w.nocc, 0, nmo - 1, w.nocc + 1], dtype=np.int32)
+    log(f"transform {prec} {name} selection {sel.tolist()}")
+    Ld, M = _L_on_device(name, delta)
+    r = oracle_cd(name, delta)
+    refs, refv = mo.transform_blocks(r.L, w.C, w.nocc, sel)
+    abss, absv = mo.transform_blocks(np.abs(r.L), np.abs(w.C), w.nocc, sel)
+    B = cds.transform(Ld, M, _dev(w.C), w.nocc, sel, prec)
+    gs, gv = (x.cpu().numpy() for x in as_float64(B))
+    u = 1e-12 * max(np.abs(refs).max(), np.abs(refv).max()) if prec == "fp64" else None
+    if u is not None:
+        assert np.abs(gs - refs.transpose(1, 2, 0)).max() <= u
+        assert np.abs(gv - refv.transpose(1, 2, 0)).max() <= u
+    else:
+        b = _U[prec](w.nbf)
+        assert (np.abs(gs - refs.transpose(1, 2, 0)) <= b * abss.transpose(1, 2, 0) + 1e-300).all()
+        assert (np.abs(gv - refv.transpose(1, 2, 0)) <= b * absv.transpose(1, 2, 0) + 1e-300).all()
+    # the repeated target's two blocks are the same bits
+    bs = B.Bsel.reshape(*B.Bsel.shape[:-2], len(sel), nmo, B.ldk)
+    assert torch.equal(bs[..., 0, :, :M], bs[..., 2, :, :M])
+
+
 @pytest.mark.parametrize("name", ["plain", "c60"])
 def test_sigma2_fp64_trial_energies(cds, name):
     w = workload(name)
