@@ -313,6 +313,27 @@ int cds_sigma2(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nm
                double *h_dsigma);
 
 /*
+ * cds_sigma2 without any device allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, results and summation order as cds_sigma2 (bit for bit), but every device
+ * buffer it needs lives in one array of CDS_NOALLOC_SCRATCH_BYTES per GPU, reserved when the
+ * library is loaded and held until the process ends: no hipMalloc, no workspace growth, no
+ * statistics.  Limits: the blocks must suit the fused contraction (16-byte aligned, ldk >=
+ * nvec rounded up to 16 (FP64) or 32 (FP32, BF16X3), ldk times the element size a multiple of
+ * 16); the scratch holds the per-task partial sums of the targets of one launch (targets per
+ * launch x tasks per target x T x 16 bytes, tasks per target = nocc ceil(nvirt/128)
+ * (ceil(nvirt/128)+1)/2 + nvirt ceil(nocc/128)(ceil(nocc/128)+1)/2) plus 24 nsel T + 4 nsel
+ * bytes; a call that needs more returns CDS_EINVAL (fewer targets per launch with
+ * cds_set_target_chunk, or fewer trial energies, make it fit).  All calls on one GPU share
+ * the array: calls that overlap on one GPU (several contexts or threads) race.
+ */
+#define CDS_NOALLOC_SCRATCH_BYTES (32 << 20)
+int cds_sigma2_noalloc(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo, int32_t nocc,
+                       int32_t nsel, const int32_t *h_sel, const void *Bsel, const void *Bvo,
+                       const double *eps, int32_t T, const double *h_omega, double *h_sigma,
+                       double *h_dsigma);
+
+/*
  * Quasi-particle equation w = e_q + Sigma_qq(w), Eq. (qpapp), solved per
  * target by Newton-Raphson, Eq. (iter), with pole strength Eq. (ps):
  *   P_n = 1/(1 - Sigma'(w_n)),  w_{n+1} = w_n + (e_q + Sigma(w_n) - w_n) P_n,

@@ -76,7 +76,11 @@ struct cds_ctx {
     bool mail_off = false;           // 1: the word did not follow the state (state read after every batch)
     int cd_mailbox = 1;              // 0: the caller turned the word off
     uint64_t mail_base = 0;          // block count the last Cholesky call started from
+    void *scratch = nullptr;         // device address of the allocation-free path's array on this device
 };
+
+// device address of the allocation-free path's scratch array on the current device
+int cds_noalloc_scratch_address(void **out);
 
 // error helpers -------------------------------------------------------------
 int cds_fail(cds_ctx *ctx, int code, const char *fmt, ...);

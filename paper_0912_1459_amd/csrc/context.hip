@@ -126,6 +126,8 @@ int cds_create(int device, void *hip_stream, cds_ctx **out)
     if (!c) return CDS_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // the allocation-free path's array on this device (its name is no device address)
+    if (cds_noalloc_scratch_address(&c->scratch) != CDS_OK) c->scratch = nullptr;
     *out = c;
     return CDS_OK;
 }

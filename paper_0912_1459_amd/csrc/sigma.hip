@@ -458,6 +458,15 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
     if (threadIdx.x == 0) out[idx] = v;
 }
 
+// sig[s][t] and dsig[s][t] (the two components written apart); same order as above
+__global__ __launch_bounds__(256) void reduce_split_kernel(const double *__restrict__ part, int nsc, int nblk, int T,
+                                                           double *__restrict__ sig, double *__restrict__ dsig)
+{
+    const int idx = blockIdx.x, s = idx / (T * 2), tc = idx - s * T * 2;
+    const double v = reduce_blocks(part, s, tc, nblk, T);
+    if (threadIdx.x == 0) (tc & 1 ? dsig : sig)[s * T + (tc >> 1)] = v;
+}
+
 struct SigmaShape {
     int prec;
     int64_t nvec, ldk;
@@ -935,5 +944,70 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
     }
     CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_newton_ms));
     CDS_CALL(cds_timers_flush(ctx));
+    return CDS_OK;
+}
+
+// ---- allocation-free self-energy -----------------------------------------------------------
+// Device memory of cds_sigma2_noalloc: one array per GPU, held from the library's load until
+// the process ends.  Host code must not use the array's name as an address: its device address
+// comes from hipGetSymbolAddress (cds_noalloc_scratch_address, called by cds_create with the
+// context's device current) and is kept in the context.
+static __device__ __align__(256) unsigned char scratch[CDS_NOALLOC_SCRATCH_BYTES];
+
+int cds_noalloc_scratch_address(void **out)
+{
+    *out = nullptr;
+    return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)) == hipSuccess && *out ? CDS_OK : CDS_EDEVICE;
+}
+
+extern "C" int cds_sigma2_noalloc(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ldk, int32_t nmo,
+                                  int32_t nocc, int32_t nsel, const int32_t *h_sel, const void *Bsel,
+                                  const void *Bvo, const double *eps, int32_t T, const double *h_omega,
+                                  double *h_sigma, double *h_dsigma)
+{
+    CDS_CALL(cds_enter(ctx));
+    SigmaShape sh = {prec, nvec, ldk, nmo, nocc, nmo - nocc, nsel,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsel * nmo};
+    CDS_CALL(check_shape(ctx, sh, h_sel, Bsel, Bvo, eps));
+    CDS_REQUIRE(ctx, T >= 1 && T <= TMAX, "T must be in [1, %d]", TMAX);
+    CDS_REQUIRE(ctx, h_omega && h_sigma && h_dsigma, "NULL host pointer");
+    const void *Slo, *Vlo;
+    lo_planes(sh, Bsel, Bvo, &Slo, &Vlo);
+    CdsFusedPlan fp;
+    CDS_REQUIRE(ctx, cds_fused_plan(prec, nvec, ldk, nmo, nocc, Bsel, Bvo, Slo, Vlo, &fp),
+                "allocation-free path needs 16-byte aligned blocks with ldk >= nvec rounded up to the "
+                "K stage (16 FP64, 32 FP32 / BF16X3) and ldk * element size a multiple of 16");
+    if (!ctx->scratch) return cds_fail(ctx, CDS_ESTATE, "no device address for the scratch array");
+    // scratch layout: partials [csz][tpt][T][2], sigma [nsel][T], dsigma [nsel][T],
+    // trial energies [nsel][T], target slots [nsel]
+    const int csz = fused_chunk(ctx, sh);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_part = up((size_t)csz * fp.tpt * T * 2 * 8), b_nt = up((size_t)nsel * T * 8);
+    const size_t need = b_part + 3 * b_nt + up((size_t)nsel * 4);
+    CDS_REQUIRE(ctx, need <= (size_t)CDS_NOALLOC_SCRATCH_BYTES,
+                "allocation-free path: %zu bytes of scratch needed, %d available (fewer targets per "
+                "launch, see cds_set_target_chunk, or fewer trial energies)",
+                need, CDS_NOALLOC_SCRATCH_BYTES);
+    unsigned char *sp = (unsigned char *)ctx->scratch;
+    double *part = (double *)sp;
+    double *sig = (double *)(sp + b_part), *dsig = (double *)(sp + b_part + b_nt);
+    double *om = (double *)(sp + b_part + 2 * b_nt);
+    int *tsel = (int *)(sp + b_part + 3 * b_nt);
+    CDS_HIP(ctx, hipMemcpyAsync(om, h_omega, (size_t)nsel * T * 8, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)cds_ceil_div(nsel, 256)), dim3(256), 0, ctx->stream, tsel, nsel);
+    CDS_LAUNCHED(ctx);
+    for (int s0 = 0; s0 < nsel; s0 += csz) {
+        const int nsc = std::min(csz, nsel - s0);
+        CDS_CALL(cds_fused_sigma(ctx, prec, fp, ldk, nmo, nocc, nsc, tsel + s0, Bsel, Bvo, Slo, Vlo, eps,
+                                 om + (int64_t)s0 * T, T, part));
+        const int nout = nsc * T * 2;
+        hipLaunchKernelGGL(reduce_split_kernel, dim3((unsigned)nout), dim3(256), 0, ctx->stream,
+                           (const double *)part, nsc, (int)fp.tpt, T, sig + (int64_t)s0 * T,
+                           dsig + (int64_t)s0 * T);
+        CDS_LAUNCHED(ctx);
+    }
+    CDS_HIP(ctx, hipMemcpyAsync(h_sigma, sig, (size_t)nsel * T * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CDS_HIP(ctx, hipMemcpyAsync(h_dsigma, dsig, (size_t)nsel * T * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return CDS_OK;
 }
