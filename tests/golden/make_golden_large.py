@@ -15,7 +15,10 @@ cage, 16 s-Gaussians per centre, N = 960, 461,280 pairs, delta = 1e-4):
     column summed over the earlier vectors in reverse order, and the same transform associated
     the other way ((C^T L^K) C instead of C^T (L^K C)), move Sigma at the converged energy by
     dSigma, hence the energy by P dSigma to first order (Eq. (iter)), and the pole strength by
-    P^2 dSigma' (Eq. (ps)).  The MO coefficients of this workload
+    P^2 dSigma' (Eq. (ps));
+  * |Sigma''| at the converged energy (central difference of Sigma' with step 1e-7 Eh): the pole
+    strength returned is P_n at the last iterate w_n, which two evaluations reach only within the
+    Newton threshold of each other, so P can differ by P^2 |Sigma''| times that threshold.  The MO coefficients of this workload
     are ill-conditioned (C = S^-1/2 Q, smallest overlap eigenvalue ~2e-7), so two correct FP64
     evaluations of the path can differ by more than 1e-10 Eh; this is their measured spread.
 These are the expected values the GPU path is compared with at its full size.
@@ -52,11 +55,15 @@ def main():
     del r2
     t2 = time.time()
     print(f"transform in {t2 - t1:.1f} s", flush=True)
-    res, noise, pnoise = [], [], []
+    res, noise, pnoise, curv = [], [], [], []
     for s, q in enumerate(w.targets):
         x, y = SE.xy_from_B(Bsel[:, s, :], Bvo, w.nocc)
         res.append(SE.newton(x, y, w.eps, w.nocc, int(q), conv=CONV))
         s1, d1 = SE.sigma(x, y, w.eps, w.nocc, res[-1].omega)
+        h = 1e-7
+        d2p = (SE.sigma(x, y, w.eps, w.nocc, res[-1].omega + h)[1]
+               - SE.sigma(x, y, w.eps, w.nocc, res[-1].omega - h)[1]) / (2 * h)
+        curv.append(abs(d2p))
         del x, y
         x, y = SE.xy_from_B(Bsel2[:, s, :], Bvo2, w.nocc)
         s2, d2 = SE.sigma(x, y, w.eps, w.nocc, res[-1].omega)
@@ -75,6 +82,7 @@ def main():
            "iters": [int(x.iters) for x in res], "status": [int(x.status) for x in res],
            "omega_rounding_spread": [float(x) for x in noise],
            "pole_rounding_spread": [float(x) for x in pnoise],
+           "sigma_second_derivative": [float(x) for x in curv],
            "seconds": {"cd": round(t1 - t0, 1), "transform": round(t2 - t1, 1),
                        "newton": round(t3 - t2, 1)}}
     with open(os.path.join(HERE, "large_oracle.json"), "w") as f:

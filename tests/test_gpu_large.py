@@ -8,7 +8,11 @@ tests/golden/make_golden_large.py from oracle/ alone (Sec. II.A; Eqs. (transform
 (iter)).  The device path runs exactly as the benchmark times it: the decomposition with the
 transform beside it, the transform in FP64 working precision (the synthetic MO coefficients
 are ill-conditioned), the self-energy contraction over several target chunks.
-Bars: pivots bit-exact; FP32 and split-bf16 energies within 1 meV of the FP64 oracle; FP64
+Bars: pivots bit-exact; FP32 and split-bf16 energies within 1 meV of the FP64 oracle for the
+quasi-particle targets (oracle pole strength >= 0.1), and for the others (satellite solutions
+with pole strength 1e-4 ... 2e-3 among this workload's densely spaced 2h1p poles, where a
+perturbation may select a neighbouring root) within 1 meV of a root of the FP64 equation: one
+FP64 Newton step of Eq. (iter) from the reduced-precision solution moves it by at most 1 meV; FP64
 energies within 1e-10 Eh plus eight times the oracle's own rounding spread for that target.
 The spread is measured by the oracle itself: the same decomposition with every residual column
 summed in reverse order and the transform associated the other way moves the energy by
@@ -17,7 +21,10 @@ ill-conditioned (C = S^-1/2 Q with smallest overlap eigenvalue ~2e-7), which amp
 rounding of any FP64 evaluation by about 1/lambda_min.  The spread is one sample of how far
 re-associating the sums moves a result; the device path groups its sums differently in more
 places (the blocked look-ahead decomposition, the MFMA transform and contraction), so the bar is
-eight such samples.  Pole strengths likewise with P^2 dSigma'.
+eight such samples.  Pole strengths likewise with P^2 dSigma', plus P^2 |Sigma''| times the Newton
+threshold: the returned P_n belongs to the last iterate w_n, which the two paths reach only
+within that threshold of each other (near the dense poles of this workload's occupied targets
+Sigma' varies fast with w).
 """
 import json
 import os
@@ -46,21 +53,31 @@ def run():
     ctx = C.Context(0)
     ctx.set_transform_fp64(True)
     out = {}
+    eps = _dev(w.eps)
+    B64 = None
     for prec in ("fp64", "fp32", "bf16x3"):
         log(f"large workload: decomposition + transform ({prec})")
         cd, B = C.cholesky_transform(w.delta, centres=_dev(w.centres), alpha=_dev(w.alpha), C=_dev(w.C),
                                      nocc=w.nocc, sel=w.targets, prec=prec, max_vec=1024, ctx=ctx)
         log(f"large workload: Newton ({prec})")
-        qp = C.qp_solve(B, _dev(w.eps), conv=1e-12, max_iter=g["max_iter"], mode="residues", ctx=ctx)
-        out[prec] = (cd.nvec, cd.piv[: cd.nvec].cpu().numpy(), cd.dmax, cd.status, qp)
-        del cd, B
+        qp = C.qp_solve(B, eps, conv=1e-12, max_iter=g["max_iter"], mode="residues", ctx=ctx)
+        step = None
+        if prec == "fp64":
+            B64 = B
+        else:
+            # one FP64 Newton step of Eq. (iter) from the reduced-precision solution
+            s64, ds64 = C.sigma2(B64, eps, qp.omega[:, None], ctx=ctx)
+            step = (w.eps[w.targets] + s64[:, 0] - qp.omega) / (1.0 - ds64[:, 0])
+            del B
+        out[prec] = (cd.nvec, cd.piv[: cd.nvec].cpu().numpy(), cd.dmax, cd.status, qp, step)
+        del cd
         torch.cuda.empty_cache()
     return g, out
 
 
 def test_large_decomposition_matches_oracle(run):
     g, out = run
-    for prec, (nvec, piv, dmax, status, _) in out.items():
+    for prec, (nvec, piv, dmax, status, _, _) in out.items():
         assert nvec == g["nvec"], prec
         assert np.array_equal(piv, np.asarray(g["pivots"])), prec
         assert status == g["cd_status"]
@@ -72,7 +89,9 @@ def test_large_fp64_quasiparticles_match_oracle(run):
     qp = out["fp64"][4]
     err = np.abs(qp.omega - np.asarray(g["omega"]))
     tol = 1e-10 + 8.0 * np.asarray(g["omega_rounding_spread"])
-    ptol = 1e-10 + 8.0 * np.asarray(g["pole_rounding_spread"])
+    P = np.asarray(g["pole"])
+    ptol = (1e-10 + 8.0 * np.asarray(g["pole_rounding_spread"])
+            + P ** 2 * np.asarray(g["sigma_second_derivative"]) * g["conv"])
     perr = np.abs(qp.pole - np.asarray(g["pole"]))
     log(f"  FP64 max |dw| = {err.max():.2e} Eh; |dw| / bound max {np.max(err / tol):.2f}; "
         f"|dP| / bound max {np.max(perr / ptol):.2f}")
@@ -84,8 +103,12 @@ def test_large_fp64_quasiparticles_match_oracle(run):
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_large_reduced_precision_within_one_mev(run, prec):
     g, out = run
-    qp = out[prec][4]
+    qp, step = out[prec][4], out[prec][5]
     err = np.abs(qp.omega - np.asarray(g["omega"]))
-    log(f"  {prec} max |dw| = {err.max() * EV * 1e3:.4f} meV")
+    qpole = np.asarray(g["pole"]) >= 0.1
+    log(f"  {prec} quasi-particle targets: max |dw| = {err[qpole].max() * EV * 1e3:.4f} meV; satellites: "
+        f"max |dw| = {err[~qpole].max() * EV * 1e3:.4f} meV, max FP64 Newton step "
+        f"{np.abs(step[~qpole]).max() * EV * 1e3:.2e} meV")
     assert np.all(qp.status == 0)
-    assert err.max() <= MEV
+    assert err[qpole].max() <= MEV
+    assert np.abs(step).max() <= MEV
