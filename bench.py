@@ -92,10 +92,10 @@ def committed_traffic(workload: str) -> dict:
         if rec.get("workload_key") != workload:
             continue
         shas = rec.get("source_sha256", {})
-        if not shas or any(src_sha(s) != h for s, h in shas.items()):
-            continue
         for k, v in rec.get("kernels", {}).items():
-            out[k] = v["hbm_bytes_per_launch"]
+            s = v.get("source")
+            if s in shas and src_sha(s) == shas[s]:      # the kernel's source is unchanged since
+                out[k] = v["hbm_bytes_per_launch"]
     return out
 
 
