@@ -25,6 +25,8 @@ int cds_contract_internal(cds_ctx *ctx, int prec, int64_t nvec, int64_t ldk, int
 int cds_grad_epilogue_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int nsc, const void *G,
                                const double *eps, const double *d_omega, const double *d_gscale,
                                void *W, double *epsA, double *epsB);
+int cds_sigma_from_g_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int nsc, const void *G,
+                              const double *eps, const double *d_omega, double *d_out);
 
 namespace {
 
@@ -170,12 +172,8 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
     const int nvirt = nmo - nocc;
     const int64_t nvo = (int64_t)nvirt * nocc, nselr = (int64_t)nsel * nmo;
 
-    // pole strengths at the converged energies
-    std::vector<double> out((size_t)nsel * 2);
-    CDS_CALL(cds_sigma_eval_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, eps, h_omega, 1,
-                                     out.data()));
-    std::vector<double> hscale(nsel);
-    for (int s = 0; s < nsel; ++s) hscale[s] = h_omega_bar[s] / (1.0 - out[2 * s + 1]);
+    // the pole strengths at the converged energies come from each chunk's integrals (below)
+    std::vector<double> out((size_t)nsel * 2), hscale(nsel);
 
     // working copies: float operands for BF16X3 (planes -> float)
     const int gprec = prec == CDS_PREC_FP64 ? CDS_PREC_FP64 : CDS_PREC_FP32;
@@ -183,7 +181,7 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
     const void *Bs = Bsel, *Bv = Bvo;
     void *tmp;
     size_t nB = (size_t)(nselr + nvo) * ldk;
-    size_t small = (size_t)nsel * 8 * 3 + (size_t)nsel * 4 + 256;
+    size_t small = (size_t)nsel * 8 * 5 + (size_t)nsel * 4 + 256;
     size_t epsbytes = (size_t)2 * nsel * nvirt * (nocc + 1) * 8;
     CDS_CALL(cds_ws(ctx, WS_AD_TMP, (prec == CDS_PREC_BF16X3 ? nB * 4 : 0) + small + epsbytes, &tmp));
     unsigned char *tp = (unsigned char *)tmp;
@@ -200,16 +198,17 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
     }
     double *d_omega = (double *)tp;
     double *d_scale = d_omega + nsel;
-    int32_t *d_sel = (int32_t *)(d_scale + nsel);
+    double *d_sig = d_scale + nsel;                    // [nsel][2]: Sigma, Sigma'
+    int32_t *d_sel = (int32_t *)(d_sig + 2 * nsel);
     double *epsA = (double *)(tp + small);
     double *epsB = epsA + (size_t)nsel * nvirt * (nocc + 1);
     CDS_HIP(ctx, hipMemcpyAsync(d_omega, h_omega, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
-    CDS_HIP(ctx, hipMemcpyAsync(d_scale, hscale.data(), (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
     CDS_HIP(ctx, hipMemcpyAsync(d_sel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
 
-    // chunks of targets: G and W each nsc * nmo * nvo
+    // chunks of targets: G, W and W^T each nsc * nmo * nvo, at most 12 GiB each (few, large
+    // chunks: the product over nvo below has only nsc * nmo / 128 tile rows)
     size_t per = (size_t)nmo * nvo * es;
-    int csz = (int)std::max<size_t>(1, ((size_t)2 << 30) / std::max<size_t>(per, 1));
+    int csz = (int)std::max<size_t>(1, ((size_t)12 << 30) / std::max<size_t>(per, 1));
     if (ctx->target_chunk > 0) csz = std::min(csz, ctx->target_chunk);
     csz = std::min(csz, (int)nsel);
     void *G, *W;
@@ -226,6 +225,14 @@ extern "C" int cds_qp_adjoint(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t 
     for (int s0 = 0; s0 < nsel; s0 += csz) {
         const int nsc = std::min(csz, nsel - s0);
         CDS_CALL(cds_contract_internal(ctx, prec, nvec, ldk, nmo, nocc, nsel, Bsel, Bvo, s0, nsc, G));
+        // P_s = 1 / (1 - Sigma'(w*_s)) from the same integrals, then the weights' scale
+        CDS_CALL(cds_sigma_from_g_internal(ctx, prec, nmo, nocc, nsc, G, eps, d_omega + s0, d_sig + 2 * s0));
+        CDS_HIP(ctx, hipMemcpyAsync(out.data() + 2 * s0, d_sig + 2 * s0, (size_t)nsc * 2 * 8, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int s = s0; s < s0 + nsc; ++s) hscale[s] = h_omega_bar[s] / (1.0 - out[2 * s + 1]);
+        CDS_HIP(ctx, hipMemcpyAsync(d_scale + s0, hscale.data() + s0, (size_t)nsc * 8, hipMemcpyHostToDevice,
+                                    ctx->stream));
         CDS_CALL(cds_grad_epilogue_internal(ctx, prec, nmo, nocc, nsc, G, eps, d_omega + s0, d_scale + s0, W,
                                             epsA + (size_t)s0 * nvirt * (nocc + 1),
                                             epsB + (size_t)s0 * nvirt * (nocc + 1)));

@@ -710,6 +710,36 @@ int cds_contract_internal(cds_ctx *ctx, int prec, int64_t nvec, int64_t ldk, int
     return contract_chunk(ctx, sh, Bsel, Bvo, s0, nsc, G);
 }
 
+// Sigma and Sigma' of a chunk's targets at one energy each (device d_omega[nsc]) from its formed
+// integrals G -> device d_out[nsc][2] (adjoint: the pole strengths at the converged energies)
+int cds_sigma_from_g_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int nsc, const void *G,
+                              const double *eps, const double *d_omega, double *d_out)
+{
+    SigmaShape sh = {prec, 0, 0, nmo, nocc, nmo - nocc, nsc,
+                     (int64_t)(nmo - nocc) * nocc, (int64_t)nsc * nmo};
+    const int nblk = sh.nvirt + (sh.nvirt + 1) / 2;
+    void *part;
+    CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsc * nblk * 2 * 8, &part));
+    EpArgs e = {};
+    e.G = G;
+    e.nmo = nmo;
+    e.nocc = nocc;
+    e.nvirt = sh.nvirt;
+    e.nsc = nsc;
+    e.nvo = sh.nvo;
+    e.eps = eps;
+    e.omega = d_omega;
+    e.T = 1;
+    e.part = (double *)part;
+    e.nblkA = sh.nvirt;
+    e.nblkB = (sh.nvirt + 1) / 2;
+    CDS_CALL(launch_epilogue<EP_SIGMA>(ctx, sh, e, prec == CDS_PREC_FP64));
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(nsc * 2)), dim3(256), 0, ctx->stream,
+                       (const double *)part, nsc, nblk, 1, d_out);
+    CDS_LAUNCHED(ctx);
+    return CDS_OK;
+}
+
 // gradient-weight epilogue for a chunk (adjoint)
 int cds_grad_epilogue_internal(cds_ctx *ctx, int prec, int nmo, int nocc, int nsc, const void *G,
                                const double *eps, const double *d_omega, const double *d_gscale,
