@@ -418,6 +418,116 @@ bool fast_ok(const void *p, int64_t srow, int64_t sk, int64_t K, int kb, size_t 
     return sk == 1 && K % kb == 0 && cds_aligned(p, 16) && (srow * (int64_t)esz) % 16 == 0;
 }
 
+// ---- FP64 GEMM with direct-to-LDS operand stages -------------------------------------------
+// For K-contiguous FP64 operands (rows 16-byte aligned, K % 16 == 0): 128 x 128 tile per
+// 512-thread workgroup, 8 waves in 2 x 4 with 64 x 32 each (v_mfma_f64_16x16x4f64, 8 blocks),
+// 16-k stages of both operands (128 rows x 128 bytes each) loaded straight from global memory
+// into LDS with global_load_lds_dwordx4, G64_NB stages in the ring (G64_NB - 1 in flight), the
+// 16-byte chunks of a row XOR-swizzled by row & 7 so the fragment reads of 8 consecutive rows hit
+// distinct banks.  Two stages of 32 KB and two workgroups per CU (measured on the large workload:
+// adjoint of the solve 154 ms against 169 / 164 ms for one workgroup with three / four stages;
+// the 128 x 128 register-staged kernel took 222 ms).  Each output takes its K terms in the same
+// order as in gemm_kernel's FP64
+// path (stages of 16 in order, within a stage k pairs (2c, 2c+1) for chunk c in the order
+// c = g, g + 4 of the lane groups), so the two kernels agree bit for bit.
+constexpr int G64_NT = 512, G64_KS = 16, G64_SLICE = 16384, G64_STAGE = 2 * G64_SLICE, G64_NB = 2;
+
+static_assert(G64_NB >= 2 && G64_NB <= 4, "the stage waits cover rings of 2 to 4 stages");
+
+template <int N>
+__device__ __forceinline__ void g64_wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+__global__ __launch_bounds__(G64_NT, 2) void gemm64_dma_kernel(Args a)
+{
+    __shared__ __align__(16) unsigned char lds[G64_NB * G64_STAGE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, r16 = lane & 15;
+    const int wr = wave >> 2, wc = wave & 3;
+    const int64_t n0 = (int64_t)blockIdx.x * BN, m0 = (int64_t)blockIdx.y * BM, batch = blockIdx.z;
+    const int64_t ns = a.K / G64_KS;
+    // this wave's four loads per stage: slice sl (0 A, 1 B), rows 8 q + lane / 8 for q in
+    // [4 (wave & 3), 4 (wave & 3) + 4), position lane % 8 holding the swizzled logical chunk
+    const int sl = wave >> 2;
+    const int lrow = lane >> 3, pc = lane & 7;
+    const unsigned char *mat = sl ? a.B : a.A;
+    const int64_t srow = sl ? a.sBn : a.sAm, sb = sl ? a.sBb : a.sAb;
+    const int64_t nrows = sl ? a.N : a.M, r0g = sl ? n0 : m0;
+    const unsigned char *src[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rr = 8 * (4 * (wave & 3) + q) + lrow;
+        const int64_t row = min(r0g + rr, nrows - 1);
+        src[q] = mat + ((batch * sb + row * srow) * 8) + ((pc ^ (rr & 7)) * 16);
+    }
+    auto stage_load = [&](int buf, int64_t st) __attribute__((always_inline)) {
+        unsigned char *dst = lds + buf * G64_STAGE + sl * G64_SLICE + (4 * (wave & 3)) * 1024;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cds_lds_dma16(src[q] + st * G64_KS * 8, dst + q * 1024);
+    };
+    doublex4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    auto frag = [&](const unsigned char *buf, int slc, int rr, int lc) __attribute__((always_inline)) {
+        return *reinterpret_cast<const double2 *>(buf + slc * G64_SLICE + rr * 128 + ((lc ^ (rr & 7)) * 16));
+    };
+    // prologue: stages 0 .. NB - 2 in flight
+#pragma unroll
+    for (int i = 0; i < G64_NB - 1; ++i)
+        if (i < ns) stage_load(i, i);
+    for (int64_t st = 0; st < ns; ++st) {
+        const int buf = (int)(st % G64_NB);
+        // this wave's loads of stage st have landed (4 loads per later stage may still be in flight)
+        const int64_t later = min((int64_t)(G64_NB - 2), ns - 1 - st);
+        if (later >= 2) g64_wait_vm<8>();
+        else if (later == 1) g64_wait_vm<4>();
+        else g64_wait_vm<0>();
+        __builtin_amdgcn_s_barrier();                      // every wave's; and stage st - 1 is read
+        if (st + G64_NB - 1 < ns) stage_load((int)((st + G64_NB - 1) % G64_NB), st + G64_NB - 1);
+        const unsigned char *cur = lds + buf * G64_STAGE;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int lc = g + 4 * h;
+            double2 fa[4], fb[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = frag(cur, 0, wr * 64 + 16 * i + r16, lc);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) fb[j] = frag(cur, 1, wc * 32 + 16 * j + r16, lc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].x, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j], 0, 0, 0);
+                }
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);                // lgkmcnt(0): this wave's reads are done
+    }
+    double *C = reinterpret_cast<double *>(a.C) + batch * a.sCb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t n = n0 + wc * 32 + 16 * j + r16;
+            if (n >= a.N) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t m = m0 + wr * 64 + 16 * i + g + 4 * e;
+                if (m >= a.M) continue;
+                double *dst = C + m * a.sCm + n * a.sCn;
+                double v = a.alpha * acc[i][j][e];
+                if (a.beta != 0.0) v += a.beta * (*dst);
+                *dst = v;
+            }
+        }
+}
+
 template <int PREC>
 int launch(cds_ctx *ctx, Args &a)
 {
@@ -444,6 +554,13 @@ int launch(cds_ctx *ctx, Args &a)
             CDS_LAUNCHED(ctx);
             return CDS_OK;
         }
+    }
+    if (PREC == CDS_PREC_FP64 && a.fastA && a.fastB && a.K % G64_KS == 0 && cds_aligned(a.A, 16) &&
+        cds_aligned(a.B, 16) && (a.sAb * 8) % 16 == 0 && (a.sBb * 8) % 16 == 0) {
+        hipLaunchKernelGGL(gemm64_dma_kernel, dim3((unsigned)gx, (unsigned)gy, (unsigned)a.batch), dim3(G64_NT), 0,
+                           ctx->stream, a);
+        CDS_LAUNCHED(ctx);
+        return CDS_OK;
     }
     size_t lds = (size_t)2 * Tr<PREC>::PLANES * BM * PITCH;
     hipLaunchKernelGGL(gemm_kernel<PREC>, dim3((unsigned)gx, (unsigned)gy, (unsigned)a.batch), dim3(NT),
