@@ -57,6 +57,8 @@ constexpr int CD_PCHUNK = 1024;         // pivot-row entries staged in LDS per c
 constexpr int CD_AUX_NT = 1024;         // threads of the one-block kernels
 constexpr int CD_NSUP = 64;             // super-tiles of the hierarchical pivot search
 constexpr int CD_NCAND = 64;            // candidate residual columns per look-ahead block
+constexpr int CD_CG = 8;                 // candidate columns per thread in the column kernels
+constexpr int CD_NCG = CD_NCAND / CD_CG; // column groups (rows of the column grid)
 constexpr int CD_PASS_D = 2;            // k-steps (4 vectors each) in flight per wave in the pass
 constexpr int CD_PASS_ZROWS = 8;        // zero rows of P after row k0
 constexpr int CD_TPT = 4;               // tile records per thread in the flat pivot search
@@ -1480,23 +1482,27 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     }
 }
 
-// Base of the candidate residual columns: R[c][I] = V[I][cand_c] for candidate c, rows I of
-// x-block bx; the pass then subtracts the projection on the earlier vectors.
+// Base of the candidate residual columns: R[c][I] = V[I][cand_c] for the candidates c of group
+// grp (CD_CG columns), rows I of x-block bx; the pass then subtracts the projection on the
+// earlier vectors.  Each thread loads its pair's data once and evaluates its row of the group's
+// columns (the pair table is read once per group, not once per column).
 template <bool DENSE>
 __device__ __forceinline__ void candcol_body(const PairTable &pt, const double *__restrict__ V, int64_t ldv,
-                                             int64_t npairs, const int64_t *__restrict__ cand, int c, int64_t bx,
-                                             double *__restrict__ R, int64_t ldr)
+                                             int64_t npairs, const int64_t *__restrict__ cand, int nc, int grp,
+                                             int64_t bx, double *__restrict__ R, int64_t ldr)
 {
     const int64_t I = bx * blockDim.x + threadIdx.x;
     if (I >= npairs) return;
-    const int64_t q = cand[c];
-    double v;
+    const int c0 = grp * CD_CG, c1 = min(nc, c0 + CD_CG);
     if constexpr (DENSE) {
-        v = V[q * ldv + I];
+        for (int c = c0; c < c1; ++c) R[(int64_t)c * ldr + I] = V[cand[c] * ldv + I];
     } else {
-        v = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[q], pt.Px[q], pt.Py[q], pt.Pz[q], pt.K[q]);
+        const double p = pt.p[I], Px = pt.Px[I], Py = pt.Py[I], Pz = pt.Pz[I], K = pt.K[I];
+        for (int c = c0; c < c1; ++c) {
+            const int64_t q = cand[c];
+            R[(int64_t)c * ldr + I] = eri_pp(p, Px, Py, Pz, K, pt.p[q], pt.Px[q], pt.Py[q], pt.Pz[q], pt.K[q]);
+        }
     }
-    R[(int64_t)c * ldr + I] = v;
 }
 
 // P[j][c] = L[j][cand_c], j < k0, c < nc (stride over the entries from block b of nb);
@@ -1518,9 +1524,9 @@ __global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, in
                                   const CdState *__restrict__ st, const int64_t *__restrict__ cand,
                                   double *__restrict__ R, int64_t ldr)
 {
-    const int c = blockIdx.y;
-    if (spec_idle(st) || c >= st->ncand) return;
-    candcol_body<DENSE>(pt, V, ldv, npairs, cand, c, blockIdx.x, R, ldr);
+    const int grp = blockIdx.y, nc = st->ncand;
+    if (spec_idle(st) || grp * CD_CG >= nc) return;
+    candcol_body<DENSE>(pt, V, ldv, npairs, cand, nc, grp, blockIdx.x, R, ldr);
 }
 
 // the gather alone; k0 < 0: the start of the current speculative block
@@ -1532,8 +1538,8 @@ __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int6
 }
 
 // one launch for both, at the start of the current speculative block (they need only the
-// candidate list): block rows y < CD_NCAND evaluate candidate y's column, the rows after them
-// gather (enough of them that each thread gathers at most one entry: a strided loop waits on
+// candidate list): block rows y < CD_NCG evaluate the columns of candidate group y, the rows after
+// them gather (enough of them that each thread gathers at most one entry: a strided loop waits on
 // each of its loads)
 template <bool DENSE>
 __global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict__ V, int64_t ldv, int64_t npairs,
@@ -1543,14 +1549,14 @@ __global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict_
 {
     if (spec_idle(st)) return;
     const int nc = st->ncand;
-    if ((int)blockIdx.y >= CD_NCAND) {          // gather: rows CD_NCAND.. of the grid, one entry per thread
-        const int64_t gb = (int64_t)(blockIdx.y - CD_NCAND) * gridDim.x + blockIdx.x;
-        const int64_t nb = (int64_t)(gridDim.y - CD_NCAND) * gridDim.x;
+    if ((int)blockIdx.y >= CD_NCG) {            // gather: rows CD_NCG.. of the grid, one entry per thread
+        const int64_t gb = (int64_t)(blockIdx.y - CD_NCG) * gridDim.x + blockIdx.x;
+        const int64_t nb = (int64_t)(gridDim.y - CD_NCG) * gridDim.x;
         if (nc > 0) gather_body(L, ldl, st->k, nc, cand, P, gb, nb);
         return;
     }
-    if ((int)blockIdx.y >= nc) return;
-    candcol_body<DENSE>(pt, V, ldv, npairs, cand, blockIdx.y, blockIdx.x, R, ldr);
+    if ((int)blockIdx.y * CD_CG >= nc) return;
+    candcol_body<DENSE>(pt, V, ldv, npairs, cand, nc, blockIdx.y, blockIdx.x, R, ldr);
 }
 
 // R[c][I] -= sum_{j<k0} L[j][I] P[j][c] for all candidates (R holds V[I][cand_c]), one
@@ -1937,7 +1943,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         CDS_LAUNCHED(ctx);
         const int64_t cgx = cds_ceil_div(npairs, 256);
         const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
-        const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCAND + gy));
+        const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCG + gy));
         if (dense)
             hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
                                npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
@@ -2069,7 +2075,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                        (const int64_t *)cand, Pc);
                     CDS_LAUNCHED(ctx);
                 }
-                const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCAND);
+                const dim3 cgrid((unsigned)cds_ceil_div(npairs, 256), CD_NCG);
                 if (dense)
                     hipLaunchKernelGGL(cd_candcol_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv, npairs,
                                        (const CdState *)st, (const int64_t *)cand, Rc, ldr);
