@@ -17,8 +17,8 @@
 // partner through an LDS transpose.  Operand slices (128 rows x 128 bytes per stage) go straight
 // from global memory into two LDS stages (global_load_lds_dwordx4), the 16-byte chunks of a row
 // XOR-swizzled so the fragment reads of consecutive rows hit distinct banks; 16 x 16 MFMA blocks
-// entirely past the matrix edge are skipped.  Tasks are ordered so that those sharing an
-// operand row set run at the same time (spread over all XCDs).
+// entirely past the matrix edge are skipped.  Tasks are ordered so that those sharing their P
+// operand slices run at the same time on one XCD.
 //
 // SIGMA mode: each workgroup sums R / d and -R / d^2 over its elements at T trial energies in
 // FP64 (fixed order) and writes one partial per trial energy; a second kernel adds the partials
@@ -106,30 +106,27 @@ __device__ __forceinline__ void pair_tiles(int p, int n, int &TR, int &TC)
     TC = r + p;
 }
 
-// launch order: part B tasks by (i, target, pair), then part A tasks by (a, target, pair), so
-// tasks that read the same Bvo rows run together and every target's Bsel rows stay in the
-// last-level cache
+// launch order: part B tasks by (target, pair, i), then part A tasks by (target, pair, a): runs of
+// tasks that share the P operand slices (rows of Bsel for one target) and differ only in the Q rows
 __device__ __forceinline__ Task task_of_launch(const FArgs &a, int64_t t)
 {
     Task k;
     const int64_t nB = (int64_t)a.nocc * a.nsc * a.nPB;
     if (t < nB) {
-        const int64_t per = (int64_t)a.nsc * a.nPB;
         k.fam = 1;
-        k.idx = (int)(t / per);
-        const int64_t rem = t - (int64_t)k.idx * per;
+        k.idx = (int)(t % a.nocc);
+        const int64_t rem = t / a.nocc;
+        k.pair = (int)(rem % a.nPB);
         k.sl = (int)(rem / a.nPB);
-        k.pair = (int)(rem - (int64_t)k.sl * a.nPB);
         pair_tiles(k.pair, a.nTB, k.TR, k.TC);
         k.tin = (int64_t)k.idx * a.nPB + k.pair;
     } else {
         t -= nB;
-        const int64_t per = (int64_t)a.nsc * a.nPA;
         k.fam = 0;
-        k.idx = (int)(t / per);
-        const int64_t rem = t - (int64_t)k.idx * per;
+        k.idx = (int)(t % a.nvirt);
+        const int64_t rem = t / a.nvirt;
+        k.pair = (int)(rem % a.nPA);
         k.sl = (int)(rem / a.nPA);
-        k.pair = (int)(rem - (int64_t)k.sl * a.nPA);
         pair_tiles(k.pair, a.nTA, k.TR, k.TC);
         k.tin = (int64_t)a.nocc * a.nPB + (int64_t)k.idx * a.nPA + k.pair;
     }
@@ -216,10 +213,18 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, r16 = lane & 15;
     const int wr = wave >> 2, wc = wave & 3;
-    // consecutive tasks go to consecutive workgroups (dealt to the 8 XCDs in turn): a task
-    // group sharing one Bvo row set is spread over all XCDs (measured faster than giving each
-    // XCD a contiguous task range: 62.6 against 65.6 ms for the FP64 large-workload call)
-    const Task k = task_of_launch(a, blockIdx.x);
+    // workgroups are dealt to the 8 XCDs in turn; each group of 256 consecutive workgroups takes
+    // 256 consecutive tasks, 32 per XCD, so the 32 tasks one XCD runs at a time read the same P
+    // slices (one target, one tile pair) from its L2 and differ only in their Q rows.  Large
+    // workload, FP64 residues: 57.0 ms in the order (index, target, pair) dealt round robin, 53.9
+    // ms in the order (target, pair, index) dealt round robin, 53.3 ms with 32 per XCD (64 per
+    // XCD: 53.3 ms; order (target, index, pair): 54.7 ms; one contiguous range per XCD: 59.8 ms)
+    int64_t tid = blockIdx.x;
+    {
+        const int64_t full = ((int64_t)gridDim.x / 256) * 256;
+        if (tid < full) tid = (tid / 256) * 256 + (tid % 8) * 32 + (tid / 8) % 32;
+    }
+    const Task k = task_of_launch(a, tid);
     const bool diag = k.TR == k.TC;
     const int n = k.fam ? a.nvirt : a.nocc;
     const int s = a.tsel[k.sl];
