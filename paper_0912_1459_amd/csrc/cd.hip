@@ -1024,7 +1024,9 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
 }
 
 // every row of the workgroup: the speculated vectors L[k0+j] (same operations as
-// spec_body), the residual after each (Dbuf[j][I] = D after vector j) and the step checks
+// spec_body), the residual at the end of each chunk of CD_SPEC_CHUNK steps (Dbuf[j][I] = D after
+// vector j, for j = CD_SPEC_CHUNK - 1, 2 CD_SPEC_CHUNK - 1, ...; the commit replays the steps
+// after the last such checkpoint from L) and the step checks
 __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, const double *__restrict__ R,
                                           int64_t ldr, double *__restrict__ L, int64_t ldl,
                                           double *__restrict__ Dbuf, SpecOut *so, const SpecOut &ss)
@@ -1071,7 +1073,7 @@ __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, c
                 d = fma(-lj, lj, d);
             }
             L[(k0 + j) * ldl + I] = lj;
-            Dbuf[(int64_t)j * cp.npairs + I] = d;
+            if (u == CD_SPEC_CHUNK - 1) Dbuf[(int64_t)j * cp.npairs + I] = d;
             if (m != 1) {
                 // a pivot row (also the one made now) takes no further values; lpiv[j][j'] =
                 // L_j[p_j'], 0 for j' >= ns
@@ -1152,7 +1154,7 @@ struct RowWave {
         lr[j] = lj;
         if (ok) {
             L[(k0 + j) * ldl + I] = lj;
-            Dbuf[(int64_t)j * cp.npairs + I] = d;
+            if (j % CD_SPEC_CHUNK == CD_SPEC_CHUNK - 1) Dbuf[(int64_t)j * cp.npairs + I] = d;
         }
     }
 };
@@ -1249,6 +1251,7 @@ __global__ void reset_super_kernel(CdBufs b, CdParams cp, const CdState *st, con
 // commit the first nc speculated steps: residuals, pivot marks and tile records into the
 // buffers of parity w (the step k0 + nc reads them), pivots and the state
 __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, const double *__restrict__ Dbuf,
+                                                        const double *__restrict__ L, int64_t ldl,
                                                         const SpecOut *so, CdState *st, int64_t *__restrict__ piv,
                                                         uint64_t *mail)
 {
@@ -1268,14 +1271,33 @@ __global__ __launch_bounds__(256) void cd_commit_kernel(CdBufs b, CdParams cp, c
     const int r = (int)(s & 1), w = (int)((s + nc) & 1), sw = (int)((s + nc) % 3);
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool ok = I < cp.npairs;
+    // D after the kept steps: the rows kernel's last checkpoint before step nc (or D at the block
+    // start), then the steps after it replayed from L with the rows kernel's own operations
+    const int jc = (nc / CD_SPEC_CHUNK) * CD_SPEC_CHUNK;     // steps covered by the checkpoint
     unsigned char m = ok ? b.mask[r][I] : 1;
-    double d = ok ? Dbuf[(int64_t)(nc - 1) * cp.npairs + I] : 0.0;
+    double d = 0.0, lv[CD_SPEC_CHUNK];
+    if (ok) {
+        d = jc > 0 ? Dbuf[(int64_t)(jc - 1) * cp.npairs + I] : b.D[r][I];
+#pragma unroll
+        for (int u = 0; u < CD_SPEC_CHUNK; ++u) lv[u] = jc + u < nc ? L[(k0 + jc + u) * ldl + I] : 0.0;
+    }
     // the block's pivots, loaded once (a loop of loads would wait on each)
     if ((int)threadIdx.x < CD_SPEC_MAX) sp[threadIdx.x] = (int)threadIdx.x < nc ? so->p[threadIdx.x] : -1;
     __syncthreads();
     if (ok) {
-        for (int j = 0; j < nc; ++j)
+        for (int j = 0; j < jc; ++j)
             if (I == sp[j]) m = 1;
+#pragma unroll
+        for (int u = 0; u < CD_SPEC_CHUNK; ++u) {
+            const int j = jc + u;
+            if (j >= nc || m == 1) continue;
+            if (I == sp[j]) {
+                d = 0.0;
+                m = 1;
+            } else {
+                d = fma(-lv[u], lv[u], d);
+            }
+        }
         b.D[w][I] = d;
         b.mask[w][I] = m;
     }
@@ -1989,7 +2011,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             CDS_LAUNCHED(ctx);
         }
         hipLaunchKernelGGL(cd_commit_kernel, dim3((unsigned)cds_ceil_div(npairs, 256)), dim3(256), 0,
-                           ctx->stream, bf, cp, (const double *)Dbuf, (const SpecOut *)so, st, piv,
+                           ctx->stream, bf, cp, (const double *)Dbuf, (const double *)L, ldl, (const SpecOut *)so,
+                           st, piv,
                            mb && !ctx->mail_off ? ctx->mail_dev : nullptr);
         CDS_LAUNCHED(ctx);
         if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
