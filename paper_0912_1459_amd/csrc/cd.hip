@@ -1598,12 +1598,16 @@ __global__ void cd_candcol_gather_kernel(PairTable pt, const double *__restrict_
 // candidates of P at once (16 bytes), half the load instructions of one row each; the MFMA
 // row (column) r16 of block 2u + h is then tile row (candidate) 32u + 2 r16 + h.  Each output
 // takes the same products in the same order either way.
-template <bool W16>
+// ERI: R holds nothing yet; the epilogue evaluates the candidate columns' integrals V[I][cand_c]
+// itself (the values the column kernel would have stored, bit for bit), which saves writing R and
+// reading it back (2 x 8 x npairs x 64 bytes per block).
+template <bool W16, bool ERI>
 __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_t ldl, int64_t npairs,
                                                          int64_t k0, const CdState *__restrict__ st,
                                                          const double *P, double *__restrict__ R,
                                                          int64_t ldr, const signed char *__restrict__ slotmap,
-                                                         double *__restrict__ rc)
+                                                         double *__restrict__ rc, PairTable pt,
+                                                         const int64_t *__restrict__ cand)
 {
     constexpr int D = CD_PASS_D;
     __shared__ double red[2][CD_NCAND][CD_TILE];           // red[slot][cand][row ^ cand]
@@ -1716,11 +1720,26 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
     const int row = threadIdx.x % CD_TILE;
     const int64_t I = tile0 + row;
     const int sl = I < npairs ? slotmap[I] : -1;
+    double ip = 0.0, ipx = 0.0, ipy = 0.0, ipz = 0.0, ik = 0.0;
+    if (ERI && I < npairs) {
+        ip = pt.p[I];
+        ipx = pt.Px[I];
+        ipy = pt.Py[I];
+        ipz = pt.Pz[I];
+        ik = pt.K[I];
+    }
 #pragma unroll
     for (int q = 0; q < CD_TILE * CD_NCAND / 256; ++q) {
         const int c = (threadIdx.x + 256 * q) / CD_TILE;
         if (c < nc && I < npairs) {
-            const double v = R[(int64_t)c * ldr + I] - (red[0][c][row ^ c] + red[1][c][row ^ c]);  // base V[I][cand_c]
+            double base;                                           // V[I][cand_c]
+            if constexpr (ERI) {
+                const int64_t qc = cand[c];
+                base = eri_pp(ip, ipx, ipy, ipz, ik, pt.p[qc], pt.Px[qc], pt.Py[qc], pt.Pz[qc], pt.K[qc]);
+            } else {
+                base = R[(int64_t)c * ldr + I];
+            }
+            const double v = base - (red[0][c][row ^ c] + red[1][c][row ^ c]);
             R[(int64_t)c * ldr + I] = v;
             if (sl >= 0) rc[c * CD_NCAND + sl] = v;
         }
@@ -1966,25 +1985,35 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         const int64_t cgx = cds_ceil_div(npairs, 256);
         const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
         const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCG + gy));
+        // on demand, the pass evaluates the candidate columns' integrals in its epilogue and only the
+        // gather runs before it
         if (dense)
             hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
                                npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
                                ldl, Pc);
         else
-            hipLaunchKernelGGL(cd_candcol_gather_kernel<false>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
-                               npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
-                               ldl, Pc);
+            hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256)),
+                               dim3(256), 0, ctx->stream, (const double *)L, ldl, (int64_t)-1, (const CdState *)st,
+                               (const int64_t *)cand, Pc);
         CDS_LAUNCHED(ctx);
         CdsTimer tp;
         if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
-        if (pass16)
-            hipLaunchKernelGGL(cd_pass_kernel<true>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
-                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc);
+        if (pass16 && !dense)
+            hipLaunchKernelGGL((cd_pass_kernel<true, true>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
+        else if (pass16)
+            hipLaunchKernelGGL((cd_pass_kernel<true, false>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
+        else if (!dense)
+            hipLaunchKernelGGL((cd_pass_kernel<false, true>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
         else
-            hipLaunchKernelGGL(cd_pass_kernel<false>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl, npairs,
-                               (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc);
+            hipLaunchKernelGGL((cd_pass_kernel<false, false>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
         CDS_LAUNCHED(ctx);
         if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
         if (hook && hook->block) CDS_CALL(hook->block(hook->user));
@@ -2109,13 +2138,13 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 CdsTimer tp;
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
                 if (pass16)
-                    hipLaunchKernelGGL(cd_pass_kernel<true>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                                       npairs, k, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                                       (const signed char *)bf.slot, bf.rc);
+                    hipLaunchKernelGGL((cd_pass_kernel<true, false>), grid, dim3(256), 0, ctx->stream,
+                                       (const double *)L, ldl, npairs, k, (const CdState *)st, (const double *)Pc, Rc,
+                                       ldr, (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
                 else
-                    hipLaunchKernelGGL(cd_pass_kernel<false>, grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                                       npairs, k, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                                       (const signed char *)bf.slot, bf.rc);
+                    hipLaunchKernelGGL((cd_pass_kernel<false, false>), grid, dim3(256), 0, ctx->stream,
+                                       (const double *)L, ldl, npairs, k, (const CdState *)st, (const double *)Pc, Rc,
+                                       ldr, (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
                 CDS_LAUNCHED(ctx);
                 if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
                 ctx->stats.n_cd_pass_launch += 1;
