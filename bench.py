@@ -182,8 +182,8 @@ def cd_report(st: dict, steps: int, npairs: int, M: int) -> dict:
                  "hardware_frac": round(st["flops_cd_pass"] / t_pass / 1e12 / FP64_MFMA_TFLOPS, 4) if t_pass > 0 else None,
                  "method_tflops_fp64": round(st["flops_cd_pass_method"] / t_pass / 1e12, 2) if t_pass > 0 else None,
                  "method_frac": round(st["flops_cd_pass_method"] / t_pass / 1e12 / FP64_MFMA_TFLOPS, 4) if t_pass > 0 else None,
-                 "units": ("hardware: 2 x pairs x k0 x 64 candidate columns per launch; method: 2 x pairs x k0 "
-                           "per step the block keeps")},
+                 "units": ("hardware: 2 x pairs x k0 x columns formed per launch (the block's speculated steps, "
+                           "in groups of 16); method: 2 x pairs x k0 per step the block keeps")},
         "speculative": {"blocks_per_cd": st["n_cd_spec_block"] / steps, "steps_per_cd": st["n_cd_spec"] / steps,
                         "state_reads_per_cd": st["n_cd_state_read"] / steps},
         "decomposition": {"ms": round(t_cd * 1e3 / steps, 3), "method_tflops_fp64": round(plain_flops / t_cd / 1e12, 2),

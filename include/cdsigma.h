@@ -91,10 +91,12 @@ typedef struct cds_stats {
     int64_t n_contract;
     int64_t n_newton_iter;
     double t_cd_pass_ms;     /* look-ahead pass kernels (with kernel timing on) */
-    double bytes_cd_pass;    /* bytes those passes read/write: 8 npairs (k0 + 64) */
+    double bytes_cd_pass;    /* bytes those passes read/write: 8 npairs (k0 + ncol),
+                                ncol = 64 candidates, or on the large path the
+                                block's speculated steps rounded up to 16 */
     int64_t n_cd_pass;       /* look-ahead passes that did work               */
     int64_t n_cd_miss;       /* steps whose pivot was not a look-ahead candidate */
-    double flops_cd_pass;    /* nominal pass flops: 2 npairs k0 (64 candidates) */
+    double flops_cd_pass;    /* nominal pass flops: 2 npairs k0 ncol          */
     double bytes_cd_step;    /* algorithmic bytes of the step kernels: per step and
                                 pair row 8 per vector subtracted + 26 (D, mask,
                                 L_k) + 8 (column from R or V) or 40 (pair data) */

@@ -22,6 +22,11 @@
 //                outside the candidates would have changed the pivot choice
 //     cd_commit  the steps before the first failing one become real (D, mask, tile
 //                records, pivots); the next block starts there
+//   large path (separate speculative and row kernels): only the speculated pivots' columns
+//   are ever read, so the candidates' own 64 x 64 block comes first from the gathered rows
+//   (cd_cc, the pass's operations entry for entry), cd_spec chooses the steps, and the pass
+//   forms just those columns (cd_pass_cols, 16 per group): the same values, a fraction of
+//   the work
 //   per-step kernel (block_steps steps per block when speculation is off, or when
 //   nothing could be committed): ONE launch per step (cd_step), each block of one
 //   (or, for many tiles, four) 64-row tiles:
@@ -96,6 +101,8 @@ struct CdState {
     double sumk0s;   // sum over committed blocks of start step x steps kept (the pass's share of
                      // the plain algorithm's products: each kept step needs vectors 0 .. k0-1)
     double sumwin;   // sum over committed blocks of j for each kept step j (the block's own share)
+    double sumk0c;   // large path: sum over passes of start step x columns formed (16 per group)
+    int64_t ncols;   // large path: columns the passes formed
 };
 
 // Host mailbox word, written by each speculative block's commit: the committed step count,
@@ -162,18 +169,22 @@ __device__ __forceinline__ double okey_min(unsigned long long u)
 // square root, one division); the series near T = 0
 __device__ __forceinline__ double boys_f0(double T)
 {
+#pragma clang fp contract(off)
     if (T < 1e-12) return 1.0 - T / 3.0 + T * T / 10.0;
     const double t = sqrt(T);
     return 0.88622692545275801365 * erf(t) / t;           // sqrt(pi) / 2
 }
 
-// (rho_I | V | rho_J) for two s-Gaussian product densities
+// (rho_I | V | rho_J) for two s-Gaussian product densities.  No implicit contraction: the fused
+// multiply-adds are written out, so every kernel that inlines it forms the same value (the
+// speculative path relies on the candidates' block and the pass agreeing bit for bit).
 __device__ __forceinline__ double eri_pp(double p, double Px, double Py, double Pz, double Kp,
                                          double q, double Qx, double Qy, double Qz, double Kq)
 {
+#pragma clang fp contract(off)
     const double two_pi_52 = 2.0 * 17.493418327624862;   // 2 pi^(5/2)
     const double dx = Px - Qx, dy = Py - Qy, dz = Pz - Qz;
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     const double s = p + q, pq = p * q;
     const double e = 1.0 / (pq * s);                        // one division for both factors
     const double T = pq * pq * e * r2;                      // p q / (p + q) * r2
@@ -587,12 +598,16 @@ __global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, CdParams 
 // written (atomics) and reset for the step after next.  Loads that do not depend on the
 // pivot (the vectors made since the block start, D, mask, the candidate list) are issued
 // before the pivot search.
+struct SpecOut;
+// whether candidate slot sl had its residual column formed by the block's pass (defined below)
+__device__ bool spec_formed(const SpecOut *so, int sl);
+
 template <int VW, int TB, bool DENSE>
 __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     CdBufs b, CdParams cp, int r, int sr, int sw, int sz, int64_t k, int64_t k0, int bsteps,
     PairTable pt, const double *__restrict__ V, int64_t ldv, double *__restrict__ L, int64_t ldl,
     const double *__restrict__ R, int64_t ldr, const int64_t *__restrict__ cand, CdState *st,
-    int64_t *__restrict__ piv)
+    int64_t *__restrict__ piv, const SpecOut *__restrict__ sov)
 {
     constexpr int NR = CD_TILE * TB;            // rows per block
     constexpr int RL = NR / VW;                 // row lanes
@@ -656,7 +671,12 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     const double sq = sqrt(pk.dp);
     if (threadIdx.x < 64) {
         const unsigned long long hit = __ballot((int)threadIdx.x < nc && cl == p);
-        if (threadIdx.x == 0) sslot = hit ? __ffsll((long long)hit) - 1 : -1;
+        if (threadIdx.x == 0) {
+            int sl = hit ? __ffsll((long long)hit) - 1 : -1;
+            // large path (sov set): only the speculated candidates' columns were formed
+            if (sl >= 0 && sov && !spec_formed(sov, sl)) sl = -1;
+            sslot = sl;
+        }
     }
     __syncthreads();
     const int slot = sslot;
@@ -827,6 +847,13 @@ struct SpecOut {
 // kernels of later blocks then return at once until the host has run one per-step launch.
 __device__ __forceinline__ bool spec_idle(const CdState *st) { return st->done || st->stall; }
 
+__device__ bool spec_formed(const SpecOut *so, int sl)
+{
+    bool formed = false;
+    for (int j = 0; j < so->nspec; ++j) formed |= so->slot[j] == sl;
+    return formed;
+}
+
 // steps of the block that stand: those before the first failed check
 __device__ __forceinline__ int spec_keep(const SpecOut *so)
 {
@@ -880,7 +907,8 @@ struct SpecWave {
         I = have ? cand[l] : -1;
         d = have ? b.D[r][I] : 0.0;
         m = have ? b.mask[r][I] : 1;
-        // the candidates' 64 x 64 residual block (compact, written by the pass), 32 loads in flight
+        // the candidates' 64 x 64 residual block (compact, written by the pass or, on the large
+        // path, by cd_cc_kernel), 32 loads in flight
         {
             double v[CD_NCAND];
 #pragma unroll
@@ -1011,8 +1039,9 @@ __device__ __forceinline__ void spec_publish(const SpecOut &ss, SpecOut *so)
         if (q != iv) ((int64_t *)so)[q] = ((const int64_t *)&ss)[q];
 }
 
+// (the large path: before the pass, which then forms the ns speculated columns in groups of 16)
 __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, const int64_t *__restrict__ cand,
-                                                     const CdState *st, SpecOut *so)
+                                                     CdState *st, SpecOut *so)
 {
     __shared__ SpecLds sm;
     __shared__ SpecOut ss;
@@ -1020,7 +1049,12 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
     spec_body(b, cp, cand, st, sm, ss);
     wave_lds_sync();
     spec_publish(ss, so);
-    if (threadIdx.x == 0) so->viol = 0ull;
+    if (threadIdx.x == 0) {
+        so->viol = 0ull;
+        const int cols = 16 * ((ss.nspec + 15) / 16);
+        st->sumk0c += (double)ss.k0 * (double)cols;
+        st->ncols += cols;
+    }
 }
 
 // every row of the workgroup: the speculated vectors L[k0+j] (same operations as
@@ -1746,6 +1780,265 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
     }
 }
 
+// Large path, step 1 of a speculative block: the candidates' own residual block before any
+// full-length column exists, rc[c][s] = V[cand_s][cand_c] - sum_{j<k0} P[j][s] P[j][c] (s, c < nc;
+// P[j][s] = L[j][cand_s] from the gather).  Each entry takes exactly the operations the pass
+// applies to row cand_s, column c: the same f64 MFMA over k-steps of 4 vectors (lane g supplies
+// vector 4s + g), the same four vector ranges accumulated in order, summed (w0 + w2) + (w1 + w3),
+// subtracted from the same integral.  Steps past a range add products with a zero row of P,
+// which change nothing, so the ring depth may differ from the pass's.  16 workgroups, one 16 x 16
+// block each; the speculative block then runs on rc exactly as when the pass wrote it.
+template <bool DENSE>
+__global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ st, const double *P,
+                                                    const int64_t *__restrict__ cand, PairTable pt,
+                                                    const double *__restrict__ V, int64_t ldv,
+                                                    double *__restrict__ rc)
+{
+    constexpr int D = 8;                                   // k-steps in flight per wave
+    __shared__ double red[2][16][16];
+    if (spec_idle(st) || st->ncand == 0) return;
+    const int64_t k0 = st->k;
+    const int nc = st->ncand;
+    const int rg = (int)blockIdx.x >> 2, cgp = (int)blockIdx.x & 3;
+    if (16 * rg >= nc || 16 * cgp >= nc) return;           // uniform over the workgroup
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+    const int64_t ks = (k0 + 3) / 4;
+    const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
+    const int64_t jz = 4 * ks;                             // a zero row of P
+    doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+    double a[D], b[D];
+    auto load = [&](int64_t s, double &as, double &bs) {
+        const int64_t j = s < s1 ? 4 * s + g : jz;
+        as = P[j * CD_NCAND + 16 * rg + r16];
+        bs = P[j * CD_NCAND + 16 * cgp + r16];
+    };
+    if (s1 > s0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            load(s0 + i, a[i], b[i]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int64_t s = s0; s < s1; s += D) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[i], acc, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                asm volatile("" ::: "memory");
+                load(s + i + D, a[i], b[i]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    // acc[e]: row g + 4e, column r16 of the block, over this wave's range
+    if (w >= 2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[w - 2][g + 4 * e][r16] = acc[e];
+    __syncthreads();
+    if (w < 2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += red[w][g + 4 * e][r16];
+    __syncthreads();
+    if (w < 2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[w][g + 4 * e][r16] = acc[e];
+    __syncthreads();
+    if (w == 0) {
+        const int c = 16 * cgp + r16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int s = 16 * rg + g + 4 * e;
+            if (s < nc && c < nc) {
+                const int64_t I = cand[s], q = cand[c];
+                double base;                                   // V[cand_s][cand_c], as the pass forms it
+                if constexpr (DENSE)
+                    base = V[q * ldv + I];
+                else
+                    base = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[q], pt.Px[q], pt.Py[q],
+                                  pt.Pz[q], pt.K[q]);
+                rc[c * CD_NCAND + s] = base - (red[0][g + 4 * e][r16] + red[1][g + 4 * e][r16]);
+            }
+        }
+    }
+}
+
+// Large path, step 3 of a speculative block (after the speculative wave has chosen its ns steps
+// from rc): the pass for the speculated columns only.  Column j < ns is candidate slot_j:
+// R[slot_j][I] = V[I][cand_slot_j] - sum_{j'<k0} L[j'][I] P[j'][slot_j], every entry with the
+// operations of cd_pass_kernel (same A operand and ring, same vector ranges, same reduction),
+// so the values equal those of the full pass; the rows kernel reads exactly these columns.
+// NG = ceil(ns / 16) column groups of 16; columns past ns read a zero row of P and are not
+// written.  Work and R traffic scale with ns instead of all 64 candidates.
+template <bool W16, bool DENSE, int NG>
+__device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int64_t npairs, int64_t k0,
+                                               const double *P, double *__restrict__ R, int64_t ldr,
+                                               const PairTable &pt, const double *__restrict__ V,
+                                               int64_t ldv, int ns, const int *csl, const double (*cdat)[CD_SPEC_MAX],
+                                               const int64_t *ccol, double (*red)[CD_SPEC_MAX][CD_TILE])
+{
+    constexpr int D = CD_PASS_D;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+    const int64_t tile0 = (int64_t)blockIdx.x * CD_TILE;
+    int64_t rowL[4];
+    if constexpr (W16) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) rowL[u] = min(tile0 + 32 * u + 2 * r16, ldl - 2);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) rowL[m] = min(tile0 + 16 * m + r16, npairs - 1);
+    }
+    // this lane's B columns: slot of column 16 n + r16, or a zero row of P past ns
+    int bcol[NG];
+    bool bon[NG];
+#pragma unroll
+    for (int n = 0; n < NG; ++n) {
+        const int col = 16 * n + r16;
+        bon[n] = col < ns;
+        bcol[n] = bon[n] ? csl[col] : 0;
+    }
+    const int64_t ks = (k0 + 3) / 4;
+    const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
+    const int64_t jz = 4 * ks;
+    const int64_t jl_max = k0 > 0 ? k0 - 1 : 0;
+    doublex4 acc[4][NG];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NG; ++n) acc[m][n] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double a[D][4], b[D][NG];
+    auto load = [&](int64_t s, double *as, double *bs) {
+        const int64_t j = 4 * s + g;
+        const int64_t jl = min(j, jl_max);
+        const int64_t jp = s < s1 ? j : jz;
+        if constexpr (W16) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const double2 x = *reinterpret_cast<const double2 *>(L + jl * ldl + rowL[u]);
+                as[2 * u] = x.x;
+                as[2 * u + 1] = x.y;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) as[m] = L[jl * ldl + rowL[m]];
+        }
+#pragma unroll
+        for (int n = 0; n < NG; ++n) bs[n] = P[(bon[n] ? jp : jz) * CD_NCAND + bcol[n]];
+    };
+    auto trow = [&](int m, int q) { return W16 ? 32 * (m >> 1) + 2 * q + (m & 1) : 16 * m + q; };
+    if (k0 > 0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            load(s0 + i, a[i], b[i]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int64_t s = s0; s < s1; s += D) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < NG; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][m], b[i][n], acc[m][n], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                asm volatile("" ::: "memory");
+                load(s + i + D, a[i], b[i]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    // (w0 + w2) + (w1 + w3) as in cd_pass_kernel; entry (column c, row) at red[.][c][row ^ c]
+    auto put = [&](int slot) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < NG; ++n)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 16 * n + r16, row = trow(m, g + 4 * e);
+                    red[slot][c][row ^ c] = acc[m][n][e];
+                }
+    };
+    auto add = [&](int slot) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < NG; ++n)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 16 * n + r16, row = trow(m, g + 4 * e);
+                    acc[m][n][e] += red[slot][c][row ^ c];
+                }
+    };
+    if (w >= 2) put(w - 2);
+    __syncthreads();
+    if (w < 2) add(w);
+    __syncthreads();
+    if (w < 2) put(w);
+    __syncthreads();
+    const int row = threadIdx.x % CD_TILE;
+    const int64_t I = tile0 + row;
+    if (I >= npairs) return;
+    double ip = 0.0, ipx = 0.0, ipy = 0.0, ipz = 0.0, ik = 0.0;
+    if constexpr (!DENSE) {
+        ip = pt.p[I];
+        ipx = pt.Px[I];
+        ipy = pt.Py[I];
+        ipz = pt.Pz[I];
+        ik = pt.K[I];
+    }
+#pragma unroll
+    for (int q = 0; q < 16 * NG * CD_TILE / 256; ++q) {
+        const int c = (threadIdx.x + 256 * q) / CD_TILE;        // uniform over the wave
+        if (c < ns) {
+            double base;
+            if constexpr (DENSE)
+                base = V[ccol[c] * ldv + I];
+            else
+                base = eri_pp(ip, ipx, ipy, ipz, ik, cdat[0][c], cdat[1][c], cdat[2][c], cdat[3][c], cdat[4][c]);
+            R[(int64_t)csl[c] * ldr + I] = base - (red[0][c][row ^ c] + red[1][c][row ^ c]);
+        }
+    }
+}
+
+template <bool W16, bool DENSE>
+__global__ __launch_bounds__(256, 3) void cd_pass_cols_kernel(const double *L, int64_t ldl, int64_t npairs,
+                                                              const CdState *__restrict__ st, const SpecOut *so,
+                                                              const double *P, double *__restrict__ R, int64_t ldr,
+                                                              PairTable pt, const double *__restrict__ V, int64_t ldv,
+                                                              const int64_t *__restrict__ cand)
+{
+    __shared__ double red[2][CD_SPEC_MAX][CD_TILE];   // 48 KB: three workgroups per CU
+    __shared__ int csl[CD_SPEC_MAX];                  // candidate slot of column j
+    __shared__ double cdat[5][CD_SPEC_MAX];           // its pair data (integrals)
+    __shared__ int64_t ccol[CD_SPEC_MAX];             // its pair index (dense V)
+    if (spec_idle(st)) return;
+    const int ns = so->nspec;
+    if (ns <= 0) return;
+    const int64_t k0 = so->k0;
+    if (threadIdx.x < CD_SPEC_MAX) {
+        const int j = threadIdx.x;
+        const int sl = j < ns ? so->slot[j] : 0;
+        csl[j] = sl;
+        const int64_t q = cand[sl];
+        ccol[j] = q;
+        if constexpr (!DENSE) {
+            cdat[0][j] = pt.p[q];
+            cdat[1][j] = pt.Px[q];
+            cdat[2][j] = pt.Py[q];
+            cdat[3][j] = pt.Pz[q];
+            cdat[4][j] = pt.K[q];
+        }
+    }
+    __syncthreads();
+    if (ns <= 16)
+        pass_cols_body<W16, DENSE, 1>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, ns, csl, cdat, ccol, red);
+    else if (ns <= 32)
+        pass_cols_body<W16, DENSE, 2>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, ns, csl, cdat, ccol, red);
+    else
+        pass_cols_body<W16, DENSE, 3>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, ns, csl, cdat, ccol, red);
+}
+
 __global__ void max_reduce_kernel(int64_t n, const double *__restrict__ x, double *__restrict__ out)
 {
     __shared__ double sh[CD_AUX_NT / 64];
@@ -1776,11 +2069,12 @@ int setup_pairs(cds_ctx *ctx, int32_t nbf, const double *centres, const double *
 template <int VW, int TB, bool DENSE>
 void launch_step(cds_ctx *ctx, const CdBufs &b, const CdParams &cp, int r, int sr, int sw, int sz,
                  int64_t k, int64_t k0, int bsteps, const PairTable &pt, const double *V, int64_t ldv, double *L,
-                 int64_t ldl, const double *R, int64_t ldr, const int64_t *cand, CdState *st, int64_t *piv)
+                 int64_t ldl, const double *R, int64_t ldr, const int64_t *cand, CdState *st, int64_t *piv,
+                 const SpecOut *sov)
 {
     const dim3 grid((unsigned)cds_ceil_div(b.ntile, TB));
     hipLaunchKernelGGL((cd_step_kernel<VW, TB, DENSE>), grid, dim3(CD_NT), 0, ctx->stream, b, cp, r, sr, sw, sz,
-                       k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+                       k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv, sov);
 }
 
 // step-kernel shape: rows per thread (16-byte loads when the layout allows) and tiles per
@@ -1789,16 +2083,16 @@ template <bool DENSE>
 void launch_step_any(cds_ctx *ctx, int vw, int tb, const CdBufs &b, const CdParams &cp, int r, int sr, int sw,
                      int sz, int64_t k, int64_t k0, int bsteps, const PairTable &pt, const double *V, int64_t ldv,
                      double *L, int64_t ldl, const double *R, int64_t ldr, const int64_t *cand, CdState *st,
-                     int64_t *piv)
+                     int64_t *piv, const SpecOut *sov)
 {
     if (vw == 2 && tb == 4)
-        launch_step<2, 4, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+        launch_step<2, 4, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv, sov);
     else if (vw == 2)
-        launch_step<2, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+        launch_step<2, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv, sov);
     else if (tb == 4)
-        launch_step<1, 4, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+        launch_step<1, 4, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv, sov);
     else
-        launch_step<1, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv);
+        launch_step<1, 1, DENSE>(ctx, b, cp, r, sr, sw, sz, k, k0, bsteps, pt, V, ldv, L, ldl, R, ldr, cand, st, piv, sov);
 }
 
 // The mailbox word (coherent pinned host memory, written by the device over the bus), made
@@ -1978,60 +2272,103 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     const bool mb = spec_on && mail_ready(ctx);
     if (mb) __atomic_store_n(ctx->mail, mb_word(st0.nblk, 0, 0), __ATOMIC_RELEASE);
     bool blocks_ran = false;               // speculative blocks since the last read of the state
+    // the large path (separate speculative and row kernels) forms the candidates' own block
+    // first, lets the speculative wave choose its steps, and then passes over the speculated
+    // columns only; the small path runs the full pass and the lockstep kernel
+    const unsigned nrb = (unsigned)cds_ceil_div(npairs, 256);
+    const unsigned nlb = (unsigned)cds_ceil_div(npairs, CD_LS_ROWS);
+    const bool lockstep = nlb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path;
+    const bool early = spec_on && !lockstep;
     auto queue_block = [&]() -> int {
         hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
                            st, cand, so);
         CDS_LAUNCHED(ctx);
-        const int64_t cgx = cds_ceil_div(npairs, 256);
-        const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
-        const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCG + gy));
-        // on demand, the pass evaluates the candidate columns' integrals in its epilogue and only the
-        // gather runs before it
-        if (dense)
-            hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
-                               npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
-                               ldl, Pc);
-        else
-            hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256)),
-                               dim3(256), 0, ctx->stream, (const double *)L, ldl, (int64_t)-1, (const CdState *)st,
-                               (const int64_t *)cand, Pc);
-        CDS_LAUNCHED(ctx);
-        CdsTimer tp;
-        if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
-        if (pass16 && !dense)
-            hipLaunchKernelGGL((cd_pass_kernel<true, true>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
-        else if (pass16)
-            hipLaunchKernelGGL((cd_pass_kernel<true, false>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
-        else if (!dense)
-            hipLaunchKernelGGL((cd_pass_kernel<false, true>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
-        else
-            hipLaunchKernelGGL((cd_pass_kernel<false, false>), grid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                               npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
-                               (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
-        CDS_LAUNCHED(ctx);
-        if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
-        if (hook && hook->block) CDS_CALL(hook->block(hook->user));
+        const dim3 ggrid((unsigned)cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256));
+        if (early) {
+            hipLaunchKernelGGL(cd_gather_kernel, ggrid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                               (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
+            CDS_LAUNCHED(ctx);
+            CdsTimer tcc;
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tcc));
+            if (dense)
+                hipLaunchKernelGGL(cd_cc_kernel<true>, dim3(16), dim3(256), 0, ctx->stream, (const CdState *)st,
+                                   (const double *)Pc, (const int64_t *)cand, pt, V, ldv, bf.rc);
+            else
+                hipLaunchKernelGGL(cd_cc_kernel<false>, dim3(16), dim3(256), 0, ctx->stream, (const CdState *)st,
+                                   (const double *)Pc, (const int64_t *)cand, pt, V, ldv, bf.rc);
+            CDS_LAUNCHED(ctx);
+            hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
+                               st, so);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tcc, &ctx->stats.t_cd_spec_ms));
+            CdsTimer tp;
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
+            if (pass16 && !dense)
+                hipLaunchKernelGGL((cd_pass_cols_kernel<true, false>), grid, dim3(256), 0, ctx->stream,
+                                   (const double *)L, ldl, npairs, (const CdState *)st, (const SpecOut *)so,
+                                   (const double *)Pc, Rc, ldr, pt, V, ldv, (const int64_t *)cand);
+            else if (pass16)
+                hipLaunchKernelGGL((cd_pass_cols_kernel<true, true>), grid, dim3(256), 0, ctx->stream,
+                                   (const double *)L, ldl, npairs, (const CdState *)st, (const SpecOut *)so,
+                                   (const double *)Pc, Rc, ldr, pt, V, ldv, (const int64_t *)cand);
+            else if (!dense)
+                hipLaunchKernelGGL((cd_pass_cols_kernel<false, false>), grid, dim3(256), 0, ctx->stream,
+                                   (const double *)L, ldl, npairs, (const CdState *)st, (const SpecOut *)so,
+                                   (const double *)Pc, Rc, ldr, pt, V, ldv, (const int64_t *)cand);
+            else
+                hipLaunchKernelGGL((cd_pass_cols_kernel<false, true>), grid, dim3(256), 0, ctx->stream,
+                                   (const double *)L, ldl, npairs, (const CdState *)st, (const SpecOut *)so,
+                                   (const double *)Pc, Rc, ldr, pt, V, ldv, (const int64_t *)cand);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
+            if (hook && hook->block) CDS_CALL(hook->block(hook->user));
+        }
         CdsTimer tsp;
         if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
-        const unsigned nrb = (unsigned)cds_ceil_div(npairs, 256);
-        const unsigned nlb = (unsigned)cds_ceil_div(npairs, CD_LS_ROWS);
-        if (nlb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path) {
+        if (early) {
+            hipLaunchKernelGGL(cd_rows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp, (const CdState *)st,
+                               (const double *)Rc, ldr, L, ldl, Dbuf, so);
+            CDS_LAUNCHED(ctx);
+        } else {
+            const int64_t cgx = cds_ceil_div(npairs, 256);
+            const int64_t gy = cds_ceil_div(cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256), cgx);
+            const dim3 cgrid((unsigned)cgx, (unsigned)(CD_NCG + gy));
+            // on demand, the pass evaluates the candidate columns' integrals in its epilogue and
+            // only the gather runs before it
+            if (dense)
+                hipLaunchKernelGGL(cd_candcol_gather_kernel<true>, cgrid, dim3(256), 0, ctx->stream, pt, V, ldv,
+                                   npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
+                                   ldl, Pc);
+            else
+                hipLaunchKernelGGL(cd_gather_kernel, ggrid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+                                   (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
+            CdsTimer tp;
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tp));
+            if (pass16 && !dense)
+                hipLaunchKernelGGL((cd_pass_kernel<true, true>), grid, dim3(256), 0, ctx->stream, (const double *)L,
+                                   ldl, npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                                   (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
+            else if (pass16)
+                hipLaunchKernelGGL((cd_pass_kernel<true, false>), grid, dim3(256), 0, ctx->stream, (const double *)L,
+                                   ldl, npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                                   (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
+            else if (!dense)
+                hipLaunchKernelGGL((cd_pass_kernel<false, true>), grid, dim3(256), 0, ctx->stream, (const double *)L,
+                                   ldl, npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                                   (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
+            else
+                hipLaunchKernelGGL((cd_pass_kernel<false, false>), grid, dim3(256), 0, ctx->stream, (const double *)L,
+                                   ldl, npairs, (int64_t)-1, (const CdState *)st, (const double *)Pc, Rc, ldr,
+                                   (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
+            CDS_LAUNCHED(ctx);
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
+            if (hook && hook->block) CDS_CALL(hook->block(hook->user));
+            if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
             hipLaunchKernelGGL(cd_lockstep_kernel, dim3(nlb), dim3(64 + CD_LS_ROWS), 0, ctx->stream, bf, cp,
                                (const int64_t *)cand, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf,
                                so);
-            CDS_LAUNCHED(ctx);
-        } else {
-            hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
-                               (const CdState *)st, so);
-            CDS_LAUNCHED(ctx);
-            hipLaunchKernelGGL(cd_rows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp, (const CdState *)st,
-                               (const double *)Rc, ldr, L, ldl, Dbuf, so);
             CDS_LAUNCHED(ctx);
         }
         if (!bf.flat) {
@@ -2069,10 +2406,10 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tk));
             if (dense)
                 launch_step_any<true>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k, bsteps, pt, V, ldv, L, ldl, Rc,
-                                      ldr, cand, st, piv);
+                                      ldr, cand, st, piv, early ? (const SpecOut *)so : nullptr);
             else
                 launch_step_any<false>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k, bsteps, pt, V, ldv, L, ldl, Rc,
-                                       ldr, cand, st, piv);
+                                       ldr, cand, st, piv, early ? (const SpecOut *)so : nullptr);
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tk, &ctx->stats.t_cd_kernel_ms));
             ctx->stats.n_cd_step_launch += 1;
@@ -2158,10 +2495,10 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             }
             if (dense)
                 launch_step_any<true>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
-                                      ldr, cand, st, piv);
+                                      ldr, cand, st, piv, nullptr);
             else
                 launch_step_any<false>(ctx, vw, tb, bf, cp, r2, sr2, sw2, sz2, k, k0, bsteps, pt, V, ldv, L, ldl, Rc,
-                                       ldr, cand, st, piv);
+                                       ldr, cand, st, piv, nullptr);
             CDS_LAUNCHED(ctx);
             ctx->stats.n_cd_step_launch += 1;
         }
@@ -2186,8 +2523,14 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         ctx->stats.n_cd_pass += hs.npass;
         ctx->stats.n_cd_spec_block += hs.npass;
         ctx->stats.n_cd_spec += hs.nspec;
-        ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * hs.sumk0 + 8.0 * CD_NCAND * (double)npairs * (double)hs.npass;
-        ctx->stats.flops_cd_pass += 2.0 * (double)npairs * hs.sumk0 * CD_NCAND;
+        if (early) {
+            // the columns formed (16 per group of speculated steps)
+            ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * hs.sumk0 + 8.0 * (double)npairs * (double)hs.ncols;
+            ctx->stats.flops_cd_pass += 2.0 * (double)npairs * hs.sumk0c;
+        } else {
+            ctx->stats.bytes_cd_pass += 8.0 * (double)npairs * hs.sumk0 + 8.0 * CD_NCAND * (double)npairs * (double)hs.npass;
+            ctx->stats.flops_cd_pass += 2.0 * (double)npairs * hs.sumk0 * CD_NCAND;
+        }
         ctx->stats.flops_cd_pass_method += 2.0 * (double)npairs * hs.sumk0s;
         ctx->stats.flops_cd_block_method += 2.0 * (double)npairs * hs.sumwin;
     }

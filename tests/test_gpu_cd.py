@@ -170,6 +170,46 @@ def test_cd_large_path(cds, name, delta, lookahead):
 
 
 @pytest.mark.parametrize("name,delta", [("plain", 1e-8), ("c60", 1e-6)])
+def test_cd_large_path_equals_small_path(cds, name, delta):
+    # the large path forms the candidates' own block first and passes over the speculated columns
+    # only; every value it uses equals the full pass's, so the decomposition equals the small
+    # path's (full pass, lockstep kernel) bit for bit
+    w = workload(name)
+    log(f"cd large path against small path {name} delta={delta}")
+    c, a = _dev(w.centres), _dev(w.alpha)
+    got = []
+    for large in (False, True):
+        ctx = cds.Context(0)
+        ctx.set_cd_large_path(large)
+        got.append(cds.cholesky(delta, centres=c, alpha=a, ctx=ctx))
+    small, large = got
+    assert large.nvec == small.nvec and large.status == small.status
+    assert torch.equal(large.piv[: large.nvec], small.piv[: small.nvec])
+    assert torch.equal(large.L.contiguous().view(torch.int64), small.L.contiguous().view(torch.int64))
+    assert torch.equal(large.D.view(torch.int64), small.D.view(torch.int64))
+
+
+@pytest.mark.parametrize("delta", [1e-6, 1e-8])
+def test_cd_large_path_dense(cds, delta):
+    # the large path's speculative blocks on a dense V (the candidates' own block first, then the
+    # pass over the speculated columns, reading V directly): the oracle's pivots, vectors to rounding
+    w = workload("plain")
+    V = dense_V("plain")
+    log(f"cd large-problem path, dense plain delta={delta}")
+    ctx = cds.Context(0)
+    ctx.set_cd_large_path(True)
+    ref = oracle_cd("plain", delta, dense=True)
+    got = cds.cholesky(delta, V=_dev(V), max_vec=w.npairs, ctx=ctx)
+    st = ctx.stats()
+    log(f"  {st['n_cd_spec']} of {got.nvec} steps from {st['n_cd_spec_block']} speculative blocks")
+    assert got.status == 0 and got.nvec == ref.M
+    assert np.array_equal(got.piv[: got.nvec].cpu().numpy(), ref.piv)
+    assert st["n_cd_spec"] >= got.nvec // 2
+    tol = cd_tolerance(ref, np.diag(V).max())
+    assert np.all(np.abs(got.L.cpu().numpy().T - ref.L).max(axis=0) <= tol)
+
+
+@pytest.mark.parametrize("name,delta", [("plain", 1e-8), ("c60", 1e-6)])
 def test_cd_speculative_blocks(cds, name, delta):
     # speculative look-ahead blocks on and off: same pivots, vectors equal to rounding; most
     # steps come from the speculative blocks
