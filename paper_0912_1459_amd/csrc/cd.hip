@@ -1743,14 +1743,9 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
                     acc[m][n][e] += red[slot][c][row ^ c];
                 }
     };
-    if (w >= 2) put(w - 2);
-    __syncthreads();
-    if (w < 2) add(w);
-    __syncthreads();
-    if (w < 2) put(w);
-    __syncthreads();
     // R[c][I] -= block[I][c], all 256 threads, consecutive threads on consecutive rows (each
-    // thread keeps one row); a candidate row also goes to the compact block rc
+    // thread keeps one row); a candidate row also goes to the compact block rc.  The row's data
+    // is loaded under the reduction.
     const int row = threadIdx.x % CD_TILE;
     const int64_t I = tile0 + row;
     const int sl = I < npairs ? slotmap[I] : -1;
@@ -1762,6 +1757,12 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
         ipz = pt.Pz[I];
         ik = pt.K[I];
     }
+    if (w >= 2) put(w - 2);
+    __syncthreads();
+    if (w < 2) add(w);
+    __syncthreads();
+    if (w < 2) put(w);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < CD_TILE * CD_NCAND / 256; ++q) {
         const int c = (threadIdx.x + 256 * q) / CD_TILE;
@@ -1790,19 +1791,56 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
 // block each; the speculative block then runs on rc exactly as when the pass wrote it.
 template <bool DENSE>
 __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ st, const double *P,
-                                                    const int64_t *__restrict__ cand, PairTable pt,
+                                                    const int64_t *__restrict__ cand, int64_t npairs, PairTable pt,
                                                     const double *__restrict__ V, int64_t ldv,
                                                     double *__restrict__ rc)
 {
     constexpr int D = 8;                                   // k-steps in flight per wave
     __shared__ double red[2][16][16];
+    const int rg = (int)blockIdx.x >> 2, cgp = (int)blockIdx.x & 3;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+    // the epilogue's integrals (wave 0: rows 16 rg + g + 4e, column 16 cgp + r16), their inputs
+    // loaded with the state so that they land under the products; entries past the candidates
+    // (and any index out of range) read pair 0 and are not used
+    double base[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t ci = 0, ri[4] = {0, 0, 0, 0};
+    if (w == 0) {
+        ci = cand[16 * cgp + r16];
+        ci = ci >= 0 && ci < npairs ? ci : 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            ri[e] = cand[16 * rg + g + 4 * e];
+            ri[e] = ri[e] >= 0 && ri[e] < npairs ? ri[e] : 0;
+        }
+    }
     if (spec_idle(st) || st->ncand == 0) return;
     const int64_t k0 = st->k;
     const int nc = st->ncand;
-    const int rg = (int)blockIdx.x >> 2, cgp = (int)blockIdx.x & 3;
     if (16 * rg >= nc || 16 * cgp >= nc) return;           // uniform over the workgroup
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+    // the integrals' inputs, issued before the ring (they land with its first loads); the
+    // integrals themselves are formed after the products
+    double rp[4][5], cp5[5];
+    if (w == 0) {
+        if constexpr (DENSE) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) base[e] = V[ci * ldv + ri[e]];   // V[cand_s][cand_c]
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                rp[e][0] = pt.p[ri[e]];
+                rp[e][1] = pt.Px[ri[e]];
+                rp[e][2] = pt.Py[ri[e]];
+                rp[e][3] = pt.Pz[ri[e]];
+                rp[e][4] = pt.K[ri[e]];
+            }
+            cp5[0] = pt.p[ci];
+            cp5[1] = pt.Px[ci];
+            cp5[2] = pt.Py[ci];
+            cp5[3] = pt.Pz[ci];
+            cp5[4] = pt.K[ci];
+        }
+    }
     const int64_t ks = (k0 + 3) / 4;
     const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
     const int64_t jz = 4 * ks;                             // a zero row of P
@@ -1849,14 +1887,10 @@ __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ 
         for (int e = 0; e < 4; ++e) {
             const int s = 16 * rg + g + 4 * e;
             if (s < nc && c < nc) {
-                const int64_t I = cand[s], q = cand[c];
-                double base;                                   // V[cand_s][cand_c], as the pass forms it
-                if constexpr (DENSE)
-                    base = V[q * ldv + I];
-                else
-                    base = eri_pp(pt.p[I], pt.Px[I], pt.Py[I], pt.Pz[I], pt.K[I], pt.p[q], pt.Px[q], pt.Py[q],
-                                  pt.Pz[q], pt.K[q]);
-                rc[c * CD_NCAND + s] = base - (red[0][g + 4 * e][r16] + red[1][g + 4 * e][r16]);
+                if constexpr (!DENSE)                  // V[cand_s][cand_c], as the pass forms it
+                    base[e] = eri_pp(rp[e][0], rp[e][1], rp[e][2], rp[e][3], rp[e][4], cp5[0], cp5[1], cp5[2],
+                                     cp5[3], cp5[4]);
+                rc[c * CD_NCAND + s] = base[e] - (red[0][g + 4 * e][r16] + red[1][g + 4 * e][r16]);
             }
         }
     }
@@ -1872,9 +1906,10 @@ __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ 
 template <bool W16, bool DENSE, int NG>
 __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int64_t npairs, int64_t k0,
                                                const double *P, double *__restrict__ R, int64_t ldr,
-                                               const PairTable &pt, const double *__restrict__ V,
-                                               int64_t ldv, int ns, const int *csl, const double (*cdat)[CD_SPEC_MAX],
-                                               const int64_t *ccol, double (*red)[CD_SPEC_MAX][CD_TILE])
+                                               const PairTable &pt, const double *__restrict__ V, int64_t ldv,
+                                               const int64_t *__restrict__ cand, int ns, const int (&sl3)[3],
+                                               int *csl, double (*cdat)[CD_SPEC_MAX], int64_t *ccol,
+                                               double (*red)[CD_SPEC_MAX][CD_TILE])
 {
     constexpr int D = CD_PASS_D;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1893,10 +1928,14 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
     bool bon[NG];
 #pragma unroll
     for (int n = 0; n < NG; ++n) {
-        const int col = 16 * n + r16;
-        bon[n] = col < ns;
-        bcol[n] = bon[n] ? csl[col] : 0;
+        bon[n] = 16 * n + r16 < ns;
+        bcol[n] = bon[n] ? sl3[n] : 0;
     }
+    // lane l < 48 of wave 0 owns column l (its slot is sl3[l / 16]): the slot list for the
+    // epilogue, and later the column's candidate data
+    const bool own = threadIdx.x < CD_SPEC_MAX;
+    const int osl = threadIdx.x < ns ? (g == 0 ? sl3[0] : g == 1 ? sl3[1] : sl3[2]) : 0;
+    if (own) csl[threadIdx.x] = osl;
     const int64_t ks = (k0 + 3) / 4;
     const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
     const int64_t jz = 4 * ks;
@@ -1947,6 +1986,20 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
             }
         }
     }
+    // the epilogue's data, loaded under the reduction: the column's candidate (owners), then the
+    // row's pair data
+    const int row = threadIdx.x % CD_TILE;
+    const int64_t I = tile0 + row;
+    const int64_t Ir = min(I, npairs - 1);
+    const int64_t q = own ? cand[osl] : 0;
+    double ip = 0.0, ipx = 0.0, ipy = 0.0, ipz = 0.0, ik = 0.0;
+    if constexpr (!DENSE) {
+        ip = pt.p[Ir];
+        ipx = pt.Px[Ir];
+        ipy = pt.Py[Ir];
+        ipz = pt.Pz[Ir];
+        ik = pt.K[Ir];
+    }
     // (w0 + w2) + (w1 + w3) as in cd_pass_kernel; entry (column c, row) at red[.][c][row ^ c]
     auto put = [&](int slot) {
 #pragma unroll
@@ -1955,8 +2008,8 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
             for (int n = 0; n < NG; ++n)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int c = 16 * n + r16, row = trow(m, g + 4 * e);
-                    red[slot][c][row ^ c] = acc[m][n][e];
+                    const int c = 16 * n + r16, rw = trow(m, g + 4 * e);
+                    red[slot][c][rw ^ c] = acc[m][n][e];
                 }
     };
     auto add = [&](int slot) {
@@ -1966,8 +2019,8 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
             for (int n = 0; n < NG; ++n)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int c = 16 * n + r16, row = trow(m, g + 4 * e);
-                    acc[m][n][e] += red[slot][c][row ^ c];
+                    const int c = 16 * n + r16, rw = trow(m, g + 4 * e);
+                    acc[m][n][e] += red[slot][c][rw ^ c];
                 }
     };
     if (w >= 2) put(w - 2);
@@ -1975,21 +2028,21 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
     if (w < 2) add(w);
     __syncthreads();
     if (w < 2) put(w);
-    __syncthreads();
-    const int row = threadIdx.x % CD_TILE;
-    const int64_t I = tile0 + row;
-    if (I >= npairs) return;
-    double ip = 0.0, ipx = 0.0, ipy = 0.0, ipz = 0.0, ik = 0.0;
-    if constexpr (!DENSE) {
-        ip = pt.p[I];
-        ipx = pt.Px[I];
-        ipy = pt.Py[I];
-        ipz = pt.Pz[I];
-        ik = pt.K[I];
+    if (own) {
+        ccol[threadIdx.x] = q;
+        if constexpr (!DENSE) {
+            cdat[0][threadIdx.x] = pt.p[q];
+            cdat[1][threadIdx.x] = pt.Px[q];
+            cdat[2][threadIdx.x] = pt.Py[q];
+            cdat[3][threadIdx.x] = pt.Pz[q];
+            cdat[4][threadIdx.x] = pt.K[q];
+        }
     }
+    __syncthreads();
+    if (I >= npairs) return;
 #pragma unroll
-    for (int q = 0; q < 16 * NG * CD_TILE / 256; ++q) {
-        const int c = (threadIdx.x + 256 * q) / CD_TILE;        // uniform over the wave
+    for (int qq = 0; qq < 16 * NG * CD_TILE / 256; ++qq) {
+        const int c = (threadIdx.x + 256 * qq) / CD_TILE;        // uniform over the wave
         if (c < ns) {
             double base;
             if constexpr (DENSE)
@@ -2009,34 +2062,24 @@ __global__ __launch_bounds__(256, 3) void cd_pass_cols_kernel(const double *L, i
                                                               const int64_t *__restrict__ cand)
 {
     __shared__ double red[2][CD_SPEC_MAX][CD_TILE];   // 48 KB: three workgroups per CU
-    __shared__ int csl[CD_SPEC_MAX];                  // candidate slot of column j
-    __shared__ double cdat[5][CD_SPEC_MAX];           // its pair data (integrals)
-    __shared__ int64_t ccol[CD_SPEC_MAX];             // its pair index (dense V)
-    if (spec_idle(st)) return;
+    __shared__ double cdat[5][CD_SPEC_MAX];           // column j's pair data (integrals)
+    __shared__ int64_t ccol[CD_SPEC_MAX];             // column j's pair index
+    __shared__ int csl[CD_SPEC_MAX];                  // column j's candidate slot
+    // the state, the record and this lane's three column slots in one round of loads (the
+    // record's slot list has CD_SPEC_MAX entries, those past nspec finite and unused)
+    const int r16 = threadIdx.x & 15;
+    int sl3[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) sl3[n] = so->slot[16 * n + r16];
     const int ns = so->nspec;
-    if (ns <= 0) return;
     const int64_t k0 = so->k0;
-    if (threadIdx.x < CD_SPEC_MAX) {
-        const int j = threadIdx.x;
-        const int sl = j < ns ? so->slot[j] : 0;
-        csl[j] = sl;
-        const int64_t q = cand[sl];
-        ccol[j] = q;
-        if constexpr (!DENSE) {
-            cdat[0][j] = pt.p[q];
-            cdat[1][j] = pt.Px[q];
-            cdat[2][j] = pt.Py[q];
-            cdat[3][j] = pt.Pz[q];
-            cdat[4][j] = pt.K[q];
-        }
-    }
-    __syncthreads();
+    if (spec_idle(st) || ns <= 0) return;
     if (ns <= 16)
-        pass_cols_body<W16, DENSE, 1>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, ns, csl, cdat, ccol, red);
+        pass_cols_body<W16, DENSE, 1>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, csl, cdat, ccol, red);
     else if (ns <= 32)
-        pass_cols_body<W16, DENSE, 2>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, ns, csl, cdat, ccol, red);
+        pass_cols_body<W16, DENSE, 2>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, csl, cdat, ccol, red);
     else
-        pass_cols_body<W16, DENSE, 3>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, ns, csl, cdat, ccol, red);
+        pass_cols_body<W16, DENSE, 3>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, csl, cdat, ccol, red);
 }
 
 __global__ void max_reduce_kernel(int64_t n, const double *__restrict__ x, double *__restrict__ out)
@@ -2292,10 +2335,10 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tcc));
             if (dense)
                 hipLaunchKernelGGL(cd_cc_kernel<true>, dim3(16), dim3(256), 0, ctx->stream, (const CdState *)st,
-                                   (const double *)Pc, (const int64_t *)cand, pt, V, ldv, bf.rc);
+                                   (const double *)Pc, (const int64_t *)cand, npairs, pt, V, ldv, bf.rc);
             else
                 hipLaunchKernelGGL(cd_cc_kernel<false>, dim3(16), dim3(256), 0, ctx->stream, (const CdState *)st,
-                                   (const double *)Pc, (const int64_t *)cand, pt, V, ldv, bf.rc);
+                                   (const double *)Pc, (const int64_t *)cand, npairs, pt, V, ldv, bf.rc);
             CDS_LAUNCHED(ctx);
             hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
                                st, so);

@@ -14,10 +14,11 @@
 // A workgroup owns one pair of 128-row tiles (TR <= TC) of one matrix: off the diagonal it
 // forms Y[TR][TC] and, in the same registers' layout, Y[TC][TR]^T as Q[TR] P[TC]^T (both
 // partners of an element sit in one lane); on the diagonal it forms Y[TR][TR] and reads each
-// partner through an LDS transpose.  Operand slices (128 rows x 128 bytes per stage) go straight
-// from global memory into two LDS stages (global_load_lds_dwordx4), the 16-byte chunks of a row
-// XOR-swizzled so the fragment reads of consecutive rows hit distinct banks; 16 x 16 MFMA blocks
-// entirely past the matrix edge are skipped.  Tasks are ordered so that those sharing their P
+// partner through an LDS transpose.  Operand slices (128 rows x 64 bytes per stage and plane) go
+// straight from global memory into a ring of LDS stages (global_load_lds_dwordx4; four stages of
+// 32 KB in FP64 and FP32, two of 64 KB in split bf16), one barrier per stage, the 16-byte chunks
+// of a row XOR-swizzled so the fragment reads of consecutive rows hit distinct banks; 16 x 16
+// MFMA blocks entirely past the matrix edge are skipped.  Tasks are ordered so that those sharing their P
 // operand slices run at the same time on one XCD.
 //
 // SIGMA mode: each workgroup sums R / d and -R / d^2 over its elements at T trial energies in
@@ -37,33 +38,36 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int FT = 128;                         // tile edge
 constexpr int FNT = 512;                        // threads per workgroup: 8 waves, 2 (rows) x 4 (cols)
-constexpr int SLICE = 16384;                    // one operand slice per stage: 128 rows x 128 bytes
-constexpr int STAGE = 4 * SLICE;                // P[TR], Q[TC], Q[TR], P[TC]
 constexpr int TPITCH = FT + 1;                  // transpose buffer pitch (elements)
 constexpr int DIAG_SLOTS = FT * (FT + 1) / 2;   // residues of a diagonal task
 constexpr int OFF_SLOTS = FT * FT;              // residues of an off-diagonal task
 constexpr int FTT = 8;                          // trial energies per epilogue pass (at most)
-// each of the two stage buffers also holds 64 rows of the diagonal tasks' transposition buffer
-constexpr int LDS_HALF = (STAGE > (FT / 2) * TPITCH * 8) ? STAGE : (FT / 2) * TPITCH * 8;
+// a diagonal task's transposition buffer (after the main loop, over the stage buffers): rows
+// 0..63 at byte 0, rows 64..127 at TR_HALF
+constexpr int TR_HALF = (FT / 2) * TPITCH * 8;
 
 template <int PREC> struct FTr;
+// k per stage, planes, row bytes per plane and stages in the ring: a stage holds four operand
+// slices of 128 rows x RB x PL bytes (P[TR], Q[TC], Q[TR], P[TC]); NB stages of 32 KB (FP64,
+// FP32) keep three stages in flight under the products of the fourth, in the same 128 KB as
+// two stages of 64 KB (split bf16, whose MFMA takes 32 k at once)
 template <> struct FTr<CDS_PREC_FP64> {
     typedef double E;
     typedef double A1;
     typedef doublex4 Acc;
-    static constexpr int KS = 16, PL = 1, RB = 128;   // k per stage, planes, row bytes per plane
+    static constexpr int KS = 8, PL = 1, RB = 64, NB = 4;
 };
 template <> struct FTr<CDS_PREC_FP32> {
     typedef float E;
     typedef float A1;
     typedef floatx4 Acc;
-    static constexpr int KS = 32, PL = 1, RB = 128;
+    static constexpr int KS = 16, PL = 1, RB = 64, NB = 4;
 };
 template <> struct FTr<CDS_PREC_BF16X3> {
     typedef __bf16 E;
     typedef float A1;
     typedef floatx4 Acc;
-    static constexpr int KS = 32, PL = 2, RB = 64;
+    static constexpr int KS = 32, PL = 2, RB = 64, NB = 2;
 };
 
 struct FArgs {
@@ -198,14 +202,18 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
     typedef typename Tr::E E;
     typedef typename Tr::A1 A1;
     typedef typename Tr::Acc Acc;
-    constexpr int KS = Tr::KS, RB = Tr::RB, PL = Tr::PL;
+    constexpr int KS = Tr::KS, RB = Tr::RB, PL = Tr::PL, NB = Tr::NB;
     constexpr int ES = (int)sizeof(E);
     constexpr int RPW = 1024 / RB;              // slice rows per wave load (per plane)
     constexpr int LPR = RB / 16;                // lanes per slice row
+    constexpr int SL = FT * RB * PL;            // one operand slice
+    constexpr int STG = 4 * SL;                 // one stage
+    constexpr int PPS = SL / 1024;              // wave loads per slice
+    constexpr int LDS_ALL = NB * STG > 2 * TR_HALF ? NB * STG : 2 * TR_HALF;
+    static_assert(NB >= 2 && NB <= 4 && PPS * 4 <= 64, "stage ring shape");
 
-    // the two stage buffers (each also holds half of a diagonal task's transposition buffer)
-    __shared__ __align__(16) unsigned char lds0[LDS_HALF];
-    __shared__ __align__(16) unsigned char lds1[LDS_HALF];
+    // the stage ring (after the main loop: a diagonal task's transposition buffer)
+    __shared__ __align__(16) unsigned char lds[LDS_ALL];
     __shared__ double red[FNT / 64][2 * FTT];
     __shared__ double seps[2][FT];
 
@@ -240,15 +248,15 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
     }
 
     // per-lane source of each wave load of a stage (the stage offset is added per stage):
-    // wave load id = wave * 8 + i covers slice id / 16 (0 P[TR], 1 Q[TC], 2 Q[TR], 3 P[TC]),
-    // part id % 16 (plane part / 8 for split bf16)
-    const int nload = diag ? 4 : 8;             // wave loads per wave and stage
+    // wave load id = wave * nload + i covers slice id / PPS (0 P[TR], 1 Q[TC], 2 Q[TR], 3 P[TC]),
+    // part id % PPS (plane part / 8 for split bf16)
+    const int nload = diag ? PPS / 4 : PPS / 2; // wave loads per wave and stage
     const unsigned char *src[8];
     unsigned ldst[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int id = wave * nload + i;
-        const int sl = id >> 4, part = id & 15;
+        const int sl = id / PPS, part = id % PPS;
         const int plane = PL == 2 ? part >> 3 : 0;
         const int rr = (PL == 2 ? (part & 7) : part) * RPW + lane / LPR;
         const int pc = lane % LPR;
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
         const int64_t row = isP ? pb + x : qb + x * qs;
         const unsigned char *base = isP ? (plane ? a.Bsel_lo : a.Bsel) : (plane ? a.Bvo_lo : a.Bvo);
         src[i] = base + (row * a.ldk) * ES + lc * 16;
-        ldst[i] = (unsigned)(sl * SLICE + part * 1024);
+        ldst[i] = (unsigned)(sl * SL + part * 1024);
     }
     auto stage_load = [&](unsigned char *buf, int64_t st) {
         const int64_t koff = st * KS * ES;
@@ -284,7 +292,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
 
     // fragment address of slice sl, slice row rr, logical chunk lc (plane pl)
     auto frag = [&](const unsigned char *buf, int sl, int pl, int rr, int lc) {
-        return buf + sl * SLICE + pl * 8192 + rr * RB + chunk_pos<RB>(lc, rr) * 16;
+        return buf + sl * SL + pl * 8192 + rr * RB + chunk_pos<RB>(lc, rr) * 16;
     };
     // one stage of products: acc1 += P[TR] Q[TC]^T, and off the diagonal acc2 += Q[TR] P[TC]^T.
     // Consecutive MFMAs go to different accumulators (each k slot over all blocks in turn).
@@ -294,7 +302,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
         auto on = [&](int i, int j) { return full || (i < nbr && j < nbc); };
         if constexpr (PREC == CDS_PREC_FP64) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < RB / 64; ++h) {
                 const int lc = g + 4 * h;
                 double2 fa[4], fb[2], ga[4], gb[2];
 #pragma unroll
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
             }
         } else if constexpr (PREC == CDS_PREC_FP32) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < RB / 64; ++h) {
                 const int lc = g + 4 * h;
                 float4 fa[4], fb[2], ga[4], gb[2];
 #pragma unroll
@@ -389,29 +397,52 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
         }
     };
 
-    // main loop: two LDS stages; the next stage's loads run under this stage's products
-    // (unrolled by two: each step reads one fixed buffer and fills the other)
+    // main loop: a ring of NB LDS stages, one barrier per stage.  At stage st the loads of
+    // stages st+1 .. st+NB-2 may still run; after the barrier (every wave's loads of stage st
+    // have landed and every wave is done with stage st-1) the freed buffer takes stage st+NB-1.
+    // With two stages (split bf16) the next stage's loads are issued before the barrier instead,
+    // and a second barrier frees the buffer read (measured faster there).
     auto main_loop = [&](auto OFFc, auto FULLc) {
         constexpr bool off = decltype(OFFc)::value;
-        auto step = [&](unsigned char *cur, unsigned char *nxt, int64_t st) {
-            if (st + 1 < a.ns) {
-                stage_load(nxt, st + 1);              // nxt was freed by the last barrier
-                if (off) wait_vm<8>();                // this wave's loads of stage st have landed
-                else wait_vm<4>();
-            } else {
-                wait_vm<0>();
+        constexpr int NL = off ? PPS / 2 : PPS / 4;   // wave loads per wave and stage
+        const int64_t ns = a.ns;
+        if constexpr (NB == 2) {
+            auto step = [&](unsigned char *cur, unsigned char *nxt, int64_t st) {
+                if (st + 1 < ns) {
+                    stage_load(nxt, st + 1);          // nxt was freed by the last barrier
+                    wait_vm<NL>();                    // this wave's loads of stage st have landed
+                } else {
+                    wait_vm<0>();
+                }
+                __builtin_amdgcn_s_barrier();         // ... and every wave's
+                compute(cur, OFFc, FULLc);
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS reads are done
+                __builtin_amdgcn_s_barrier();         // cur may be refilled
+            };
+            stage_load(lds, 0);
+            step(lds, lds + STG, 0);
+            for (int64_t st = 1; st < ns; st += 2) {
+                step(lds + STG, lds, st);
+                if (st + 1 < ns) step(lds, lds + STG, st + 1);
             }
-            __builtin_amdgcn_s_barrier();             // ... and every wave's
-            compute(cur, OFFc, FULLc);
-            __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0): this wave's LDS reads are done
-            __builtin_amdgcn_s_barrier();             // cur may be refilled
-        };
-        stage_load(lds0, 0);
-        step(lds0, lds1, 0);
-        for (int64_t st = 1; st < a.ns; st += 2) {
-            step(lds1, lds0, st);
-            if (st + 1 < a.ns) step(lds0, lds1, st + 1);
+            return;
         }
+#pragma unroll
+        for (int i = 0; i < NB - 1; ++i)
+            if (i < ns) stage_load(lds + i * STG, i);
+        for (int64_t st = 0; st < ns; ++st) {
+            const int64_t later = min((int64_t)NB - 2, ns - 1 - st);
+            if (later >= 2) wait_vm<2 * NL>();
+            else if (later == 1) wait_vm<NL>();
+            else wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");            // no LDS read moves above the barrier
+            if (st + NB - 1 < ns) stage_load(lds + ((st + NB - 1) % NB) * STG, st + NB - 1);
+            compute(lds + (st % NB) * STG, OFFc, FULLc);
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);           // lgkmcnt(0): this wave's LDS reads are done
+        __builtin_amdgcn_s_barrier();                 // ... and every wave's: the ring is free
+        asm volatile("" ::: "memory");
     };
     typedef std::integral_constant<bool, true> T_;
     typedef std::integral_constant<bool, false> F_;
@@ -426,9 +457,9 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
 
     // epilogue.  Lane element (i, j, e): tile row rl = wr*64 + 16 i + rowmap(g, e), tile column
     // cl = wc*32 + 16 j + r16 (FP64 MFMA rows g + 4e, FP32-accumulating rows 4g + e)
-    // transposition buffer: tile row r at trow(r) (rows 0..63 in lds0, 64..127 in lds1)
+    // transposition buffer: tile row r at trow(r) (rows 0..63 from byte 0, 64..127 from TR_HALF)
     auto trow = [&](int r) {
-        return reinterpret_cast<A1 *>(r < FT / 2 ? lds0 : lds1) + (r & (FT / 2 - 1)) * TPITCH;
+        return reinterpret_cast<A1 *>(lds + (r < FT / 2 ? 0 : TR_HALF)) + (r & (FT / 2 - 1)) * TPITCH;
     };
     if (diag) {
         // partners through LDS: tm[rl][cl] = Y[rl][cl]; the stage buffers are free (last barrier)
@@ -587,7 +618,7 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(FArgs a, const int *__
 
 // ---- host side ---------------------------------------------------------------------------
 
-static int fused_ks(int prec) { return prec == CDS_PREC_FP64 ? 16 : 32; }
+static int fused_ks(int prec) { return prec == CDS_PREC_FP64 ? 8 : (prec == CDS_PREC_FP32 ? 16 : 32); }
 
 bool cds_fused_plan(int prec, int64_t nvec, int64_t ldk, int nmo, int nocc, const void *Bsel, const void *Bvo,
                     const void *Bsel_lo, const void *Bvo_lo, CdsFusedPlan *p)
