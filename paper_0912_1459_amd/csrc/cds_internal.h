@@ -216,10 +216,12 @@ bool cds_fused_plan(int prec, int64_t nvec, int64_t ldk, int nmo, int nocc, cons
 int cds_fused_sigma(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, int nmo, int nocc, int nsc,
                     const int *d_tsel, const void *Bsel, const void *Bvo, const void *Bsel_lo, const void *Bvo_lo,
                     const double *eps, const double *d_omega, int T, double *d_part);
-// pole residues R[nsc][nres] (double for FP64, float otherwise) of the targets d_tsel[0..nsc)
+// pole residues R[nsc][nres] (double for FP64, float otherwise) of the targets d_tsel[0..nsc); with
+// d_part, also the sums at d_omega0[nsc] from the stored residues, d_part[nsc][tpt][2] (the
+// layout of a sweep's partials)
 int cds_fused_residues(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, int nmo, int nocc, int nsc,
                        const int *d_tsel, const void *Bsel, const void *Bvo, const void *Bsel_lo, const void *Bvo_lo,
-                       const double *eps, void *R);
+                       const double *eps, void *R, const double *d_omega0 = nullptr, double *d_part = nullptr);
 // one Newton sweep: d_part[nactive][tpt][2] for the targets d_active at d_omega[target]
 int cds_fused_sweep(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int nmo, int nocc, int nactive,
                     const int *d_active, const double *eps, const double *d_omega, const void *R, double *d_part);

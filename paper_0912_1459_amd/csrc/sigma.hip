@@ -830,9 +830,23 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
     CdsFusedPlan fp;
     const bool fused = cds_fused_plan(prec, nvec, ldk, nmo, nocc, Bsel, Bvo, Slo, Vlo, &fp);
     int64_t nblk_sweep = nblkA + nblkB;
+    void *hp;
+    CDS_CALL(cds_pinned(ctx, (size_t)nsel * (2 * 8 + 8 + 4) + 64, &hp));
+    double *h_out = (double *)hp;
+    double *h_w = h_out + (size_t)nsel * 2;
+    int *h_act = (int *)(h_w + nsel);
+    bool first_done = false;              // the first evaluation came with the residues
     if (mode == CDS_QP_RESIDUES && fused) {
-        // residues formed by the fused contraction (no integrals in HBM), swept per task
+        // residues formed by the fused contraction (no integrals in HBM), swept per task; the
+        // contraction also sums them at the starting energies (the first Newton evaluation)
         CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * fp.nres * res_es, &R));
+        nblk_sweep = fp.tpt;
+        CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * 8, &om));
+        CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsel * nblk_sweep * 2 * 8, &part));
+        CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)nsel * 2 * 8 + (size_t)nsel * 4 + 64, &outd));
+        act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
+        for (int s = 0; s < nsel; ++s) h_w[s] = w[s];
+        CDS_HIP(ctx, hipMemcpyAsync(om, h_w, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
         const int csz = fused_chunk(ctx, sh);
         int *tsel;
         CDS_CALL(target_slots(ctx, nsel, &tsel));
@@ -841,16 +855,13 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
             CdsTimer t;
             CDS_CALL(cds_timer_start(ctx, &t));
             CDS_CALL(cds_fused_residues(ctx, prec, fp, ldk, nmo, nocc, nsc, tsel + s0, Bsel, Bvo, Slo, Vlo, eps,
-                                        (unsigned char *)R + (size_t)s0 * fp.nres * res_es));
+                                        (unsigned char *)R + (size_t)s0 * fp.nres * res_es, (const double *)om + s0,
+                                        (double *)part + (size_t)s0 * nblk_sweep * 2));
             CDS_CALL(cds_timer_stop(ctx, &t, &ctx->stats.t_contract_ms));
             ctx->stats.flops_contract += 2.0 * (double)nvec * nsc * nmo * (double)sh.nvo;
             ctx->stats.n_contract += 1;
         }
-        nblk_sweep = fp.tpt;
-        CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * 8, &om));
-        CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsel * nblk_sweep * 2 * 8, &part));
-        CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)nsel * 2 * 8 + (size_t)nsel * 4 + 64, &outd));
-        act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
+        first_done = true;
     } else if (mode == CDS_QP_RESIDUES) {
         // blocks the fused kernel cannot read: integrals through HBM, then the residue epilogue
         CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * nres * res_es + (size_t)nsel * 4, &R));
@@ -881,44 +892,42 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
         CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)nsel * 2 * 8 + (size_t)nsel * 4 + 64, &outd));
         act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
     }
-    void *hp;
-    CDS_CALL(cds_pinned(ctx, (size_t)nsel * (2 * 8 + 8 + 4) + 64, &hp));
-    double *h_out = (double *)hp;
-    double *h_w = h_out + (size_t)nsel * 2;
-    int *h_act = (int *)(h_w + nsel);
 
     for (int s = 0; s < nsel; ++s) active.push_back(s);
     std::vector<double> out_all((size_t)nsel * 2);
     for (int it = 1; it <= max_iter && !active.empty(); ++it) {
         if (mode == CDS_QP_RESIDUES) {
-            for (int s = 0; s < nsel; ++s) h_w[s] = w[s];
-            for (size_t k = 0; k < active.size(); ++k) h_act[k] = active[k];
-            CDS_HIP(ctx, hipMemcpyAsync(om, h_w, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
-            CDS_HIP(ctx, hipMemcpyAsync(act, h_act, active.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-            if (fused) {
-                CDS_CALL(cds_fused_sweep(ctx, prec, fp, nmo, nocc, (int)active.size(), (const int *)act, eps,
-                                         (const double *)om, R, (double *)part));
-            } else {
-                EpArgs e = {};
-                e.nmo = nmo;
-                e.nocc = nocc;
-                e.nvirt = sh.nvirt;
-                e.nvo = sh.nvo;
-                e.eps = eps;
-                e.omega = (const double *)om;
-                e.T = 1;
-                e.R = R;
-                e.nres = nres;
-                e.offB = (int64_t)sh.nvirt * npairA;
-                e.part = (double *)part;
-                e.nblkA = nblkA;
-                e.nblkB = nblkB;
-                dim3 g((unsigned)(nblkA + nblkB), (unsigned)active.size());
-                if (prec == CDS_PREC_FP64)
-                    hipLaunchKernelGGL(sweep_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
-                else
-                    hipLaunchKernelGGL(sweep_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
-                CDS_LAUNCHED(ctx);
+            // the first evaluation of the fused path came with the residues (all targets active)
+            if (!(first_done && it == 1)) {
+                for (int s = 0; s < nsel; ++s) h_w[s] = w[s];
+                for (size_t k = 0; k < active.size(); ++k) h_act[k] = active[k];
+                CDS_HIP(ctx, hipMemcpyAsync(om, h_w, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
+                CDS_HIP(ctx, hipMemcpyAsync(act, h_act, active.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+                if (fused) {
+                    CDS_CALL(cds_fused_sweep(ctx, prec, fp, nmo, nocc, (int)active.size(), (const int *)act, eps,
+                                             (const double *)om, R, (double *)part));
+                } else {
+                    EpArgs e = {};
+                    e.nmo = nmo;
+                    e.nocc = nocc;
+                    e.nvirt = sh.nvirt;
+                    e.nvo = sh.nvo;
+                    e.eps = eps;
+                    e.omega = (const double *)om;
+                    e.T = 1;
+                    e.R = R;
+                    e.nres = nres;
+                    e.offB = (int64_t)sh.nvirt * npairA;
+                    e.part = (double *)part;
+                    e.nblkA = nblkA;
+                    e.nblkB = nblkB;
+                    dim3 g((unsigned)(nblkA + nblkB), (unsigned)active.size());
+                    if (prec == CDS_PREC_FP64)
+                        hipLaunchKernelGGL(sweep_kernel<double>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
+                    else
+                        hipLaunchKernelGGL(sweep_kernel<float>, g, dim3(EP_NT), 0, ctx->stream, e, (const int *)act);
+                    CDS_LAUNCHED(ctx);
+                }
             }
             int n = (int)active.size() * 2;
             hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)n), dim3(256), 0,

@@ -484,7 +484,11 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
         xt = diag ? (double)trow(cl)[rl] : (double)acc2[i][j][e];
         return gR0 + rl < n && gC0 + cl < n && (!diag || rl <= cl);
     };
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 0 || MODE == 2) {
+        // MODE 2: the residues as in MODE 1 and, from the stored values, the sums at the one trial
+        // energy (the Newton solve's first evaluation, without a sweep over the residues)
+        typedef typename std::conditional<PREC == CDS_PREC_FP64, double, float>::type RT;
+        RT *Rt = reinterpret_cast<RT *>(a.R) + (MODE == 2 ? (int64_t)k.sl * a.nres + residue_offset(a, k) : 0);
         for (int t0 = 0; t0 < a.T; t0 += TT) {
             double w[TT], s0[TT], s1[TT];
 #pragma unroll
@@ -501,7 +505,12 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
                         int rl, cl;
                         double x, xt;
                         if (!elem(i, j, e, rl, cl, x, xt)) continue;
-                        const double R = (diag && rl == cl) ? x * x : 2.0 * (x * x + xt * xt - x * xt);
+                        double R = (diag && rl == cl) ? x * x : 2.0 * (x * x + xt * xt - x * xt);
+                        if constexpr (MODE == 2) {
+                            const RT Rs = (RT)R;
+                            Rt[diag ? diag_slot(rl, cl) : rl * FT + cl] = Rs;
+                            R = (double)Rs;
+                        }
                         const double dd = -seps[0][rl] - seps[1][cl];
 #pragma unroll
                         for (int t = 0; t < TT; ++t) {
@@ -674,6 +683,7 @@ template <int PREC, int MODE>
 static void launch_fused_t(cds_ctx *ctx, const FArgs &a, unsigned nblk, int T)
 {
     if (MODE == 1) hipLaunchKernelGGL((sigma_fused_kernel<PREC, 1, 1>), dim3(nblk), dim3(FNT), 0, ctx->stream, a);
+    else if (MODE == 2) hipLaunchKernelGGL((sigma_fused_kernel<PREC, 2, 1>), dim3(nblk), dim3(FNT), 0, ctx->stream, a);
     else if (T <= 1) hipLaunchKernelGGL((sigma_fused_kernel<PREC, 0, 1>), dim3(nblk), dim3(FNT), 0, ctx->stream, a);
     else if (T <= 2) hipLaunchKernelGGL((sigma_fused_kernel<PREC, 0, 2>), dim3(nblk), dim3(FNT), 0, ctx->stream, a);
     else if (T <= 4) hipLaunchKernelGGL((sigma_fused_kernel<PREC, 0, 4>), dim3(nblk), dim3(FNT), 0, ctx->stream, a);
@@ -705,11 +715,15 @@ int cds_fused_sigma(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, 
 
 int cds_fused_residues(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, int nmo, int nocc, int nsc,
                        const int *d_tsel, const void *Bsel, const void *Bvo, const void *Bsel_lo, const void *Bvo_lo,
-                       const double *eps, void *R)
+                       const double *eps, void *R, const double *d_omega0, double *d_part)
 {
     FArgs a = fused_args(prec, p, ldk, nmo, nocc, nsc, d_tsel, Bsel, Bvo, Bsel_lo, Bvo_lo, eps);
     a.R = R;
-    return launch_fused<1>(ctx, prec, a, 1);
+    if (!d_part) return launch_fused<1>(ctx, prec, a, 1);
+    a.omega = d_omega0;
+    a.T = 1;
+    a.part = d_part;
+    return launch_fused<2>(ctx, prec, a, 1);
 }
 
 int cds_fused_sweep(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int nmo, int nocc, int nactive,
