@@ -480,7 +480,8 @@ def main():
     M = cd.nvec
     traffic = committed_traffic(args.workload)
     cdr = cd_report(st, args.steps, w.npairs, M)
-    cdr["pass"]["traffic"] = traffic.get("cd_pass_kernel")
+    pass_kernel = "cd_pass_cols_kernel" if "cd_pass_cols_kernel" in traffic else "cd_pass_kernel"
+    cdr["pass"]["traffic"] = traffic.get(pass_kernel)
     con = contraction_roofline(st_run, args.prec, traffic)
     t_pass = st["t_cd_pass_ms"]
     if st_run["t_contract_ms"] >= t_pass:
@@ -490,9 +491,9 @@ def main():
         n_pass = max(st["n_cd_pass_launch"], 1)
         avg = t_pass / 1e3 / n_pass
         ach = st["flops_cd_pass_method"] / n_pass / avg / 1e12
-        roofline = {"kernel": "cd_pass_kernel", "bound": "mfma", "achieved": round(ach, 2),
+        roofline = {"kernel": pass_kernel, "bound": "mfma", "achieved": round(ach, 2),
                     "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_TFLOPS, 4),
-                    "traffic": traffic.get("cd_pass_kernel"), "launches": n_pass / args.steps,
+                    "traffic": traffic.get(pass_kernel), "launches": n_pass / args.steps,
                     "avg_launch_us": round(avg * 1e6, 3), "units": cdr["pass"]["units"]}
     phases = {k: round(st_run[k] / args.steps, 3) for k in
               ("t_cd_ms", "t_transform_ms", "t_contract_ms", "t_epilogue_ms", "t_newton_ms")}
