@@ -62,6 +62,7 @@ constexpr int CD_PCHUNK = 1024;         // pivot-row entries staged in LDS per c
 constexpr int CD_AUX_NT = 1024;         // threads of the one-block kernels
 constexpr int CD_NSUP = 64;             // super-tiles of the hierarchical pivot search
 constexpr int CD_NCAND = 64;            // candidate residual columns per look-ahead block
+constexpr int CD_NCAND_L = 128;         // candidates per speculative block on the large path
 constexpr int CD_CG = 8;                 // candidate columns per thread in the column kernels
 constexpr int CD_NCG = CD_NCAND / CD_CG; // column groups (rows of the column grid)
 constexpr int CD_PASS_D = 2;            // k-steps (4 vectors each) in flight per wave in the pass
@@ -599,8 +600,9 @@ __global__ __launch_bounds__(CD_TILE) void tile_stats_kernel(CdBufs b, CdParams 
 // pivot (the vectors made since the block start, D, mask, the candidate list) are issued
 // before the pivot search.
 struct SpecOut;
-// whether candidate slot sl had its residual column formed by the block's pass (defined below)
-__device__ bool spec_formed(const SpecOut *so, int sl);
+// the column of R that the large path's pass formed for candidate slot sl (its speculated step),
+// or -1 (defined below)
+__device__ int spec_column(const SpecOut *so, int sl);
 
 template <int VW, int TB, bool DENSE>
 __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
@@ -648,12 +650,14 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
         d_old = b.D[r][If];
         m_old = b.mask[r][If];
     }
-    // candidate list of the current look-ahead block (CD_NCAND == 64: one per lane of wave 0)
-    int64_t cl = -1;
+    // candidate list of the current look-ahead block (up to 128: two per lane of wave 0; the
+    // list always has room for 128)
+    int64_t cl = -1, cl2 = -1;
     int nc = 0;
     if (bsteps > 0 && threadIdx.x < 64) {
         nc = st->ncand;
         cl = cand[threadIdx.x];
+        cl2 = cand[threadIdx.x + 64];
     }
     if (kdone < k) return;
     Pick pk = cd_pick<CD_NT>(b, r, sr, cp, k, psh);
@@ -671,15 +675,16 @@ __global__ __launch_bounds__(CD_NT) void cd_step_kernel(
     const double sq = sqrt(pk.dp);
     if (threadIdx.x < 64) {
         const unsigned long long hit = __ballot((int)threadIdx.x < nc && cl == p);
+        const unsigned long long hit2 = __ballot((int)threadIdx.x + 64 < nc && cl2 == p);
         if (threadIdx.x == 0) {
-            int sl = hit ? __ffsll((long long)hit) - 1 : -1;
-            // large path (sov set): only the speculated candidates' columns were formed
-            if (sl >= 0 && sov && !spec_formed(sov, sl)) sl = -1;
+            int sl = hit ? __ffsll((long long)hit) - 1 : (hit2 ? 64 + __ffsll((long long)hit2) - 1 : -1);
+            // large path (sov set): R holds the speculated steps' columns only, by step
+            if (sl >= 0 && sov) sl = spec_column(sov, sl);
             sslot = sl;
         }
     }
     __syncthreads();
-    const int slot = sslot;
+    const int slot = sslot;                              // the pivot's column of R, or -1
     // this row's entry of the pivot column (residual from the look-ahead pass on a hit),
     // issued before the pivot-row gather so the two loads overlap
     double cfin = 0.0;
@@ -847,11 +852,12 @@ struct SpecOut {
 // kernels of later blocks then return at once until the host has run one per-step launch.
 __device__ __forceinline__ bool spec_idle(const CdState *st) { return st->done || st->stall; }
 
-__device__ bool spec_formed(const SpecOut *so, int sl)
+__device__ int spec_column(const SpecOut *so, int sl)
 {
-    bool formed = false;
-    for (int j = 0; j < so->nspec; ++j) formed |= so->slot[j] == sl;
-    return formed;
+    int col = -1;
+    for (int j = 0; j < so->nspec; ++j)
+        if (so->slot[j] == sl) col = j;
+    return col;
 }
 
 // steps of the block that stand: those before the first failed check
@@ -1018,18 +1024,6 @@ struct SpecWave {
     }
 };
 
-__device__ __forceinline__ void spec_body(const CdBufs &b, const CdParams &cp, const int64_t *__restrict__ cand,
-                                          const CdState *st, SpecLds &sm, SpecOut &out)
-{
-    SpecWave sw;
-    sw.init(b, cp, cand, st, sm);
-    wave_lds_sync();
-#pragma unroll
-    for (int j = 0; j < CD_SPEC_MAX; ++j) sw.step(j, cp, sm);
-    wave_lds_sync();
-    sw.finish(sm, out);
-}
-
 // copy of the record without viol (which the rows update while the copy may still run)
 __device__ __forceinline__ void spec_publish(const SpecOut &ss, SpecOut *so)
 {
@@ -1039,14 +1033,186 @@ __device__ __forceinline__ void spec_publish(const SpecOut &ss, SpecOut *so)
         if (q != iv) ((int64_t *)so)[q] = ((const int64_t *)&ss)[q];
 }
 
+// The large path's speculative block over CD_NCAND_L = 128 candidates (more candidates keep more
+// steps sure to stand: a block ends 8 steps after its tie threshold meets the largest residual
+// outside the candidates), one wave: lane l holds candidates l and l + 64 (halves h = 0, 1) and
+// their columns of the speculated vectors in registers; the pivot's earlier entries come from
+// its lane (readlane), so the 128 x 128 residual block fits in LDS.  Every candidate takes
+// SpecWave's operations in SpecWave's order.
+struct SpecLds2 {
+    double Rcc[CD_NCAND_L][CD_NCAND_L + 1];   // Rcc[s][c] = R[s][cand_c]
+    int64_t spj[CD_SPEC_MAX];
+    int ssj[CD_SPEC_MAX];
+    double ssq[CD_SPEC_MAX], scm[CD_SPEC_MAX], sth[CD_SPEC_MAX];
+};
+
+struct SpecWave2 {
+    int64_t k0, I[2];
+    int nmax, nspec, stop_at, pj[2];
+    bool have[2], alive;
+    double d[2], dnc;
+    unsigned char m[2];
+    double lc[2][CD_SPEC_MAX];
+
+    __device__ __forceinline__ void init(const CdBufs &b, const CdParams &cp, const int64_t *__restrict__ cand,
+                                         const CdState *st, SpecLds2 &sm)
+    {
+        k0 = st->k;
+        const int r = (int)((k0 - cp.nvec_in) & 1);
+        nmax = (int)min((int64_t)cp.spec_len, cp.max_vec - k0);
+        const int l = threadIdx.x;
+        const int nc = st->ncand;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = l + 64 * h;
+            have[h] = c < nc;
+            I[h] = have[h] ? cand[c] : -1;
+            d[h] = have[h] ? b.D[r][I[h]] : 0.0;
+            m[h] = have[h] ? b.mask[r][I[h]] : 1;
+            pj[h] = -1;
+        }
+        // the candidates' 128 x 128 residual block (compact, from cd_cc_kernel), 64 loads in flight
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u0 = 0; u0 < CD_NCAND_L; u0 += 64) {
+                double v[64];
+#pragma unroll
+                for (int u = 0; u < 64; ++u) v[u] = b.rc[(u0 + u) * CD_NCAND_L + l + 64 * h];
+#pragma unroll
+                for (int u = 0; u < 64; ++u) sm.Rcc[u0 + u][l + 64 * h] = (have[h] && u0 + u < nc) ? v[u] : 0.0;
+            }
+        if (l < CD_SPEC_MAX) {
+            sm.spj[l] = -1;
+            sm.ssj[l] = 0;
+            sm.ssq[l] = sm.scm[l] = sm.sth[l] = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < CD_SPEC_MAX; ++j) lc[0][j] = lc[1][j] = 0.0;
+        nspec = 0;
+        alive = true;                                     // uniform over the wave
+        dnc = st->dnc;
+        stop_at = nmax;
+    }
+
+    __device__ __forceinline__ void step(int j, const CdParams &cp, SpecLds2 &sm)
+    {
+        const int l = threadIdx.x;
+        if (j >= nmax) alive = false;
+        if (!alive) return;
+        bool elig[2];
+        double sql[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            elig[h] = have[h] && m[h] == 0;
+            sql[h] = sqrt(d[h]);                                      // off the serial path
+        }
+        const unsigned long long key = max(elig[0] ? okey(d[0]) : 0ull, elig[1] ? okey(d[1]) : 0ull);
+        const double cmax = okey_max(wave_max_key(key));             // as fmax, on integer keys
+        if (cmax == -INFINITY || cmax <= cp.delta) alive = false;    // termination: per-step path
+        if (!alive) return;
+        const double thr = cmax - tie_window(cmax, cp.tau);
+        if (!(thr > dnc) && j + CD_SPEC_MARGIN < stop_at) stop_at = j + CD_SPEC_MARGIN;
+        if (j >= stop_at) alive = false;
+        if (!alive) return;
+        // pivot: the lowest row index within the tie window; usually one candidate is in it
+        const bool in0 = elig[0] && d[0] >= thr, in1 = elig[1] && d[1] >= thr;
+        const unsigned long long w0 = __ballot(in0), w1 = __ballot(in1);
+        int64_t pm;
+        if (__popcll(w0) + __popcll(w1) == 1) {
+            const bool hi = w1 != 0;
+            const int wl = __ffsll((long long)(hi ? w1 : w0)) - 1;
+            pm = readlane_i64(hi ? I[1] : I[0], wl);
+        } else {
+            pm = wave_min_i64_dpp(min(in0 ? I[0] : INT64_MAX, in1 ? I[1] : INT64_MAX));
+        }
+        if ((w0 | w1) == 0 || pm == INT64_MAX) alive = false;       // non-finite residuals
+        if (!alive) return;
+        const unsigned long long b0 = __ballot(have[0] && I[0] == pm), b1 = __ballot(have[1] && I[1] == pm);
+        const int slot = b0 ? __ffsll((long long)b0) - 1 : 64 + __ffsll((long long)b1) - 1;
+        const bool shi = slot >= 64;
+        const int sl = slot & 63;
+        const double sq = readlane_f64(shi ? sql[1] : sql[0], sl);
+        double c[2] = {sm.Rcc[slot][l], sm.Rcc[slot][l + 64]};
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            const double lp = readlane_f64(shi ? lc[1][i] : lc[0][i], sl);   // L[k0+i][p_j]
+            c[0] = fma(-lc[0][i], lp, c[0]);
+            c[1] = fma(-lc[1][i], lp, c[1]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double lj;
+            if (m[h] == 1) {
+                lj = 0.0;
+            } else if (l + 64 * h == slot) {
+                lj = sq;
+                d[h] = 0.0;
+                m[h] = 1;
+                pj[h] = j;
+            } else {
+                lj = c[h] / sq;
+                d[h] = fma(-lj, lj, d[h]);
+            }
+            lc[h][j] = lj;
+        }
+        if (l == 0) {
+            sm.ssj[j] = slot;
+            sm.ssq[j] = sq;
+            sm.scm[j] = cmax;
+            sm.sth[j] = thr;
+            sm.spj[j] = pm;                   // step j is formed
+        }
+        nspec = j + 1;
+    }
+
+    // the records and lpiv[i][j] = L[k0+i][p_j] (i < j < nspec; 0 elsewhere): the candidate that
+    // became the pivot of step j writes column j from its registers
+    __device__ __forceinline__ void finish(const SpecLds2 &sm, SpecOut &out) const
+    {
+        const int l = threadIdx.x;
+        for (int q = l; q < CD_SPEC_MAX * CD_SPEC_MAX; q += 64) (&out.lpiv[0][0])[q] = 0.0;
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = pj[h];
+            if (jj >= 0) {
+#pragma unroll
+                for (int i = 0; i < CD_SPEC_MAX; ++i)
+                    if (i < jj) out.lpiv[i][jj] = lc[h][i];
+            }
+        }
+        if (l < CD_SPEC_MAX) {
+            out.p[l] = sm.spj[l];
+            out.slot[l] = sm.ssj[l];
+            out.sq[l] = sm.ssq[l];
+            out.cmax[l] = sm.scm[l];
+            out.thr[l] = sm.sth[l];
+        }
+        if (l == 0) {
+            out.nspec = nspec;
+            out.pad = 0;
+            out.k0 = k0;
+        }
+    }
+};
+
 // (the large path: before the pass, which then forms the ns speculated columns in groups of 16)
 __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, const int64_t *__restrict__ cand,
                                                      CdState *st, SpecOut *so)
 {
-    __shared__ SpecLds sm;
+    __shared__ SpecLds2 sm;
     __shared__ SpecOut ss;
     if (spec_idle(st)) return;
-    spec_body(b, cp, cand, st, sm, ss);
+    {
+        SpecWave2 sw;
+        sw.init(b, cp, cand, st, sm);
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < CD_SPEC_MAX; ++j) sw.step(j, cp, sm);
+        wave_lds_sync();
+        sw.finish(sm, ss);
+    }
     wave_lds_sync();
     spec_publish(ss, so);
     if (threadIdx.x == 0) {
@@ -1058,7 +1224,7 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
 }
 
 // every row of the workgroup: the speculated vectors L[k0+j] (same operations as
-// spec_body), the residual at the end of each chunk of CD_SPEC_CHUNK steps (Dbuf[j][I] = D after
+// SpecWave), the residual at the end of each chunk of CD_SPEC_CHUNK steps (Dbuf[j][I] = D after
 // vector j, for j = CD_SPEC_CHUNK - 1, 2 CD_SPEC_CHUNK - 1, ...; the commit replays the steps
 // after the last such checkpoint from L) and the step checks
 __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, const double *__restrict__ R,
@@ -1074,11 +1240,11 @@ __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, c
     double d = ok ? b.D[r][I] : 0.0;
     // right-looking within the row: cv[j] holds R[I][p_j] minus the terms of the vectors made
     // so far; once L_j[I] is known every later cv[j'] takes its term at once.  Each cv[j]
-    // still receives its terms in the order i = 0, 1, ..., j-1 (the order of spec_body),
+    // still receives its terms in the order i = 0, 1, ..., j-1 (the speculative wave's order),
     // but only one fused multiply-add per step stays on the serial path.
     double cv[CD_SPEC_MAX];
 #pragma unroll
-    for (int j = 0; j < CD_SPEC_MAX; ++j) cv[j] = (ok && j < ns) ? R[(int64_t)ss.slot[j] * ldr + I] : 0.0;
+    for (int j = 0; j < CD_SPEC_MAX; ++j) cv[j] = (ok && j < ns) ? R[(int64_t)j * ldr + I] : 0.0;
     // Steps in chunks of CD_SPEC_CHUNK.  After each chunk a wave publishes the checks it saw
     // fail, and it stops once any step before the next chunk has failed anywhere (that read
     // is issued at the chunk's start and may be late, which only delays the stop): the
@@ -1453,21 +1619,26 @@ __device__ int select_top(const unsigned long long (&u)[KPT], int want, unsigned
 }
 
 // Look-ahead block start (one block): candidates = this step's pivot, then the rows with
-// the largest residual diagonals (CD_NCAND - 1 of them).  Those rows lie in the CD_NCAND
-// tiles with the largest tile maxima, so the tiles are selected first (keys from the tile
+// the largest residual diagonals (NC - 1 of them; NC = CD_NCAND, or CD_NCAND_L on the large
+// path).  Those rows lie in the NC tiles with the largest tile maxima, so the tiles are selected first (keys from the tile
 // records), then the rows of those tiles; both selections are exact top-k on the IEEE
 // bits (ties at the boundary by lowest position), deterministic.
-__global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams cp, int r, int sr, int64_t k,
-                                                            CdState *st, int64_t *__restrict__ cand, SpecOut *so)
+// (NT threads, CD_AUX_NT in use: 512 measured far worse for 128 candidates, its 16 tile and 16
+// row keys per thread spilling)
+template <int NC, int NT>
+__global__ __launch_bounds__(NT) void cd_cand_kernel(CdBufs b, CdParams cp, int r, int sr, int64_t k,
+                                                     CdState *st, int64_t *__restrict__ cand, SpecOut *so)
 {
-    constexpr int TK = CD_CAND_MAXTILE / CD_AUX_NT;           // tile keys per thread
-    constexpr int RK = CD_NCAND * CD_TILE / CD_AUX_NT;        // row keys per thread
+    constexpr int TK = CD_CAND_MAXTILE / NT;                  // tile keys per thread
+    constexpr int RK = NC * CD_TILE / NT;                     // row keys per thread
+    static_assert(RK * NT == NC * CD_TILE && TK * NT == CD_CAND_MAXTILE && NC <= 128 && NT <= 1024 && NT > NC,
+                  "candidate selection shape");
     __shared__ PickShared psh;
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_prefix;
     __shared__ int s_need;
-    __shared__ int shs[CD_AUX_NT / 64 + 1];
-    __shared__ int64_t stile[CD_NCAND];
+    __shared__ int shs[NT / 64 + 1];
+    __shared__ int64_t stile[NC];
     __shared__ unsigned long long s_rest;
     if (st->done) return;
     const bool chained = k < 0;                  // speculative block: position from the state
@@ -1483,7 +1654,7 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
     const int nmap = st->nmap;
     if ((int)threadIdx.x < nmap) b.slot[cand[threadIdx.x]] = -1;
     __syncthreads();
-    const Pick pk = cd_pick<CD_AUX_NT>(b, r, sr, cp, k, psh);
+    const Pick pk = cd_pick<NT>(b, r, sr, cp, k, psh);
     if (pk.status != PICK_GO) {                  // the step kernel records the termination
         if (threadIdx.x == 0) {
             st->ncand = 0;                       // gather and pass have nothing to do
@@ -1500,7 +1671,7 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
         const double v = t < b.ntile ? ts[t].mx : 0.0;
         u[e] = v > 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
     }
-    const int ntsel = select_top<CD_AUX_NT, TK>(u, CD_NCAND, hist, &s_prefix, &s_need, shs,
+    const int ntsel = select_top<NT, TK>(u, NC, hist, &s_prefix, &s_need, shs,
                                                  [&](int pos, int id) { stile[pos] = id; }, &s_rest);
     const unsigned long long rest_tile = s_rest;  // largest maximum of a tile not selected
     __syncthreads();
@@ -1518,7 +1689,7 @@ __global__ __launch_bounds__(CD_AUX_NT) void cd_cand_kernel(CdBufs b, CdParams c
             }
         }
     }
-    const int nrow = select_top<CD_AUX_NT, RK>(v, CD_NCAND - 1, hist, &s_prefix, &s_need, shs, [&](int pos, int id) {
+    const int nrow = select_top<NT, RK>(v, NC - 1, hist, &s_prefix, &s_need, shs, [&](int pos, int id) {
         cand[1 + pos] = stile[id / CD_TILE] * CD_TILE + id % CD_TILE;
     }, &s_rest);
     // every eligible row outside the candidates is at most the larger of the two rests (keys
@@ -1563,14 +1734,15 @@ __device__ __forceinline__ void candcol_body(const PairTable &pt, const double *
 
 // P[j][c] = L[j][cand_c], j < k0, c < nc (stride over the entries from block b of nb);
 // rows k0 .. k0 + CD_PASS_ZROWS - 1 are zero (the pass reads them for vectors past k0)
+template <int NC = CD_NCAND>
 __device__ __forceinline__ void gather_body(const double *__restrict__ L, int64_t ldl, int64_t k0, int nc,
                                             const int64_t *__restrict__ cand, double *__restrict__ P, int64_t b,
                                             int64_t nb)
 {
-    const int64_t ne = (k0 + CD_PASS_ZROWS) * CD_NCAND;
+    const int64_t ne = (k0 + CD_PASS_ZROWS) * NC;
     for (int64_t e = b * blockDim.x + threadIdx.x; e < ne; e += nb * blockDim.x) {
-        const int64_t j = e / CD_NCAND;
-        const int c = (int)(e % CD_NCAND);
+        const int64_t j = e / NC;
+        const int c = (int)(e % NC);
         P[e] = (j < k0 && c < nc) ? L[j * ldl + cand[c]] : 0.0;
     }
 }
@@ -1586,11 +1758,12 @@ __global__ void cd_candcol_kernel(PairTable pt, const double *__restrict__ V, in
 }
 
 // the gather alone; k0 < 0: the start of the current speculative block
+template <int NC>
 __global__ void cd_gather_kernel(const double *__restrict__ L, int64_t ldl, int64_t k0, const CdState *__restrict__ st,
                                  const int64_t *__restrict__ cand, double *__restrict__ P)
 {
     if (spec_idle(st) || st->ncand == 0) return;
-    gather_body(L, ldl, k0 < 0 ? st->k : k0, st->ncand, cand, P, blockIdx.x, gridDim.x);
+    gather_body<NC>(L, ldl, k0 < 0 ? st->k : k0, st->ncand, cand, P, blockIdx.x, gridDim.x);
 }
 
 // one launch for both, at the start of the current speculative block (they need only the
@@ -1787,9 +1960,9 @@ __global__ __launch_bounds__(256, 2) void cd_pass_kernel(const double *L, int64_
 // applies to row cand_s, column c: the same f64 MFMA over k-steps of 4 vectors (lane g supplies
 // vector 4s + g), the same four vector ranges accumulated in order, summed (w0 + w2) + (w1 + w3),
 // subtracted from the same integral.  Steps past a range add products with a zero row of P,
-// which change nothing, so the ring depth may differ from the pass's.  16 workgroups, one 16 x 16
-// block each; the speculative block then runs on rc exactly as when the pass wrote it.
-template <bool DENSE>
+// which change nothing, so the ring depth may differ from the pass's.  (NC / 16)^2 workgroups, one
+// 16 x 16 block each; the speculative block then runs on rc exactly as when the pass wrote it.
+template <bool DENSE, int NC>
 __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ st, const double *P,
                                                     const int64_t *__restrict__ cand, int64_t npairs, PairTable pt,
                                                     const double *__restrict__ V, int64_t ldv,
@@ -1797,7 +1970,7 @@ __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ 
 {
     constexpr int D = 8;                                   // k-steps in flight per wave
     __shared__ double red[2][16][16];
-    const int rg = (int)blockIdx.x >> 2, cgp = (int)blockIdx.x & 3;
+    const int rg = (int)blockIdx.x / (NC / 16), cgp = (int)blockIdx.x % (NC / 16);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
     // the epilogue's integrals (wave 0: rows 16 rg + g + 4e, column 16 cgp + r16), their inputs
@@ -1848,8 +2021,8 @@ __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ 
     double a[D], b[D];
     auto load = [&](int64_t s, double &as, double &bs) {
         const int64_t j = s < s1 ? 4 * s + g : jz;
-        as = P[j * CD_NCAND + 16 * rg + r16];
-        bs = P[j * CD_NCAND + 16 * cgp + r16];
+        as = P[j * NC + 16 * rg + r16];
+        bs = P[j * NC + 16 * cgp + r16];
     };
     if (s1 > s0) {
 #pragma unroll
@@ -1890,7 +2063,7 @@ __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ 
                 if constexpr (!DENSE)                  // V[cand_s][cand_c], as the pass forms it
                     base[e] = eri_pp(rp[e][0], rp[e][1], rp[e][2], rp[e][3], rp[e][4], cp5[0], cp5[1], cp5[2],
                                      cp5[3], cp5[4]);
-                rc[c * CD_NCAND + s] = base[e] - (red[0][g + 4 * e][r16] + red[1][g + 4 * e][r16]);
+                rc[c * NC + s] = base[e] - (red[0][g + 4 * e][r16] + red[1][g + 4 * e][r16]);
             }
         }
     }
@@ -1898,7 +2071,7 @@ __global__ __launch_bounds__(256) void cd_cc_kernel(const CdState *__restrict__ 
 
 // Large path, step 3 of a speculative block (after the speculative wave has chosen its ns steps
 // from rc): the pass for the speculated columns only.  Column j < ns is candidate slot_j:
-// R[slot_j][I] = V[I][cand_slot_j] - sum_{j'<k0} L[j'][I] P[j'][slot_j], every entry with the
+// R[j][I] = V[I][cand_slot_j] - sum_{j'<k0} L[j'][I] P[j'][slot_j], every entry with the
 // operations of cd_pass_kernel (same A operand and ring, same vector ranges, same reduction),
 // so the values equal those of the full pass; the rows kernel reads exactly these columns.
 // NG = ceil(ns / 16) column groups of 16; columns past ns read a zero row of P and are not
@@ -1908,7 +2081,7 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
                                                const double *P, double *__restrict__ R, int64_t ldr,
                                                const PairTable &pt, const double *__restrict__ V, int64_t ldv,
                                                const int64_t *__restrict__ cand, int ns, const int (&sl3)[3],
-                                               int *csl, double (*cdat)[CD_SPEC_MAX], int64_t *ccol,
+                                               double (*cdat)[CD_SPEC_MAX], int64_t *ccol,
                                                double (*red)[CD_SPEC_MAX][CD_TILE])
 {
     constexpr int D = CD_PASS_D;
@@ -1931,11 +2104,10 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
         bon[n] = 16 * n + r16 < ns;
         bcol[n] = bon[n] ? sl3[n] : 0;
     }
-    // lane l < 48 of wave 0 owns column l (its slot is sl3[l / 16]): the slot list for the
-    // epilogue, and later the column's candidate data
+    // lane l < 48 of wave 0 owns column l (its slot is sl3[l / 16]): later the column's
+    // candidate data for the epilogue
     const bool own = threadIdx.x < CD_SPEC_MAX;
     const int osl = threadIdx.x < ns ? (g == 0 ? sl3[0] : g == 1 ? sl3[1] : sl3[2]) : 0;
-    if (own) csl[threadIdx.x] = osl;
     const int64_t ks = (k0 + 3) / 4;
     const int64_t s0 = ks * w / 4, s1 = ks * (w + 1) / 4;
     const int64_t jz = 4 * ks;
@@ -1962,7 +2134,7 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
             for (int m = 0; m < 4; ++m) as[m] = L[jl * ldl + rowL[m]];
         }
 #pragma unroll
-        for (int n = 0; n < NG; ++n) bs[n] = P[(bon[n] ? jp : jz) * CD_NCAND + bcol[n]];
+        for (int n = 0; n < NG; ++n) bs[n] = P[(bon[n] ? jp : jz) * CD_NCAND_L + bcol[n]];
     };
     auto trow = [&](int m, int q) { return W16 ? 32 * (m >> 1) + 2 * q + (m & 1) : 16 * m + q; };
     if (k0 > 0) {
@@ -2049,7 +2221,7 @@ __device__ __forceinline__ void pass_cols_body(const double *L, int64_t ldl, int
                 base = V[ccol[c] * ldv + I];
             else
                 base = eri_pp(ip, ipx, ipy, ipz, ik, cdat[0][c], cdat[1][c], cdat[2][c], cdat[3][c], cdat[4][c]);
-            R[(int64_t)csl[c] * ldr + I] = base - (red[0][c][row ^ c] + red[1][c][row ^ c]);
+            R[(int64_t)c * ldr + I] = base - (red[0][c][row ^ c] + red[1][c][row ^ c]);
         }
     }
 }
@@ -2064,7 +2236,6 @@ __global__ __launch_bounds__(256, 3) void cd_pass_cols_kernel(const double *L, i
     __shared__ double red[2][CD_SPEC_MAX][CD_TILE];   // 48 KB: three workgroups per CU
     __shared__ double cdat[5][CD_SPEC_MAX];           // column j's pair data (integrals)
     __shared__ int64_t ccol[CD_SPEC_MAX];             // column j's pair index
-    __shared__ int csl[CD_SPEC_MAX];                  // column j's candidate slot
     // the state, the record and this lane's three column slots in one round of loads (the
     // record's slot list has CD_SPEC_MAX entries, those past nspec finite and unused)
     const int r16 = threadIdx.x & 15;
@@ -2075,11 +2246,11 @@ __global__ __launch_bounds__(256, 3) void cd_pass_cols_kernel(const double *L, i
     const int64_t k0 = so->k0;
     if (spec_idle(st) || ns <= 0) return;
     if (ns <= 16)
-        pass_cols_body<W16, DENSE, 1>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, csl, cdat, ccol, red);
+        pass_cols_body<W16, DENSE, 1>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, cdat, ccol, red);
     else if (ns <= 32)
-        pass_cols_body<W16, DENSE, 2>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, csl, cdat, ccol, red);
+        pass_cols_body<W16, DENSE, 2>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, cdat, ccol, red);
     else
-        pass_cols_body<W16, DENSE, 3>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, csl, cdat, ccol, red);
+        pass_cols_body<W16, DENSE, 3>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, cdat, ccol, red);
 }
 
 __global__ void max_reduce_kernel(int64_t n, const double *__restrict__ x, double *__restrict__ out)
@@ -2208,14 +2379,16 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
 
     // workspace: D copy, ERI diagonal, candidate rows P (max_vec x NCAND), residual columns R
     void *w_part, *w_tile, *w_mask, *w_state;
-    const size_t nP = (size_t)(max_vec + CD_PASS_ZROWS) * CD_NCAND, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
+    // (P and the candidates' block have room for the large path's CD_NCAND_L candidates; R for
+    // CD_NCAND columns: by candidate slot on the small path, by speculated step on the large one)
+    const size_t nP = (size_t)(max_vec + CD_PASS_ZROWS) * CD_NCAND_L, nR = bsteps > 0 ? (size_t)CD_NCAND * ldr : 0;
     const bool spec_on = bsteps > 0 && ctx->cd_speculate;
     const size_t nDb = spec_on ? (size_t)CD_SPEC_MAX * npairs : 0;
     CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR + nDb) * 8 + 256, &w_part));
     CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
     CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)3 * npairs, &w_mask));
-    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND * 8 + sizeof(SpecOut) + 64 +
-                                      (size_t)CD_NCAND * CD_NCAND * 8 + 256, &w_state));
+    CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND_L * 8 + sizeof(SpecOut) + 64 +
+                                      (size_t)CD_NCAND_L * CD_NCAND_L * 8 + 256, &w_state));
     double *D1 = (double *)w_part;
     double *diag = D1 + npairs;
     double *Pc = diag + npairs;
@@ -2238,7 +2411,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     double *dscratch = (double *)(sb + 6 * CD_NSUP);
     CdState *st = (CdState *)w_state;
     int64_t *cand = (int64_t *)(st + 1);
-    SpecOut *so = (SpecOut *)(cand + CD_NCAND);
+    SpecOut *so = (SpecOut *)(cand + CD_NCAND_L);
     bf.slot = (signed char *)(bf.mask[1] + npairs);
     bf.rc = (double *)(((uintptr_t)(so + 1) + 255) & ~(uintptr_t)255);
     double *Dbuf = Rc + nR;
@@ -2323,22 +2496,30 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     const bool lockstep = nlb <= (unsigned)CD_FUSE_MAXBLK && !ctx->cd_large_path;
     const bool early = spec_on && !lockstep;
     auto queue_block = [&]() -> int {
-        hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, 0, 0, (int64_t)-1,
-                           st, cand, so);
+        if (early)
+            hipLaunchKernelGGL((cd_cand_kernel<CD_NCAND_L, CD_AUX_NT>), dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf,
+                               cp, 0, 0, (int64_t)-1, st, cand, so);
+        else
+            hipLaunchKernelGGL((cd_cand_kernel<CD_NCAND, CD_AUX_NT>), dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf,
+                               cp, 0, 0, (int64_t)-1, st, cand, so);
         CDS_LAUNCHED(ctx);
         const dim3 ggrid((unsigned)cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND, 256));
         if (early) {
-            hipLaunchKernelGGL(cd_gather_kernel, ggrid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
+            const dim3 ggl((unsigned)cds_ceil_div((max_vec + CD_PASS_ZROWS) * CD_NCAND_L, 256));
+            hipLaunchKernelGGL(cd_gather_kernel<CD_NCAND_L>, ggl, dim3(256), 0, ctx->stream, (const double *)L, ldl,
                                (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
             CDS_LAUNCHED(ctx);
             CdsTimer tcc;
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tcc));
+            constexpr unsigned ncc = (CD_NCAND_L / 16) * (CD_NCAND_L / 16);
             if (dense)
-                hipLaunchKernelGGL(cd_cc_kernel<true>, dim3(16), dim3(256), 0, ctx->stream, (const CdState *)st,
-                                   (const double *)Pc, (const int64_t *)cand, npairs, pt, V, ldv, bf.rc);
+                hipLaunchKernelGGL((cd_cc_kernel<true, CD_NCAND_L>), dim3(ncc), dim3(256), 0, ctx->stream,
+                                   (const CdState *)st, (const double *)Pc, (const int64_t *)cand, npairs, pt, V, ldv,
+                                   bf.rc);
             else
-                hipLaunchKernelGGL(cd_cc_kernel<false>, dim3(16), dim3(256), 0, ctx->stream, (const CdState *)st,
-                                   (const double *)Pc, (const int64_t *)cand, npairs, pt, V, ldv, bf.rc);
+                hipLaunchKernelGGL((cd_cc_kernel<false, CD_NCAND_L>), dim3(ncc), dim3(256), 0, ctx->stream,
+                                   (const CdState *)st, (const double *)Pc, (const int64_t *)cand, npairs, pt, V, ldv,
+                                   bf.rc);
             CDS_LAUNCHED(ctx);
             hipLaunchKernelGGL(cd_spec_kernel, dim3(1), dim3(64), 0, ctx->stream, bf, cp, (const int64_t *)cand,
                                st, so);
@@ -2383,8 +2564,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                    npairs, (const CdState *)st, (const int64_t *)cand, Rc, ldr, (const double *)L,
                                    ldl, Pc);
             else
-                hipLaunchKernelGGL(cd_gather_kernel, ggrid, dim3(256), 0, ctx->stream, (const double *)L, ldl,
-                                   (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
+                hipLaunchKernelGGL(cd_gather_kernel<CD_NCAND>, ggrid, dim3(256), 0, ctx->stream, (const double *)L,
+                                   ldl, (int64_t)-1, (const CdState *)st, (const int64_t *)cand, Pc);
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tsp, &ctx->stats.t_cd_spec_ms));
             CdsTimer tp;
@@ -2498,11 +2679,11 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                 }
                 k0 = k;
                 next_start = k + bsteps;
-                hipLaunchKernelGGL(cd_cand_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
+                hipLaunchKernelGGL((cd_cand_kernel<CD_NCAND, CD_AUX_NT>), dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, bf, cp, r, sr, k,
                                    st, cand, so);
                 CDS_LAUNCHED(ctx);
                 if (k > 0) {
-                    hipLaunchKernelGGL(cd_gather_kernel, dim3((unsigned)cds_ceil_div((k + CD_PASS_ZROWS) * CD_NCAND, 256)), dim3(256),
+                    hipLaunchKernelGGL(cd_gather_kernel<CD_NCAND>, dim3((unsigned)cds_ceil_div((k + CD_PASS_ZROWS) * CD_NCAND, 256)), dim3(256),
                                        0, ctx->stream, (const double *)L, ldl, k, (const CdState *)st,
                                        (const int64_t *)cand, Pc);
                     CDS_LAUNCHED(ctx);
