@@ -92,8 +92,9 @@ typedef struct cds_stats {
     int64_t n_newton_iter;
     double t_cd_pass_ms;     /* look-ahead pass kernels (with kernel timing on) */
     double bytes_cd_pass;    /* bytes those passes read/write: 8 npairs (k0 + ncol),
-                                ncol = 64 candidates, or on the large path the
-                                block's speculated steps rounded up to 16 */
+                                ncol = 64 candidates, or on the large path (128
+                                candidates) the block's speculated steps rounded
+                                up to 16 */
     int64_t n_cd_pass;       /* look-ahead passes that did work               */
     int64_t n_cd_miss;       /* steps whose pivot was not a look-ahead candidate */
     double flops_cd_pass;    /* nominal pass flops: 2 npairs k0 ncol          */
@@ -134,7 +135,9 @@ int cds_reset_stats(cds_ctx *ctx);
 int cds_set_kernel_timing(cds_ctx *ctx, int32_t on);
 /* Look-ahead of the pivoted Cholesky: every block_steps steps one pass over L
  * forms the residual columns of up to 64 candidate pivots (the next pivot and
- * the largest residual diagonals); steps whose pivot is a candidate then only
+ * the largest residual diagonals; with speculative blocks on problems of more
+ * than 256 x 128 pairs, 128 candidates, of which only the speculated steps'
+ * columns are formed); steps whose pivot is a candidate then only
  * subtract the vectors made since.  0 disables it (each step streams all of L).
  * With speculative blocks on, it also caps their length (at most 48).
  * Default 48; valid range [0, 256]. */

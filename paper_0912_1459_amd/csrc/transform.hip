@@ -424,12 +424,12 @@ struct StreamScope {
 // blocks, once OVL_PIECE vectors are known to be final and not yet queued, the next block's
 // pass is followed (through an event) by a piece of OVL_PIECE of them, so the piece runs in
 // the block's single-workgroup and row-update kernels, where most of the device is idle,
-// rather than beside the passes (on c60, pieces of 112 measured better than 64, 80, 96 and
-// 104, and than batches queued as soon as vectors are final, which slowed the decomposition
-// by 0.65 ms).  Without blocks (per-step launches), the vectors made since the last batch go
-// at each read of the state, at least OVL_MIN of them.
+// rather than beside the passes (pieces of 56: with the large path's shorter decomposition,
+// smaller pieces leave less of the transform after it; batches queued as soon as vectors are
+// final slowed the decomposition).  Without blocks (per-step launches), the vectors made since
+// the last batch go at each read of the state, at least OVL_MIN of them.
 constexpr int64_t OVL_MIN = 128;
-constexpr int64_t OVL_PIECE = 112;
+constexpr int64_t OVL_PIECE = 56;
 constexpr int64_t OVL_CAP = 512;    // batch size the workspace holds
 
 struct Overlap {
