@@ -278,7 +278,8 @@ int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const d
  * one call, the transform overlapped with the decomposition: vectors become
  * final when the decomposition's host loop reads its device state or the word
  * a look-ahead block's commit writes to pinned host memory, and once 112 of
- * them wait, the next block's pass is followed by their transform on a second
+ * them wait (56 on the path with 128 candidates, whose blocks are longer and
+ * fewer), the next block's pass is followed by their transform on a second
  * stream of the library (default priority), which fills the device while the
  * block's single-workgroup kernels run; the remaining vectors follow the last
  * one.  The results are those of

@@ -2545,7 +2545,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                    (const double *)Pc, Rc, ldr, pt, V, ldv, (const int64_t *)cand);
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
-            if (hook && hook->block) CDS_CALL(hook->block(hook->user));
+            if (hook && hook->block) CDS_CALL(hook->block(hook->user, early ? 1 : 0));
         }
         CdsTimer tsp;
         if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
@@ -2588,7 +2588,7 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
                                    (const signed char *)bf.slot, bf.rc, pt, (const int64_t *)cand);
             CDS_LAUNCHED(ctx);
             if (ctx->kernel_timing) CDS_CALL(cds_timer_stop(ctx, &tp, &ctx->stats.t_cd_pass_ms));
-            if (hook && hook->block) CDS_CALL(hook->block(hook->user));
+            if (hook && hook->block) CDS_CALL(hook->block(hook->user, early ? 1 : 0));
             if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
             hipLaunchKernelGGL(cd_lockstep_kernel, dim3(nlb), dim3(64 + CD_LS_ROWS), 0, ctx->stream, bf, cp,
                                (const int64_t *)cand, (const CdState *)st, (const double *)Rc, ldr, L, ldl, Dbuf,

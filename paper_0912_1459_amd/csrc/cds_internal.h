@@ -144,11 +144,12 @@ static inline size_t cds_prec_bytes(int prec) { return prec == CDS_PREC_FP64 ? 8
 // of vectors that are final (no later kernel of the decomposition writes L[0..k) again, and
 // the kernels that wrote them have completed).
 // A non-zero return ends the decomposition with that status.
-// block(user) is called after each look-ahead block's pass has been queued on the caller's
-// stream (may be NULL).
+// block(user, wide) is called after each look-ahead block's pass has been queued on the
+// caller's stream (may be NULL); wide is 1 on the path with the wider candidate set (longer
+// blocks, fewer of them), else 0.
 struct CdHook {
     int (*committed)(void *user, int64_t k);
-    int (*block)(void *user);
+    int (*block)(void *user, int wide);
     void *user;
 };
 // cds_cholesky_sgauss from a fresh start (nvec_in = 0) with a progress hook

@@ -424,12 +424,14 @@ struct StreamScope {
 // blocks, once OVL_PIECE vectors are known to be final and not yet queued, the next block's
 // pass is followed (through an event) by a piece of OVL_PIECE of them, so the piece runs in
 // the block's single-workgroup and row-update kernels, where most of the device is idle,
-// rather than beside the passes (pieces of 56: with the large path's shorter decomposition,
-// smaller pieces leave less of the transform after it; batches queued as soon as vectors are
+// rather than beside the passes (on c60's decomposition, pieces of 112 measured better than 64,
+// 80, 96 and 104; on the path with the wider candidate set, whose blocks are longer and fewer,
+// pieces of 56 leave less of the transform after it; batches queued as soon as vectors are
 // final slowed the decomposition).  Without blocks (per-step launches), the vectors made since
 // the last batch go at each read of the state, at least OVL_MIN of them.
 constexpr int64_t OVL_MIN = 128;
-constexpr int64_t OVL_PIECE = 56;
+constexpr int64_t OVL_PIECE = 112;
+constexpr int64_t OVL_PIECE_WIDE = 56;
 constexpr int64_t OVL_CAP = 512;    // batch size the workspace holds
 
 struct Overlap {
@@ -462,14 +464,15 @@ int overlap_committed(void *user, int64_t k)
 }
 
 // a piece of the final vectors, started on the side stream once the block's pass is done
-int overlap_block(void *user)
+int overlap_block(void *user, int wide)
 {
     Overlap &o = *(Overlap *)user;
     o.gated = true;
-    if (o.kfinal - o.kdone < OVL_PIECE) return CDS_OK;
+    const int64_t piece = wide ? OVL_PIECE_WIDE : OVL_PIECE;
+    if (o.kfinal - o.kdone < piece) return CDS_OK;
     CDS_HIP(o.ctx, hipEventRecord(o.ctx->gate, o.ctx->stream));
     CDS_HIP(o.ctx, hipStreamWaitEvent(o.ctx->stream2, o.ctx->gate, 0));
-    return overlap_queue(o, std::min<int64_t>(o.kfinal, o.kdone + OVL_PIECE));
+    return overlap_queue(o, std::min<int64_t>(o.kfinal, o.kdone + piece));
 }
 
 }  // namespace
