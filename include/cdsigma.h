@@ -304,6 +304,27 @@ int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const double *centr
                                   void *Bvo, int64_t *h_nvec, double *h_dmax, int32_t *h_status);
 
 /*
+ * Layout of the blocks B^K of Eq. (transformation): rows of ldk entries become
+ * rows of ldk_new entries in place, each row keeping its first ldk_new entries
+ * (entries K < ldk_new; the buffer keeps its size and the rest of it is left
+ * unspecified).  For the blocks cds_cholesky_transform_sgauss writes, whose
+ * row stride has to be chosen before the number of vectors is known: the
+ * contraction reads rows of nvec entries faster at a row stride near nvec.
+ * rows: rows of the block (Bsel: nsel * nmo, Bvo: nvirt * nocc), in the
+ * layout cds_transform writes for prec (for CDS_PREC_BF16X3 the hi plane and
+ * the lo plane after it, both re-strided, the lo plane then starting at
+ * rows * ldk_new).  Requires 1 <= ldk_new <= ldk / 2 (each launch then moves
+ * rows whose new places lie below the old ones of the rows it moves, about
+ * log(rows) / log(ldk / ldk_new) launches), rows of ldk and of ldk_new entries
+ * multiples of 16 bytes and B 16-byte aligned (device memory of at least rows
+ * * ldk entries, times two planes for CDS_PREC_BF16X3), else CDS_EINVAL with
+ * nothing written.  Queued on the context's stream; the time counts as
+ * transform time in the statistics.
+ */
+int cds_restride_blocks(cds_ctx *ctx, int32_t prec, int64_t rows, int64_t ldk, int64_t ldk_new,
+                        void *B);
+
+/*
  * Second-order self-energy, Eq. (SE), and its energy derivative at T trial
  * energies per target, with (qi|aj) and (qa|ib) formed from B by Eq. (aomo):
  *   h_sigma[s*T + t]  = Sigma_qq(h_omega[s*T + t]),   q = h_sel[s]

@@ -24,7 +24,7 @@ ERROR_NAMES = {CDS_EINVAL: "EINVAL", CDS_ENOMEM: "ENOMEM", CDS_EDEVICE: "EDEVICE
 EXPORTS = [
     "cds_create", "cds_destroy", "cds_last_error", "cds_get_stats", "cds_reset_stats",
     "cds_set_kernel_timing", "cds_set_cd_lookahead", "cds_set_cd_large_path", "cds_set_cd_speculate", "cds_set_cd_mailbox", "cds_set_transform_fp64", "cds_set_target_chunk", "cds_version", "cds_eri_columns", "cds_cholesky_sgauss", "cds_cholesky_sgauss_subset",
-    "cds_cholesky_dense", "cds_transform", "cds_cholesky_transform_sgauss", "cds_sigma2", "cds_sigma2_noalloc", "cds_qp_solve", "cds_qp_adjoint",
+    "cds_cholesky_dense", "cds_transform", "cds_cholesky_transform_sgauss", "cds_restride_blocks", "cds_sigma2", "cds_sigma2_noalloc", "cds_qp_solve", "cds_qp_adjoint",
     "cds_transform_adjoint", "cds_mp2", "cds_workspace_bytes", "cds_sigma2_matrix", "cds_dyson_solve",
 ]
 
@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
         "cds_transform": (ip, [P, i32, i32, i64, P, i64, P, i32, i32, i32, P, i64, P, P]),
         "cds_cholesky_transform_sgauss": (ip, [P, i32, P, P, d, d, d, i64, P, i64, P, P, i32, P, i32, i32, i32, P,
                                                i64, P, P, P, P, P]),
+        "cds_restride_blocks": (ip, [P, i32, i64, i64, i64, P]),
         "cds_sigma2": (ip, [P, i32, i64, i64, i32, i32, i32, P, P, P, P, i32, P, P, P]),
         "cds_sigma2_noalloc": (ip, [P, i32, i64, i64, i32, i32, i32, P, P, P, P, i32, P, P, P]),
         "cds_qp_solve": (ip, [P, i32, i64, i64, i32, i32, i32, P, P, P, P, P, d, i32, i32, P, P, P, P]),

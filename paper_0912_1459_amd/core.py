@@ -322,7 +322,9 @@ def cholesky_transform(delta: float, *, centres: torch.Tensor, alpha: torch.Tens
 
     The transform of the vectors made so far runs on a second stream while the decomposition
     goes on; the results equal the two calls with ldk = round_up(max_vec, 64).  max_vec must
-    be large enough (there is no growth): CDS_ECAP raises.
+    be large enough (there is no growth): CDS_ECAP raises.  When round_up(nvec, 64) is at most
+    half of that ldk, the blocks are re-strided in place to ldk = round_up(nvec, 64)
+    (cds_restride_blocks), the row stride the contraction reads fastest.
     """
     prec = _prec(prec)
     _dev(centres, torch.float64, "centres")
@@ -353,7 +355,27 @@ def cholesky_transform(delta: float, *, centres: torch.Tensor, alpha: torch.Tens
         _ptr(Bsel), _ptr(Bvo), ctypes.byref(nvec), ctypes.byref(dmax), ctypes.byref(status))
     ctx.check(rc, ok=(A.CDS_OK, A.CDS_ENOTPSD))
     cd = CDResult(Lbuf, piv, D, int(nvec.value), float(dmax.value), int(status.value), np_)
+    ldk_new = round_up(max(cd.nvec, 1), 64)
+    if 2 * ldk_new <= ldk:
+        Bsel = restride_blocks(Bsel, prec, ldk_new, ctx)
+        Bvo = restride_blocks(Bvo, prec, ldk_new, ctx)
+        ldk = ldk_new
     return cd, BBlocks(prec, Bsel, Bvo, cd.nvec, ldk, nmo, nocc, sel)
+
+
+def restride_blocks(B: torch.Tensor, prec, ldk_new: int, ctx: Context | None = None) -> torch.Tensor:
+    """Rows of B (as _alloc_B lays them out) cut to their first ldk_new entries, in place
+    (cds_restride_blocks); returns the view of B's storage in the new layout."""
+    prec = _prec(prec)
+    ldk = B.shape[-1]
+    rows = B.shape[-2]
+    if not (B.is_cuda and B.is_contiguous()):
+        raise ValueError("B must be a contiguous device tensor")
+    ctx = ctx or context(B.device.index or 0)
+    ctx.check(ctx.lib.cds_restride_blocks(ctx.h, prec, rows, ldk, ldk_new, _ptr(B)))
+    n = B.shape[0] * rows * ldk_new if prec == A.PREC_BF16X3 else rows * ldk_new
+    shape = (2, rows, ldk_new) if prec == A.PREC_BF16X3 else (rows, ldk_new)
+    return B.view(-1)[:n].view(shape)
 
 
 def sigma2(B: BBlocks, eps: torch.Tensor, omega: np.ndarray, ctx: Context | None = None):

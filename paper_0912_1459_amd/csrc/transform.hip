@@ -550,6 +550,55 @@ extern "C" int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const do
     return rt != CDS_OK ? rt : rc;
 }
 
+namespace {
+
+// Rows [r0, r1) of a row-major array of 16-byte chunks move from ld16 chunks per row to ldn16,
+// keeping the first ldn16 of each.  The caller sizes the batch so that every destination lies
+// below every source of the batch (r1 ldn16 <= r0 ld16) and only over rows already moved, so
+// its rows move in one launch in any order.
+__global__ __launch_bounds__(256) void restride_kernel(uint4 *B, int64_t r0, int64_t r1, int64_t ld16,
+                                                       int64_t ldn16)
+{
+    const int64_t n = (r1 - r0) * ldn16;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        const int64_t r = r0 + q / ldn16, c = q % ldn16;
+        B[r * ldn16 + c] = B[r * ld16 + c];
+    }
+}
+
+}  // namespace
+
+extern "C" int cds_restride_blocks(cds_ctx *ctx, int32_t prec, int64_t rows, int64_t ldk, int64_t ldk_new, void *B)
+{
+    CDS_CALL(cds_enter(ctx));
+    CDS_REQUIRE(ctx, prec == CDS_PREC_FP64 || prec == CDS_PREC_FP32 || prec == CDS_PREC_BF16X3, "unknown prec %d",
+                (int)prec);
+    CDS_REQUIRE(ctx, rows >= 0, "rows must be >= 0");
+    CDS_REQUIRE(ctx, ldk_new >= 1 && 2 * ldk_new <= ldk, "need 1 <= ldk_new <= ldk / 2 (ldk %lld, ldk_new %lld)",
+                (long long)ldk, (long long)ldk_new);
+    const int64_t es = prec == CDS_PREC_FP64 ? 8 : prec == CDS_PREC_FP32 ? 4 : 2;
+    CDS_REQUIRE(ctx, (ldk * es) % 16 == 0 && (ldk_new * es) % 16 == 0,
+                "rows of ldk and ldk_new entries must be multiples of 16 bytes");
+    if (rows == 0) return CDS_OK;
+    CDS_REQUIRE(ctx, B && ((uintptr_t)B & 15) == 0, "B must be a 16-byte aligned device pointer");
+    // the two bf16 planes are one array of 2 rows rows
+    const int64_t R = prec == CDS_PREC_BF16X3 ? 2 * rows : rows;
+    const int64_t ld16 = ldk * es / 16, ldn16 = ldk_new * es / 16;
+    CdsTimer tm;
+    CDS_CALL(cds_timer_start(ctx, &tm));
+    // row 0 stays; a batch starting at row a can end at a ldk / ldk_new >= 2 a
+    for (int64_t a = 1; a < R;) {
+        const int64_t b = std::min<int64_t>(R, a * ldk / ldk_new);
+        const int64_t nb = std::min<int64_t>(cds_ceil_div((b - a) * ldn16, 256), 8192);
+        hipLaunchKernelGGL(restride_kernel, dim3((unsigned)nb), dim3(256), 0, ctx->stream, (uint4 *)B, a, b, ld16,
+                           ldn16);
+        CDS_LAUNCHED(ctx);
+        a = b;
+    }
+    CDS_CALL(cds_timer_stop(ctx, &tm, &ctx->stats.t_transform_ms));
+    return CDS_OK;
+}
+
 extern "C" int cds_set_transform_fp64(cds_ctx *ctx, int32_t on)
 {
     if (!ctx) return CDS_EINVAL;

@@ -3,7 +3,9 @@
 Its results must equal the decomposition followed by the transform of its vectors, bit for
 bit, in every precision (each vector's blocks do not depend on how the vectors are batched);
 the FP64 blocks also match the oracle's transform (Eq. (transformation)) of the oracle's
-vectors.  A capped run transforms the vectors it made; bad arguments write nothing.
+vectors.  A capped run transforms the vectors it made; bad arguments write nothing.  Blocks
+re-strided in place (cds_restride_blocks, which the binding applies when the row stride is at
+least twice the entries used) keep every entry they keep bit for bit.
 """
 import ctypes
 
@@ -41,7 +43,7 @@ def _inputs(name):
 
 @pytest.mark.parametrize("name,delta,prec", [("plain", 1e-6, "fp64"), ("small_cage", 1e-6, "fp32"),
                                              ("c60", 1e-6, "fp64"), ("c60", 1e-6, "bf16x3"),
-                                             ("c60", 1e-4, "fp32")])
+                                             ("c60", 1e-4, "fp32"), ("c60", 1e-4, "bf16x3")])
 def test_fused_equals_separate_calls(C, name, delta, prec):
     w, centres, alpha, Cm = _inputs(name)
     log(f"fused decomposition + transform {name} delta={delta} {prec}")
@@ -117,3 +119,32 @@ def test_fused_rejects_short_ldk(C):
     assert rc == A.CDS_EINVAL
     assert nvec == -1 and status == -9
     assert torch.all(Bsel == 7.0) and torch.all(Bvo == 7.0) and torch.all(L == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("rows,ldk,ldk_new", [(3001, 640, 64), (1000, 640, 320), (257, 2880, 768), (1, 128, 64)])
+def test_restride_keeps_entries(C, prec, rows, ldk, ldk_new):
+    log(f"restride {prec} rows={rows} ldk={ldk} -> {ldk_new}")
+    g = torch.Generator(device="cuda").manual_seed(rows + ldk)
+    shape = (2, rows, ldk) if prec == "bf16x3" else (rows, ldk)
+    dt = {"fp64": torch.float64, "fp32": torch.float32, "bf16x3": torch.bfloat16}[prec]
+    B = torch.randn(shape, generator=g, device="cuda", dtype=torch.float32).to(dt)
+    want = _bits(B[..., :ldk_new]).clone()
+    out = C.restride_blocks(B, prec, ldk_new)
+    torch.cuda.synchronize()
+    assert out.shape == want.shape and out.data_ptr() == B.data_ptr()
+    assert torch.equal(_bits(out), want)
+
+
+def test_restride_rejects_bad_strides(C):
+    ctx = C.context(0)
+    B = torch.full((100, 640), 7.0, dtype=torch.float64, device="cuda")
+    p = ctypes.c_void_p(B.data_ptr())
+    log("restride: stride not halved, rows not 16-byte multiples, misaligned buffer")
+    assert ctx.lib.cds_restride_blocks(ctx.h, A.PREC_FP64, 100, 640, 321 + 63, p) == A.CDS_EINVAL
+    assert ctx.lib.cds_restride_blocks(ctx.h, A.PREC_FP64, 100, 640, 63, p) == A.CDS_EINVAL
+    assert ctx.lib.cds_restride_blocks(ctx.h, A.PREC_FP32, 100, 640, 2, p) == A.CDS_EINVAL
+    q = ctypes.c_void_p(B.data_ptr() + 8)
+    assert ctx.lib.cds_restride_blocks(ctx.h, A.PREC_FP64, 99, 640, 64, q) == A.CDS_EINVAL
+    torch.cuda.synchronize()
+    assert torch.all(B == 7.0)
