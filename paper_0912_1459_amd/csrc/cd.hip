@@ -1229,7 +1229,8 @@ __global__ __launch_bounds__(64) void cd_spec_kernel(CdBufs b, CdParams cp, cons
 // after the last such checkpoint from L) and the step checks
 __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, const double *__restrict__ R,
                                           int64_t ldr, double *__restrict__ L, int64_t ldl,
-                                          double *__restrict__ Dbuf, SpecOut *so, const SpecOut &ss)
+                                          double *__restrict__ Dbuf, SpecOut *so, const SpecOut &ss,
+                                          const double *__restrict__ lpg)
 {
     const int ns = ss.nspec;
     const int64_t k0 = ss.k0;
@@ -1278,7 +1279,7 @@ __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, c
                 // a pivot row (also the one made now) takes no further values; lpiv[j][j'] =
                 // L_j[p_j'], 0 for j' >= ns
 #pragma clang loop unroll(full)
-                for (int jj = j + 1; jj < CD_SPEC_MAX; ++jj) cv[jj] = fma(-lj, ss.lpiv[j][jj], cv[jj]);
+                for (int jj = j + 1; jj < CD_SPEC_MAX; ++jj) cv[jj] = fma(-lj, lpg[j * CD_SPEC_MAX + jj], cv[jj]);
             }
         }
         // wave OR of the failed checks; new ones are published at once
@@ -1295,25 +1296,30 @@ __device__ __forceinline__ void rows_body(const CdBufs &b, const CdParams &cp, c
 
 __global__ __launch_bounds__(256) void cd_rows_kernel(CdBufs b, CdParams cp, const CdState *st,
                                                       const double *__restrict__ R, int64_t ldr, double *__restrict__ L,
-                                                      int64_t ldl, double *__restrict__ Dbuf, SpecOut *so)
+                                                      int64_t ldl, double *__restrict__ Dbuf, SpecOut *so,
+                                                      const double *__restrict__ lpg)
 {
     __shared__ SpecOut ss;
     if (spec_idle(st)) return;
-    // the record into LDS, every load in flight before the first store
-    constexpr int NW = (int)(sizeof(SpecOut) / 8), NQ = (NW + 255) / 256;
+    // the record up to the pivots' vector entries, and its start step, into LDS (those entries,
+    // wave-uniform operands, come through the scalar cache from lpg)
+    constexpr int NW = (int)(offsetof(SpecOut, lpiv) / 8), NQ = (NW + 255) / 256;
+    constexpr int KW = (int)(offsetof(SpecOut, k0) / 8);
+    static_assert(offsetof(SpecOut, lpiv) % 8 == 0 && offsetof(SpecOut, k0) % 8 == 0, "record words");
     int64_t v[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int q = (int)threadIdx.x + 256 * i;
-        v[i] = q < NW ? ((const int64_t *)so)[q] : 0;
+        v[i] = q < NW ? ((const int64_t *)so)[q] : q == NW ? ((const int64_t *)so)[KW] : 0;
     }
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int q = (int)threadIdx.x + 256 * i;
         if (q < NW) ((int64_t *)&ss)[q] = v[i];
+        else if (q == NW) ((int64_t *)&ss)[KW] = v[i];
     }
     __syncthreads();
-    rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss);
+    rows_body(b, cp, R, ldr, L, ldl, Dbuf, so, ss, lpg);
 }
 
 // One row of the lockstep kernel, left-looking: step j forms L_j[I] = (R[I][p_j] - sum_{i<j}
@@ -2551,7 +2557,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
         if (ctx->kernel_timing) CDS_CALL(cds_timer_start(ctx, &tsp));
         if (early) {
             hipLaunchKernelGGL(cd_rows_kernel, dim3(nrb), dim3(256), 0, ctx->stream, bf, cp, (const CdState *)st,
-                               (const double *)Rc, ldr, L, ldl, Dbuf, so);
+                               (const double *)Rc, ldr, L, ldl, Dbuf, so,
+                               (const double *)((const char *)so + offsetof(SpecOut, lpiv)));
             CDS_LAUNCHED(ctx);
         } else {
             const int64_t cgx = cds_ceil_div(npairs, 256);
