@@ -281,8 +281,10 @@ int cds_transform(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const d
  * them wait (56 on the path with 128 candidates, whose blocks are longer and
  * fewer), the next block's pass is followed by their transform on a second
  * stream of the library (default priority), which fills the device while the
- * block's single-workgroup kernels run; the remaining vectors follow the last
- * one.  The results are those of
+ * block's single-workgroup kernels run; the vectors not yet queued when the
+ * decomposition ends are transformed on the caller's stream, beside the
+ * batches the side stream has not finished (a second set of batch buffers).
+ * The results are those of
  * cds_cholesky_sgauss(..., nvec_in = 0, ...) followed by cds_transform(...,
  * nvec = *h_nvec, ...) with the same arguments, bit for bit (each vector's
  * blocks do not depend on how the vectors are batched), over the entries K <

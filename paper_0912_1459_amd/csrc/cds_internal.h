@@ -42,6 +42,9 @@ enum CdsSlot {
     WS_AD_T2,
     WS_AD_T3,
     WS_SG_TSEL,     // target slots of the fused self-energy launches
+    WS_TR_UNPACK2,  // second set of transform batch buffers (the overlapped call's last
+    WS_TR_T2,       // vectors, on the caller's stream beside the side stream's batches)
+    WS_TR_B2,
     WS_SLOTS
 };
 
@@ -71,6 +74,7 @@ struct cds_ctx {
     hipStream_t stream2 = nullptr;   // side stream (default priority) of the overlapped transform
     hipEvent_t join = nullptr;       // orders stream2 after / before the caller's stream
     hipEvent_t gate = nullptr;       // orders a stream2 batch after a point of the caller's stream
+    hipEvent_t trset = nullptr;      // the overlapped transform's coefficient copies are made
     uint64_t *mail = nullptr;        // coherent pinned word the Cholesky commits write (host address)
     uint64_t *mail_dev = nullptr;    // the same word's device address
     bool mail_off = false;           // 1: the word did not follow the state (state read after every batch)

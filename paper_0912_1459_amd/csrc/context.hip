@@ -143,6 +143,7 @@ void cds_destroy(cds_ctx *ctx)
     }
     if (ctx->join) (void)hipEventDestroy(ctx->join);
     if (ctx->gate) (void)hipEventDestroy(ctx->gate);
+    if (ctx->trset) (void)hipEventDestroy(ctx->trset);
     for (auto &t : ctx->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);

@@ -214,6 +214,21 @@ int tr_check(cds_ctx *ctx, int32_t prec, int32_t nbf, int64_t nvec, const double
 }
 
 // sizes and workspace for batches of at most max(1, min(kb_cap, adaptive size)) vectors
+// the buffers of one batch (unpacked L^K, T and its split planes, the products) from three slots
+int tr_alloc_batch(cds_ctx *ctx, TrPlan &p, CdsSlot slu, CdsSlot st, CdsSlot sb)
+{
+    const size_t es = wsize(p.wp);
+    const int64_t nLu = (int64_t)p.kbatch * p.nbf * p.np_;
+    CDS_CALL(cds_ws(ctx, slu, (size_t)nLu * es, &p.wlu));
+    const int64_t nT = (int64_t)p.kbatch * p.nx * p.np_;
+    CDS_CALL(cds_ws(ctx, st, (size_t)nT * es * (p.wp == CDS_PREC_BF16X3 ? 2 : 1), &p.wt));
+    CDS_CALL(cds_ws(ctx, sb, (size_t)p.kbatch * p.nrows * (p.wp == CDS_PREC_FP64 ? 8 : 4), &p.wb));
+    // T: working float output, and (bf16) its two planes after it
+    p.Tf = (float *)p.wt;
+    p.Ts = (__bf16 *)((unsigned char *)p.wt + (size_t)nT * 4);
+    return CDS_OK;
+}
+
 int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L, int64_t ldl, const double *C,
              int32_t nmo, int32_t nocc, int32_t nsel, const int32_t *h_sel, int64_t ldk, void *Bsel, void *Bvo,
              int64_t kb_cap)
@@ -271,11 +286,7 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     void *wcx;
     const int64_t nCt = (int64_t)nmo * p.np_, nCX = (int64_t)p.nx * p.np_;
     CDS_CALL(cds_ws(ctx, WS_TR_CX, (size_t)(nCt + nCX) * es + 256 + nsel * 4, &wcx));
-    const int64_t nLu = (int64_t)p.kbatch * nbf * p.np_;
-    CDS_CALL(cds_ws(ctx, WS_TR_UNPACK, (size_t)nLu * es, &p.wlu));
-    const int64_t nT = (int64_t)p.kbatch * p.nx * p.np_;
-    CDS_CALL(cds_ws(ctx, WS_TR_T, (size_t)nT * es * (p.wp == CDS_PREC_BF16X3 ? 2 : 1), &p.wt));
-    CDS_CALL(cds_ws(ctx, WS_TR_B, (size_t)p.kbatch * p.nrows * (p.wp == CDS_PREC_FP64 ? 8 : 4), &p.wb));
+    CDS_CALL(tr_alloc_batch(ctx, p, WS_TR_UNPACK, WS_TR_T, WS_TR_B));
     p.Ct = (unsigned char *)wcx;
     p.CX = p.Ct + nCt * es;
     p.dext = (int32_t *)(p.CX + ((nCX * es + 255) / 256) * 256);
@@ -283,9 +294,22 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     // plane follows its hi plane inside the same byte range
     p.planeCt = nCt;
     p.planeCX = nCX;
-    // T: working float output, and (bf16) its two planes after it
-    p.Tf = (float *)p.wt;
-    p.Ts = (__bf16 *)((unsigned char *)p.wt + (size_t)nT * 4);
+    return CDS_OK;
+}
+
+// the K padding [nbf, np_) of a batch buffer set's T reads as 0 (the first GEMM writes columns
+// < nbf only)
+int tr_zero_tpad(cds_ctx *ctx, const TrPlan &p)
+{
+    if (p.np_ > p.nbf) {
+        const size_t tes0 = (p.wp == CDS_PREC_FP64) ? 8 : (p.wp == CDS_PREC_FP32 ? 4 : 2);
+        unsigned char *tb = (p.wp == CDS_PREC_BF16X3) ? (unsigned char *)p.Ts : (unsigned char *)p.wt;
+        const int64_t trows = (int64_t)p.kbatch * p.nx * (p.wp == CDS_PREC_BF16X3 ? 2 : 1);   // both planes
+        const int64_t nz = trows * (int64_t)((p.np_ - p.nbf) * tes0 / 2);
+        hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)cds_ceil_div(nz, 256)), dim3(256), 0, ctx->stream, tb,
+                           trows, (int64_t)p.np_ * (int64_t)tes0, (int)(p.nbf * tes0), (int)(p.np_ * tes0));
+        CDS_LAUNCHED(ctx);
+    }
     return CDS_OK;
 }
 
@@ -301,17 +325,7 @@ int tr_setup(cds_ctx *ctx, const TrPlan &p)
                            p.planeCt, p.planeCX);
         CDS_LAUNCHED(ctx);
     }
-    // the first GEMM writes columns < nbf of T; the K padding [nbf, np_) must read as 0
-    if (p.np_ > p.nbf) {
-        const size_t tes0 = (p.wp == CDS_PREC_FP64) ? 8 : (p.wp == CDS_PREC_FP32 ? 4 : 2);
-        unsigned char *tb = (p.wp == CDS_PREC_BF16X3) ? (unsigned char *)p.Ts : (unsigned char *)p.wt;
-        const int64_t trows = (int64_t)p.kbatch * p.nx * (p.wp == CDS_PREC_BF16X3 ? 2 : 1);   // both planes
-        const int64_t nz = trows * (int64_t)((p.np_ - p.nbf) * tes0 / 2);
-        hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)cds_ceil_div(nz, 256)), dim3(256), 0, ctx->stream, tb,
-                           trows, (int64_t)p.np_ * (int64_t)tes0, (int)(p.nbf * tes0), (int)(p.np_ * tes0));
-        CDS_LAUNCHED(ctx);
-    }
-    return CDS_OK;
+    return tr_zero_tpad(ctx, p);
 }
 
 // zero entries K in [nvec, kend) of both output blocks, kend <= ldk
@@ -448,6 +462,7 @@ int overlap_queue(Overlap &o, int64_t k1)
     StreamScope sc(o.ctx, o.ctx->stream2);
     if (!o.started) {
         CDS_CALL(tr_setup(o.ctx, *o.p));
+        CDS_HIP(o.ctx, hipEventRecord(o.ctx->trset, o.ctx->stream));
         o.started = true;
     }
     CDS_CALL(tr_range(o.ctx, *o.p, o.kdone, k1));
@@ -509,11 +524,14 @@ extern "C" int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const do
         CDS_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking));
         CDS_HIP(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
         CDS_HIP(ctx, hipEventCreateWithFlags(&ctx->gate, hipEventDisableTiming));
+        CDS_HIP(ctx, hipEventCreateWithFlags(&ctx->trset, hipEventDisableTiming));
     }
     // everything the side stream uses is allocated before any work is queued
     TrPlan p;
     CDS_CALL(tr_alloc(ctx, p, prec, nbf, L, ldl, C, nmo, nocc, nsel, h_sel, ldk, Bsel, Bvo,
                       std::min<int64_t>(OVL_CAP, max_vec)));
+    TrPlan p2 = p;                  // the last vectors' batch buffers (the caller's stream)
+    CDS_CALL(tr_alloc_batch(ctx, p2, WS_TR_UNPACK2, WS_TR_T2, WS_TR_B2));
     // the side stream starts after everything queued before this call
     CDS_HIP(ctx, hipEventRecord(ctx->join, ctx->stream));
     CDS_HIP(ctx, hipStreamWaitEvent(ctx->stream2, ctx->join, 0));
@@ -529,11 +547,21 @@ extern "C" int cds_cholesky_transform_sgauss(cds_ctx *ctx, int32_t nbf, const do
     const bool timed = rc == CDS_OK || rc == CDS_ECAP || rc == CDS_ENOTPSD;
     if (timed) rt = cds_timer_start(ctx, &tm);
     if (rt == CDS_OK && timed) {
-        // the rest of the vectors, on the side stream after the earlier batches
-        StreamScope sc(ctx, ctx->stream2);
         const std::string err = ctx->err;
-        if (!ov.started) rt = tr_setup(ctx, p);
-        if (rt == CDS_OK && *h_nvec > ov.kdone) rt = tr_range(ctx, p, ov.kdone, *h_nvec);
+        if (ov.started && *h_nvec > ov.kdone) {
+            // the rest of the vectors on the caller's stream, with a second set of batch
+            // buffers, beside the batches the side stream has not finished (they write other
+            // entries K of the blocks); the coefficient copies are the side stream's
+            rt = tr_zero_tpad(ctx, p2);
+            if (rt == CDS_OK && hipStreamWaitEvent(ctx->stream, ctx->trset, 0) != hipSuccess)
+                rt = cds_fail(ctx, CDS_EDEVICE, "hipStreamWaitEvent failed");
+            if (rt == CDS_OK) rt = tr_range(ctx, p2, ov.kdone, *h_nvec);
+        } else {
+            // no batch queued yet: everything on the side stream
+            StreamScope sc(ctx, ctx->stream2);
+            if (!ov.started) rt = tr_setup(ctx, p);
+            if (rt == CDS_OK && *h_nvec > ov.kdone) rt = tr_range(ctx, p, ov.kdone, *h_nvec);
+        }
         // ldk was sized for max_vec: only the entries up to the next multiple of 64, the last any
         // consumer of the blocks reads, are cleared
         if (rt == CDS_OK) rt = tr_pad(ctx, p, *h_nvec, std::min<int64_t>(p.ldk, cds_ceil_div(*h_nvec, 64) * 64));
