@@ -167,6 +167,29 @@ __global__ __launch_bounds__(256) void copy_out_kernel(const W *__restrict__ Wb,
     }
 }
 
+// The same copy from the single product W[r][x * nkb + kb] = sum_mu Ct[r][mu] T[x][kb][mu] over
+// every MO r and every row x of T: B_vo[a][i] from row nocc + a, column i; B_sel[s][r] from row r,
+// column xs[s].
+__global__ __launch_bounds__(256) void copy_out_all_kernel(const double *__restrict__ Wb, int64_t nvo, int nmo,
+                                                           int nocc, int nx, int nsel, const int32_t *__restrict__ xs,
+                                                           int nkb, int64_t k0, void *Bvo, void *Bsel, int64_t ldk,
+                                                           int prec, int64_t plane_vo, int64_t plane_sel)
+{
+    const int64_t nrows = nvo + (int64_t)nsel * nmo;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * nkb) return;
+    const int64_t row = t / nkb;
+    const int kb = (int)(t - row * nkb);
+    if (row < nvo) {
+        const int64_t a = row / nocc, i = row - a * nocc;
+        put(Bvo, prec, row * ldk + k0 + kb, plane_vo, Wb[((nocc + a) * nx + i) * nkb + kb]);
+    } else {
+        const int64_t rs = row - nvo;
+        const int sidx = (int)(rs / nmo), r = (int)(rs - (int64_t)sidx * nmo);
+        put(Bsel, prec, rs * ldk + k0 + kb, plane_sel, Wb[((int64_t)r * nx + xs[sidx]) * nkb + kb]);
+    }
+}
+
 __global__ void zero_pad_kernel(int64_t nrows, int64_t ldk, int64_t nvec, int64_t kend, void *B, int prec,
                                 int64_t plane)
 {
@@ -189,7 +212,8 @@ struct TrPlan {
     std::vector<int> xs;                      // row of T (x) of each selected orbital
     std::vector<std::array<int, 3>> runs;     // (s0, count, x0): consecutive s with consecutive x
     unsigned char *Ct, *CX;
-    int32_t *dext;
+    int32_t *dext, *dxs;
+    bool comb;                                // one product over all MOs and all rows of T
     void *wlu, *wt, *wb;
     float *Tf;
     __bf16 *Ts;
@@ -222,7 +246,8 @@ int tr_alloc_batch(cds_ctx *ctx, TrPlan &p, CdsSlot slu, CdsSlot st, CdsSlot sb)
     CDS_CALL(cds_ws(ctx, slu, (size_t)nLu * es, &p.wlu));
     const int64_t nT = (int64_t)p.kbatch * p.nx * p.np_;
     CDS_CALL(cds_ws(ctx, st, (size_t)nT * es * (p.wp == CDS_PREC_BF16X3 ? 2 : 1), &p.wt));
-    CDS_CALL(cds_ws(ctx, sb, (size_t)p.kbatch * p.nrows * (p.wp == CDS_PREC_FP64 ? 8 : 4), &p.wb));
+    const int64_t wrows = p.comb ? (int64_t)p.nmo * p.nx : p.nrows;
+    CDS_CALL(cds_ws(ctx, sb, (size_t)p.kbatch * wrows * (p.wp == CDS_PREC_FP64 ? 8 : 4), &p.wb));
     // T: working float output, and (bf16) its two planes after it
     p.Tf = (float *)p.wt;
     p.Ts = (__bf16 *)((unsigned char *)p.wt + (size_t)nT * 4);
@@ -274,6 +299,9 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     p.Bvo = Bvo;
     // working precision of the GEMMs; the output is rounded to `prec` in the last pass
     p.wp = ctx->transform_fp64 ? CDS_PREC_FP64 : prec;
+    // FP64: one product Ct^T T over every MO and every row of T (one launch that fills the chip)
+    // when it computes at most 15 % more than the two blocks need
+    p.comb = p.wp == CDS_PREC_FP64 && (int64_t)nmo * p.nx * 100 <= p.nrows * 115;
     const size_t es = wsize(p.wp);
     // batch: enough 128 x 128 tiles of the virtual-occupied product per launch to fill the
     // chip (that product has one tile group of nvirt x nocc per vector)
@@ -285,11 +313,12 @@ int tr_alloc(cds_ctx *ctx, TrPlan &p, int32_t prec, int32_t nbf, const double *L
     // workspace: Ct + CX (+ sel list), Lu batch, T batch (+ split copy), Bk batch
     void *wcx;
     const int64_t nCt = (int64_t)nmo * p.np_, nCX = (int64_t)p.nx * p.np_;
-    CDS_CALL(cds_ws(ctx, WS_TR_CX, (size_t)(nCt + nCX) * es + 256 + nsel * 4, &wcx));
+    CDS_CALL(cds_ws(ctx, WS_TR_CX, (size_t)(nCt + nCX) * es + 256 + nsel * 8, &wcx));
     CDS_CALL(tr_alloc_batch(ctx, p, WS_TR_UNPACK, WS_TR_T, WS_TR_B));
     p.Ct = (unsigned char *)wcx;
     p.CX = p.Ct + nCt * es;
     p.dext = (int32_t *)(p.CX + ((nCX * es + 255) / 256) * 256);
+    p.dxs = p.dext + nsel;
     // for bf16 the hi and lo planes of Ct / CX take 2 x 2 bytes = es per element: each lo
     // plane follows its hi plane inside the same byte range
     p.planeCt = nCt;
@@ -318,6 +347,8 @@ int tr_setup(cds_ctx *ctx, const TrPlan &p)
 {
     if (!p.ext.empty())
         CDS_HIP(ctx, hipMemcpyAsync(p.dext, p.ext.data(), p.ext.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    if (p.comb)
+        CDS_HIP(ctx, hipMemcpyAsync(p.dxs, p.xs.data(), p.xs.size() * 4, hipMemcpyHostToDevice, ctx->stream));
     {
         int64_t n = (int64_t)(p.nmo + p.nx) * p.np_;
         hipLaunchKernelGGL(coef_kernel, dim3((unsigned)cds_ceil_div(n, 256)), dim3(256), 0, ctx->stream,
@@ -375,6 +406,24 @@ int tr_batch(cds_ctx *ctx, const TrPlan &p, int64_t k0, int nkb)
     const int64_t planeT = (int64_t)nkb * nx * np_;
     const size_t tes = (p.wp == CDS_PREC_FP64) ? 8 : (p.wp == CDS_PREC_FP32 ? 4 : 2);
     const size_t wes = (p.wp == CDS_PREC_FP64) ? 8 : 4;
+    if (p.comb) {
+        // W[r][x*nkb + kb] = sum_mu Ct[r][mu] T[x][kb][mu] for every MO r and row x of T: both
+        // blocks from one launch (each entry the same sum as in the two products below)
+        GemmDesc gc = {};
+        gc.M = nmo; gc.N = (int64_t)nx * nkb; gc.K = np_; gc.batch = 1;
+        gc.A = p.Ct; gc.sAm = np_; gc.sAk = 1;
+        gc.B = Tout; gc.sBn = np_; gc.sBk = 1;
+        gc.C = p.wb; gc.sCm = (int64_t)nx * nkb; gc.sCn = 1;
+        gc.alpha = 1.0; gc.beta = 0.0;
+        gc.big = nmo >= 512 ? 2 : 1;
+        CDS_CALL(cds_gemm_ex(ctx, gprec, gc, nullptr, nullptr));
+        const int64_t nel = p.nrows * nkb;
+        hipLaunchKernelGGL(copy_out_all_kernel, dim3((unsigned)cds_ceil_div(nel, 256)), dim3(256), 0, ctx->stream,
+                           (const double *)p.wb, p.nvo, nmo, nocc, nx, nsel, (const int32_t *)p.dxs, nkb, k0, p.Bvo,
+                           p.Bsel, p.ldk, p.prec, p.nvo * p.ldk, p.nselr * p.ldk);
+        CDS_LAUNCHED(ctx);
+        return CDS_OK;
+    }
     // the 256 x 256 split-bf16 tiles are chosen from the per-vector shapes only, so that a
     // vector's blocks do not depend on the batching
     // W[a][i*nkb + kb] = sum_mu Ct[nocc+a][mu] T[i][kb][mu]
