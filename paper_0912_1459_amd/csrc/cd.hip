@@ -2259,6 +2259,18 @@ __global__ __launch_bounds__(256, 3) void cd_pass_cols_kernel(const double *L, i
         pass_cols_body<W16, DENSE, 3>(L, ldl, npairs, k0, P, R, ldr, pt, V, ldv, cand, ns, sl3, cdat, ccol, red);
 }
 
+// block maxima of x over a grid-stride range (the first pass of the largest ERI diagonal)
+constexpr int CD_MAXPART = 512;          // blocks of the first pass
+__global__ __launch_bounds__(256) void max_part_kernel(int64_t n, const double *__restrict__ x,
+                                                       double *__restrict__ part)
+{
+    __shared__ double sh[256 / 64];
+    double m = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = fmax(m, x[i]);
+    m = block_max<256>(m, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
 __global__ void max_reduce_kernel(int64_t n, const double *__restrict__ x, double *__restrict__ out)
 {
     __shared__ double sh[CD_AUX_NT / 64];
@@ -2391,7 +2403,8 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     const bool spec_on = bsteps > 0 && ctx->cd_speculate;
     const size_t nDb = spec_on ? (size_t)CD_SPEC_MAX * npairs : 0;
     CDS_CALL(cds_ws(ctx, WS_CD_PART, ((size_t)2 * npairs + (bsteps > 0 ? nP : 0) + nR + nDb) * 8 + 256, &w_part));
-    CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64, &w_tile));
+    CDS_CALL(cds_ws(ctx, WS_CD_TILE, (size_t)2 * ntile * sizeof(TileStat) + (size_t)6 * CD_NSUP * 8 + 64 +
+                                     (size_t)CD_MAXPART * 8, &w_tile));
     CDS_CALL(cds_ws(ctx, WS_CD_MASK, (size_t)3 * npairs, &w_mask));
     CDS_CALL(cds_ws(ctx, WS_CD_STATE, sizeof(CdState) + CD_NCAND_L * 8 + sizeof(SpecOut) + 64 +
                                       (size_t)CD_NCAND_L * CD_NCAND_L * 8 + 256, &w_state));
@@ -2428,8 +2441,15 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     else
         hipLaunchKernelGGL(eri_diag_kernel, dim3(nb), dim3(256), 0, ctx->stream, npairs, pt, diag);
     CDS_LAUNCHED(ctx);
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, npairs, diag, dscratch);
-    CDS_LAUNCHED(ctx);
+    {
+        // two passes: block maxima over the whole chip, then one block over those
+        double *dpart = dscratch + 8;
+        const int64_t nbm = std::min<int64_t>(CD_MAXPART, cds_ceil_div(npairs, 256));
+        hipLaunchKernelGGL(max_part_kernel, dim3((unsigned)nbm), dim3(256), 0, ctx->stream, npairs, diag, dpart);
+        hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(CD_AUX_NT), 0, ctx->stream, nbm, (const double *)dpart,
+                           dscratch);
+        CDS_LAUNCHED(ctx);
+    }
     void *hp;
     CDS_CALL(cds_pinned(ctx, 256, &hp));
     CDS_HIP(ctx, hipMemcpyAsync(hp, dscratch, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
