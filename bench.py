@@ -151,8 +151,11 @@ class Runner:
         """(ms per step, library stats of the timed steps, last step's results); HIP events on
         the library's stream bracket the K steps."""
         torch = self.torch
+        # the warm-up keeps each step's results alive while the next one runs, as the timed loop
+        # does, so that the allocator already holds both sets of buffers when timing starts
+        res = None
         for _ in range(warmup):
-            self.step(prec)
+            res = self.step(prec)
         torch.cuda.synchronize()
         self.ctx.reset_stats()
         ev0 = torch.cuda.Event(enable_timing=True)
