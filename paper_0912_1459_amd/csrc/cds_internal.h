@@ -227,6 +227,8 @@ int cds_fused_sigma(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, 
 int cds_fused_residues(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ldk, int nmo, int nocc, int nsc,
                        const int *d_tsel, const void *Bsel, const void *Bvo, const void *Bsel_lo, const void *Bvo_lo,
                        const double *eps, void *R, const double *d_omega0 = nullptr, double *d_part = nullptr);
-// one Newton sweep: d_part[nactive][tpt][2] for the targets d_active at d_omega[target]
+// one Newton sweep: d_part[nactive][tpt][2] for the targets d_active at d_omega[target]; with
+// d_cnt, only the first d_cnt[0] <= nactive of them (read on the device)
 int cds_fused_sweep(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int nmo, int nocc, int nactive,
-                    const int *d_active, const double *eps, const double *d_omega, const void *R, double *d_part);
+                    const int *d_active, const double *eps, const double *d_omega, const void *R, double *d_part,
+                    const int *d_cnt = nullptr);

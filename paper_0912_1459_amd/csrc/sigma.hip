@@ -458,6 +458,79 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
     if (threadIdx.x == 0) out[idx] = v;
 }
 
+// Newton's iteration on the device (residue mode, fused path): the solve's state per target
+// (energy, its own orbital energy, pole strength, status, steps) and the list of targets still
+// iterating, so that several iterations go without a round trip to the host.
+struct NewtonDev {
+    double *om, *qe, *pole;
+    int *act, *status, *iters, *sel;
+    int *cnt;                               // [0] targets still iterating, [1] last step made
+};
+
+__global__ void newton_init_kernel(int nsel, const double *__restrict__ eps, int have_w0, NewtonDev d)
+{
+    for (int s = threadIdx.x; s < nsel; s += blockDim.x) {
+        const double q = eps[d.sel[s]];
+        d.qe[s] = q;
+        if (!have_w0) d.om[s] = q;
+        d.act[s] = s;
+        d.status[s] = -1;
+        d.iters[s] = 0;
+        d.pole[s] = __builtin_nan("");
+    }
+    if (threadIdx.x == 0) {
+        d.cnt[0] = nsel;
+        d.cnt[1] = 0;
+    }
+}
+
+// Sigma and Sigma' of the k-th target still iterating (out[2k], out[2k+1]), T = 1; rows past
+// the count return
+__global__ __launch_bounds__(256) void reduce_active_kernel(const double *__restrict__ part, int nblk,
+                                                            const int *__restrict__ cnt, double *__restrict__ out)
+{
+    if ((int)blockIdx.x >= 2 * cnt[0]) return;
+    const int idx = blockIdx.x, s = idx / 2, tc = idx - s * 2;
+    const double v = reduce_blocks(part, s, tc, nblk, 1);
+    if (threadIdx.x == 0) out[idx] = v;
+}
+
+// step `it` of Eq. (NR) for every target still iterating, in list order, with the operations of
+// the host loop: P = 1 / (1 - Sigma'), w' = w + (e_q + Sigma - w) P, converged at |w' - w| <= conv
+__global__ void newton_step_kernel(const double *__restrict__ out, double conv, int it, NewtonDev d)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    const int n = d.cnt[0];
+    if (n == 0) return;
+    d.cnt[1] = it;
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        const int s = d.act[k];
+        const double sg = out[2 * k], ds = out[2 * k + 1];
+        d.iters[s] = it;
+        if (!isfinite(sg) || !isfinite(ds)) {            // a denominator vanished
+            d.status[s] = CDS_QP_NONFINITE;
+            continue;
+        }
+        const double P = 1.0 / (1.0 - ds);
+        const double w = d.om[s];
+        const double wn = w + (d.qe[s] + sg - w) * P;
+        d.pole[s] = P;
+        d.om[s] = wn;
+        if (!isfinite(wn) || !isfinite(P)) {
+            d.status[s] = CDS_QP_NONFINITE;
+            continue;
+        }
+        if (fabs(wn - w) <= conv) {
+            d.status[s] = CDS_QP_CONVERGED;
+            continue;
+        }
+        d.act[m++] = s;
+    }
+    d.cnt[0] = m;
+}
+
 // sig[s][t] and dsig[s][t] (the two components written apart); same order as above
 __global__ __launch_bounds__(256) void reduce_split_kernel(const double *__restrict__ part, int nsc, int nblk, int T,
                                                            double *__restrict__ sig, double *__restrict__ dsig)
@@ -811,13 +884,24 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
 
     CdsTimer tall;
     CDS_CALL(cds_timer_start(ctx, &tall));
-    std::vector<double> heps(nmo);
-    CDS_HIP(ctx, hipMemcpyAsync(heps.data(), eps, (size_t)nmo * 8, hipMemcpyDeviceToHost, ctx->stream));
-    CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const void *Slo, *Vlo;
+    lo_planes(sh, Bsel, Bvo, &Slo, &Vlo);
+    CdsFusedPlan fp;
+    const bool fused = cds_fused_plan(prec, nvec, ldk, nmo, nocc, Bsel, Bvo, Slo, Vlo, &fp);
+    // residues from the fused contraction: the iteration runs on the device (no orbital energies
+    // on the host, no round trip per step)
+    const bool dev = mode == CDS_QP_RESIDUES && fused;
+    std::vector<double> heps;
+    if (!dev) {
+        heps.resize(nmo);
+        CDS_HIP(ctx, hipMemcpyAsync(heps.data(), eps, (size_t)nmo * 8, hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
 
     std::vector<double> w(nsel), pole(nsel, NAN);
     std::vector<int> active, status(nsel, -1), iters(nsel, 0);
-    for (int s = 0; s < nsel; ++s) w[s] = h_omega0 ? h_omega0[s] : heps[h_sel[s]];
+    if (!dev)
+        for (int s = 0; s < nsel; ++s) w[s] = h_omega0 ? h_omega0[s] : heps[h_sel[s]];
 
     // residue mode: one contraction per target chunk, residues kept on the device
     const int64_t npairA = (int64_t)nocc * (nocc + 1) / 2;
@@ -825,10 +909,7 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
     const size_t res_es = prec == CDS_PREC_FP64 ? 8 : 4;
     void *R = nullptr, *om = nullptr, *part = nullptr, *outd = nullptr, *act = nullptr;
     const int nblkA = sh.nvirt, nblkB = (sh.nvirt + 1) / 2;
-    const void *Slo, *Vlo;
-    lo_planes(sh, Bsel, Bvo, &Slo, &Vlo);
-    CdsFusedPlan fp;
-    const bool fused = cds_fused_plan(prec, nvec, ldk, nmo, nocc, Bsel, Bvo, Slo, Vlo, &fp);
+    NewtonDev nd = {};
     int64_t nblk_sweep = nblkA + nblkB;
     void *hp;
     CDS_CALL(cds_pinned(ctx, (size_t)nsel * (2 * 8 + 8 + 4) + 64, &hp));
@@ -843,10 +924,25 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
         nblk_sweep = fp.tpt;
         CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * 8, &om));
         CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsel * nblk_sweep * 2 * 8, &part));
-        CDS_CALL(cds_ws(ctx, WS_SG_OUT, (size_t)nsel * 2 * 8 + (size_t)nsel * 4 + 64, &outd));
+        // sums, the active list, then the solve's state: e_q, P (double); status, steps, the
+        // targets' orbitals (int); the two counters
+        const size_t off_state = (((size_t)nsel * 2 * 8 + 32 + (size_t)nsel * 4) + 255) / 256 * 256;
+        CDS_CALL(cds_ws(ctx, WS_SG_OUT, off_state + (size_t)nsel * (8 + 8 + 4 + 4 + 4) + 64, &outd));
         act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
-        for (int s = 0; s < nsel; ++s) h_w[s] = w[s];
-        CDS_HIP(ctx, hipMemcpyAsync(om, h_w, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
+        unsigned char *stb = (unsigned char *)outd + off_state;
+        nd.om = (double *)om;
+        nd.qe = (double *)stb;
+        nd.pole = nd.qe + nsel;
+        nd.status = (int *)(nd.pole + nsel);
+        nd.iters = nd.status + nsel;
+        nd.sel = nd.iters + nsel;
+        nd.cnt = nd.sel + nsel;
+        nd.act = (int *)act;
+        CDS_HIP(ctx, hipMemcpyAsync(nd.sel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
+        if (h_omega0)
+            CDS_HIP(ctx, hipMemcpyAsync(om, h_omega0, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
+        hipLaunchKernelGGL(newton_init_kernel, dim3(1), dim3(256), 0, ctx->stream, nsel, eps, h_omega0 ? 1 : 0, nd);
+        CDS_LAUNCHED(ctx);
         const int csz = fused_chunk(ctx, sh);
         int *tsel;
         CDS_CALL(target_slots(ctx, nsel, &tsel));
@@ -893,6 +989,39 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
         act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
     }
 
+    if (dev) {
+        // chunks of NEWTON_CHUNK steps between reads of the count of targets still iterating;
+        // a step with none left launches kernels that return at once
+        constexpr int NEWTON_CHUNK = 3;
+        int *h_cnt = (int *)h_out;
+        for (int it = 1; it <= max_iter;) {
+            const int last = std::min(max_iter, it + NEWTON_CHUNK - 1);
+            for (; it <= last; ++it) {
+                if (!(first_done && it == 1))
+                    CDS_CALL(cds_fused_sweep(ctx, prec, fp, nmo, nocc, nsel, (const int *)act, eps,
+                                             (const double *)om, R, (double *)part, nd.cnt));
+                hipLaunchKernelGGL(reduce_active_kernel, dim3((unsigned)(2 * nsel)), dim3(256), 0, ctx->stream,
+                                   (const double *)part, (int)nblk_sweep, (const int *)nd.cnt, (double *)outd);
+                hipLaunchKernelGGL(newton_step_kernel, dim3(1), dim3(64), 0, ctx->stream, (const double *)outd, conv,
+                                   it, nd);
+                CDS_LAUNCHED(ctx);
+            }
+            CDS_HIP(ctx, hipMemcpyAsync(h_cnt, nd.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (h_cnt[0] == 0) break;
+        }
+        ctx->stats.n_newton_iter += h_cnt[1];
+        CDS_HIP(ctx, hipMemcpyAsync(h_omega, om, (size_t)nsel * 8, hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipMemcpyAsync(h_pole, nd.pole, (size_t)nsel * 8, hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipMemcpyAsync(h_iters, nd.iters, (size_t)nsel * 4, hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipMemcpyAsync(h_status, nd.status, (size_t)nsel * 4, hipMemcpyDeviceToHost, ctx->stream));
+        CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int s = 0; s < nsel; ++s)
+            if (h_status[s] < 0) h_status[s] = CDS_QP_MAX_ITER;
+        CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_newton_ms));
+        CDS_CALL(cds_timers_flush(ctx));
+        return CDS_OK;
+    }
     for (int s = 0; s < nsel; ++s) active.push_back(s);
     std::vector<double> out_all((size_t)nsel * 2);
     for (int it = 1; it <= max_iter && !active.empty(); ++it) {

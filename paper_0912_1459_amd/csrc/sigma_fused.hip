@@ -559,10 +559,12 @@ __global__ __launch_bounds__(FNT, 1) void sigma_fused_kernel(FArgs a)
 // Newton sweep over the stored residues of one task and one active target at its current
 // energy: Sigma = sum R / d, Sigma' = -sum R / d^2 over the task's elements (fixed order).
 template <typename RT>
-__global__ __launch_bounds__(256) void fused_sweep_kernel(FArgs a, const int *__restrict__ active)
+__global__ __launch_bounds__(256) void fused_sweep_kernel(FArgs a, const int *__restrict__ active,
+                                                          const int *__restrict__ cnt)
 {
     __shared__ double sh[2][4];
     __shared__ double seps[2][FT];
+    if (cnt && (int)blockIdx.y >= cnt[0]) return;       // past the targets still iterating
     const int s = active[blockIdx.y];
     const Task k = task_in_target(a, blockIdx.x);
     const bool diag = k.TR == k.TC;
@@ -727,7 +729,8 @@ int cds_fused_residues(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int64_t ld
 }
 
 int cds_fused_sweep(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int nmo, int nocc, int nactive,
-                    const int *d_active, const double *eps, const double *d_omega, const void *R, double *d_part)
+                    const int *d_active, const double *eps, const double *d_omega, const void *R, double *d_part,
+                    const int *d_cnt)
 {
     FArgs a = fused_args(prec, p, 0, nmo, nocc, 1, nullptr, nullptr, nullptr, nullptr, nullptr, eps);
     a.omega = d_omega;
@@ -737,9 +740,9 @@ int cds_fused_sweep(cds_ctx *ctx, int prec, const CdsFusedPlan &p, int nmo, int 
         return cds_fail(ctx, CDS_EINVAL, "fused sweep grid %lld x %d", (long long)p.tpt, nactive);
     const dim3 grid((unsigned)p.tpt, (unsigned)nactive);
     if (prec == CDS_PREC_FP64)
-        hipLaunchKernelGGL(fused_sweep_kernel<double>, grid, dim3(256), 0, ctx->stream, a, d_active);
+        hipLaunchKernelGGL(fused_sweep_kernel<double>, grid, dim3(256), 0, ctx->stream, a, d_active, d_cnt);
     else
-        hipLaunchKernelGGL(fused_sweep_kernel<float>, grid, dim3(256), 0, ctx->stream, a, d_active);
+        hipLaunchKernelGGL(fused_sweep_kernel<float>, grid, dim3(256), 0, ctx->stream, a, d_active, d_cnt);
     CDS_LAUNCHED(ctx);
     return CDS_OK;
 }
