@@ -537,6 +537,29 @@ __device__ Pick cd_pick(const CdBufs &b, int r, int sr, const CdParams &cp, int6
 }
 
 // pivot mask of a restricted decomposition: 0 = may become a pivot, 2 = never (row updated)
+// The decomposition's starting buffers in one launch: the pivot mask cleared (unless a kernel of
+// its own set it), no row a candidate, the three super-tile buffers empty, the state, and on a
+// fresh start the residual diagonal D = the ERI diagonal.
+__global__ __launch_bounds__(256) void cd_setup_kernel(int64_t npairs, unsigned char *__restrict__ mask0,
+                                                       int clear_mask, signed char *__restrict__ slot,
+                                                       unsigned long long *__restrict__ smax,
+                                                       unsigned long long *__restrict__ smin, double *__restrict__ D,
+                                                       const double *__restrict__ diag, int copy_d, CdState st0,
+                                                       CdState *__restrict__ st)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < npairs) {
+        if (clear_mask) mask0[t] = 0;
+        slot[t] = -1;
+        if (copy_d) D[t] = diag[t];
+    }
+    if (t < 3 * CD_NSUP) {
+        smax[t] = 0ull;
+        smin[t] = ~0ull;
+    }
+    if (t == 0) *st = st0;
+}
+
 __global__ void init_mask_kernel(int64_t npairs, const unsigned char *__restrict__ allowed,
                                  unsigned char *__restrict__ mask)
 {
@@ -2470,24 +2493,24 @@ int cholesky_impl(cds_ctx *ctx, bool dense, int32_t nbf, const double *centres,
     if (allowed) {
         hipLaunchKernelGGL(init_mask_kernel, dim3(nb), dim3(256), 0, ctx->stream, npairs, allowed, bf.mask[0]);
         CDS_LAUNCHED(ctx);
-    } else {
-        CDS_HIP(ctx, hipMemsetAsync(bf.mask[0], 0, (size_t)npairs, ctx->stream));
     }
-    CDS_HIP(ctx, hipMemsetAsync(bf.slot, 0xff, (size_t)npairs, ctx->stream));   // no row is a candidate
-    // super-tile buffers 0 and 1 start empty (2 is reset by the first step)
-    CDS_HIP(ctx, hipMemsetAsync(bf.smax[0], 0, (size_t)3 * CD_NSUP * 8, ctx->stream));
-    CDS_HIP(ctx, hipMemsetAsync(bf.smin[0], 0xff, (size_t)3 * CD_NSUP * 8, ctx->stream));
     CdState st0 = {};
     st0.k = nvec_in;
     st0.kdone = INT64_MAX;
     // block counts of successive calls start 2^16 apart, so no word a call left can be taken
     // for one of the next call's commits
     st0.nblk = (int64_t)(ctx->mail_base += (1 << 16));
-    *(CdState *)hp = st0;
-    CDS_HIP(ctx, hipMemcpyAsync(st, hp, sizeof(CdState), hipMemcpyHostToDevice, ctx->stream));
-    if (nvec_in == 0) {
-        CDS_HIP(ctx, hipMemcpyAsync(D, diag, (size_t)npairs * 8, hipMemcpyDeviceToDevice, ctx->stream));
-    } else {
+    // the mask (unless set above), no row a candidate, the super-tile buffers empty (0 and 1 are
+    // read first; 2 is reset by the first step anyway), the state, D on a fresh start
+    static_assert(sizeof(CdState) <= 2048, "the state goes as a kernel argument");
+    {
+        const int64_t nsb = std::max<int64_t>(nb, cds_ceil_div(3 * CD_NSUP, 256));
+        hipLaunchKernelGGL(cd_setup_kernel, dim3((unsigned)nsb), dim3(256), 0, ctx->stream, npairs, bf.mask[0],
+                           allowed ? 0 : 1, (signed char *)bf.slot, bf.smax[0], bf.smin[0], D, (const double *)diag,
+                           nvec_in == 0 ? 1 : 0, st0, st);
+        CDS_LAUNCHED(ctx);
+    }
+    if (nvec_in != 0) {
         hipLaunchKernelGGL(mark_pivots_kernel, dim3((unsigned)cds_ceil_div(nvec_in, 256)), dim3(256),
                            0, ctx->stream, nvec_in, piv, npairs, bf.mask[0]);
         CDS_LAUNCHED(ctx);

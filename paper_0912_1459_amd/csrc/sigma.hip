@@ -922,22 +922,23 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
         // contraction also sums them at the starting energies (the first Newton evaluation)
         CDS_CALL(cds_ws(ctx, WS_SG_RES, (size_t)nsel * fp.nres * res_es, &R));
         nblk_sweep = fp.tpt;
-        CDS_CALL(cds_ws(ctx, WS_SG_OMEGA, (size_t)nsel * 8, &om));
         CDS_CALL(cds_ws(ctx, WS_SG_PART, (size_t)nsel * nblk_sweep * 2 * 8, &part));
-        // sums, the active list, then the solve's state: e_q, P (double); status, steps, the
-        // targets' orbitals (int); the two counters
+        // sums, the active list, then the solve's state: w and P (double), status and steps
+        // (int), read back in one copy; then e_q (double), the targets' orbitals (int), the two
+        // counters
         const size_t off_state = (((size_t)nsel * 2 * 8 + 32 + (size_t)nsel * 4) + 255) / 256 * 256;
-        CDS_CALL(cds_ws(ctx, WS_SG_OUT, off_state + (size_t)nsel * (8 + 8 + 4 + 4 + 4) + 64, &outd));
+        CDS_CALL(cds_ws(ctx, WS_SG_OUT, off_state + (size_t)nsel * (8 + 8 + 4 + 4 + 8 + 4) + 64, &outd));
         act = (unsigned char *)outd + (size_t)nsel * 2 * 8 + 32;
         unsigned char *stb = (unsigned char *)outd + off_state;
-        nd.om = (double *)om;
-        nd.qe = (double *)stb;
-        nd.pole = nd.qe + nsel;
+        nd.om = (double *)stb;
+        nd.pole = nd.om + nsel;
         nd.status = (int *)(nd.pole + nsel);
         nd.iters = nd.status + nsel;
-        nd.sel = nd.iters + nsel;
+        nd.qe = (double *)(nd.iters + nsel);
+        nd.sel = (int *)(nd.qe + nsel);
         nd.cnt = nd.sel + nsel;
         nd.act = (int *)act;
+        om = nd.om;
         CDS_HIP(ctx, hipMemcpyAsync(nd.sel, h_sel, (size_t)nsel * 4, hipMemcpyHostToDevice, ctx->stream));
         if (h_omega0)
             CDS_HIP(ctx, hipMemcpyAsync(om, h_omega0, (size_t)nsel * 8, hipMemcpyHostToDevice, ctx->stream));
@@ -1011,13 +1012,17 @@ extern "C" int cds_qp_solve(cds_ctx *ctx, int32_t prec, int64_t nvec, int64_t ld
             if (h_cnt[0] == 0) break;
         }
         ctx->stats.n_newton_iter += h_cnt[1];
-        CDS_HIP(ctx, hipMemcpyAsync(h_omega, om, (size_t)nsel * 8, hipMemcpyDeviceToHost, ctx->stream));
-        CDS_HIP(ctx, hipMemcpyAsync(h_pole, nd.pole, (size_t)nsel * 8, hipMemcpyDeviceToHost, ctx->stream));
-        CDS_HIP(ctx, hipMemcpyAsync(h_iters, nd.iters, (size_t)nsel * 4, hipMemcpyDeviceToHost, ctx->stream));
-        CDS_HIP(ctx, hipMemcpyAsync(h_status, nd.status, (size_t)nsel * 4, hipMemcpyDeviceToHost, ctx->stream));
+        // w, P, status and steps in one copy (24 bytes per target; the pinned buffer holds 28)
+        CDS_HIP(ctx, hipMemcpyAsync(hp, nd.om, (size_t)nsel * 24, hipMemcpyDeviceToHost, ctx->stream));
         CDS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        for (int s = 0; s < nsel; ++s)
-            if (h_status[s] < 0) h_status[s] = CDS_QP_MAX_ITER;
+        const double *hw = (const double *)hp, *hpo = hw + nsel;
+        const int *hs = (const int *)(hpo + nsel), *hi = hs + nsel;
+        for (int s = 0; s < nsel; ++s) {
+            h_omega[s] = hw[s];
+            h_pole[s] = hpo[s];
+            h_status[s] = hs[s] < 0 ? CDS_QP_MAX_ITER : hs[s];
+            h_iters[s] = hi[s];
+        }
         CDS_CALL(cds_timer_stop(ctx, &tall, &ctx->stats.t_newton_ms));
         CDS_CALL(cds_timers_flush(ctx));
         return CDS_OK;
